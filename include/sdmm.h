@@ -1,0 +1,210 @@
+/*
+ * sdmm.h - C ABI of the stochastic multiscale flux basis library for
+ * coupled Stokes-Darcy flow (MI355X / gfx950).
+ *
+ * The library computes, for a domain split into Stokes and Darcy
+ * subdomains with a KL-parameterised log-permeability:
+ *   - the stochastic multiscale flux basis: one local solve per mortar
+ *     degree of freedom of every subdomain, for every local KL realization
+ *     of each Darcy subdomain (Section 5.4, Method S3, pre-computation
+ *     loop; the basis functions phi = S_{H,i} xi^j of Section 5.3);
+ *   - the interface problem S_H lambda = g_H (Section 5.1, eq.
+ *     operatorform) for a batch of global collocation points, by CG in
+ *     which S_H is applied as linear combinations of that basis
+ *     (Section 5.4, main loop, Steps 3-5);
+ *   - the weighted moments of Section 2 (mean and Var = E[u^2] - E[u]^2)
+ *     with the collocation weights of Section 4 (Step 6).
+ *
+ * Conventions
+ *   - Every function returns an int status (SDMM_OK or a negative code);
+ *     sdmm_last_error() describes the last failure on that context.
+ *     No exception or abort crosses the ABI.
+ *   - The caller owns every array it passes; the library copies what it
+ *     keeps.  The library owns all device state it allocates (basis cache,
+ *     factors, CG workspace, moment accumulators).
+ *   - Arguments documented as "device" are device pointers on the
+ *     context's GPU (for instance from a torch tensor); "host" arguments
+ *     are ordinary host memory.
+ *   - Calls taking a stream enqueue their work on it (a hipStream_t passed
+ *     as void*; NULL means the null stream) and may return before the work
+ *     completes.  Results are valid once the stream is synchronised.  The
+ *     get_* calls synchronise the context's stream themselves.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef SDMM_H
+#define SDMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDMM_OK 0
+#define SDMM_EINVAL (-1)     /* invalid argument or problem description       */
+#define SDMM_ENOMEM (-2)     /* device memory could not be allocated          */
+#define SDMM_EDEVICE (-3)    /* a HIP runtime call failed                      */
+#define SDMM_ENOTCONV (-4)   /* some realization did not converge (status set) */
+#define SDMM_EBREAKDOWN (-5) /* CG breakdown (p^T S p <= 0 or NaN)             */
+#define SDMM_ESTATE (-6)     /* call made in the wrong order                   */
+
+#define SDMM_PREC_FP64 0     /* factor and solves in FP64                      */
+#define SDMM_PREC_MIXED 1    /* FP32 factor and solves + FP64 refinement       */
+
+/* status values written per realization by sdmm_solve_interface */
+#define SDMM_CG_CONVERGED 0
+#define SDMM_CG_MAXITER 1
+#define SDMM_CG_BREAKDOWN 2
+
+/* fields of sdmm_get_moments */
+#define SDMM_FIELD_LAMBDA 0   /* mortar coefficients, M values                 */
+#define SDMM_FIELD_DARCY_P 1  /* Darcy cell pressures                          */
+#define SDMM_FIELD_DARCY_U 2  /* Darcy RT0 normal velocities (+x / +y)         */
+#define SDMM_FIELD_STOKES_U 3 /* Stokes Q2 nodal velocities (x, y per node)    */
+#define SDMM_FIELD_STOKES_P 4 /* Stokes Q1 nodal pressures                     */
+
+/* index maps of sdmm_get_index_map */
+#define SDMM_MAP_INTERFACES 0 /* n_iface x 5: i, j, kind (0 ss 1 sd 2 dd), ndof, offset */
+#define SDMM_MAP_SUB_PTR 1    /* n_sub + 1: CSR pointer into the DOF list       */
+#define SDMM_MAP_SUB_DOFS 2   /* global mortar DOF of each local mortar DOF     */
+#define SDMM_MAP_SUB_SIGN 3   /* +1 / -1 of each local mortar DOF               */
+#define SDMM_MAP_G2L 4        /* n_real x n_region local realization indices     */
+#define SDMM_MAP_NLOCAL 5     /* n_region local realization counts              */
+#define SDMM_MAP_NODE_IDS 6   /* n_real x n_term collocation node ids          */
+
+typedef struct sdmm_ctx sdmm_ctx;
+
+/*
+ * Problem description (Section 3.1: N_s Stokes subdomains numbered first,
+ * then N_d Darcy subdomains; Section 3.3: mortar spaces; Section 2.1 and
+ * eq. covariance: KL regions; Section 4: collocation rule).  All arrays are
+ * host memory and are copied by sdmm_set_problem.
+ *
+ * Outer boundary: the velocity (inflow_x, inflow_y) is imposed on the whole
+ * Stokes outer boundary; the Darcy outer boundary has p = p_bottom on
+ * y = domain[2] and no flow elsewhere.  Body forces and sources are zero.
+ * The GPU path requires p_bottom == 0 (the Darcy complementary solution is
+ * then zero).
+ */
+typedef struct {
+    double nu_s, nu_d;       /* viscosities                                   */
+    double alpha;            /* BJS friction coefficient (eq. BJS)            */
+    double k_bjs;            /* permeability in the BJS term (deterministic)  */
+    double inflow_x, inflow_y;
+    double p_bottom;
+    double domain[4];        /* x0 x1 y0 y1                                   */
+    int32_t n_sub;
+    const int32_t* sub_type;   /* n_sub: 0 Stokes, 1 Darcy                     */
+    const double* sub_rect;    /* 4 n_sub: x0 x1 y0 y1                          */
+    const int32_t* sub_n;      /* 2 n_sub: elements nx ny                       */
+    const int32_t* sub_region; /* n_sub: KL region of a Darcy subdomain, else -1*/
+    int32_t mortar_degree;     /* 1 or 2: discontinuous Lagrange                */
+    int32_t mortar_elements;   /* elements per interface                       */
+    int32_t n_region;
+    const double* region_rect;      /* 4 n_region                              */
+    const int32_t* region_nterm;    /* n_region: KL terms kept                 */
+    const double* region_sigma2;    /* n_region: covariance amplitude          */
+    const double* region_eta;       /* 2 n_region: correlation lengths         */
+    const double* region_mean_logk; /* n_region: E[Y]                          */
+    int32_t rule_kind;   /* 0 tensor Gauss-Hermite, 1 Smolyak sparse grid      */
+    int32_t rule_m;      /* tensor: points per dimension                       */
+    int32_t rule_level;  /* sparse: l_max                                      */
+    int32_t rule_growth; /* sparse: 0 -> 2^(p+1)-1 points at level p, 1 -> p+1 */
+} sdmm_problem;
+
+typedef struct {
+    int64_t n_sub, n_stokes, n_darcy, n_iface, M;
+    int64_t n_real, n_term, n_region;
+    int64_t n_units;        /* Darcy (subdomain, local realization) pairs      */
+    int64_t n_floating;     /* floating Stokes subdomains (FETI)               */
+    int64_t n_kernel;       /* columns of the FETI matrix G                    */
+    int64_t field_size[5];  /* sizes of the five moment fields                 */
+    int64_t basis_bytes;    /* device bytes of the S_{H,i}^{(k)} cache        */
+    int64_t response_bytes; /* device bytes of the stored fine responses        */
+    int64_t max_R;          /* largest number of mortar DOFs on one subdomain  */
+    int64_t darcy_flops;    /* banded factor + solve flops of one full build   */
+} sdmm_sizes;
+
+typedef struct {
+    int64_t basis_solves_darcy;   /* sum over Darcy subdomains of R_i L_j       */
+    int64_t basis_solves_stokes;  /* sum over Stokes subdomains of R_i          */
+    int64_t complementary_solves; /* solves for g_H (once, deterministic)       */
+    int64_t units_built;          /* Darcy (i, k) bases built                   */
+    int64_t refinement_steps;     /* FP64 refinement sweeps (mixed precision)   */
+    int64_t cg_iterations;        /* summed over realizations                   */
+    int64_t realizations;         /* taken through CG                           */
+    double ms_basis_darcy;        /* last build: Darcy units                    */
+    double ms_basis_stokes;       /* last build: Stokes subdomains              */
+    double ms_solve;              /* last solve_interface                       */
+    double max_refine_residual;   /* largest relative residual after refinement */
+} sdmm_counters;
+
+/* Create a context on HIP device `device`.  Ownership of *out passes to the
+ * caller, who releases it with sdmm_destroy.  EINVAL for a bad device.
+ * device = -1 creates a context without a GPU: sdmm_set_problem, the sizes,
+ * index maps, collocation and KL queries work; every call that computes on
+ * the device returns ESTATE. */
+int sdmm_create(int device, sdmm_ctx** out);
+int sdmm_destroy(sdmm_ctx* ctx);
+/* Message of the last failure on ctx; owned by ctx, valid until the next call. */
+const char* sdmm_last_error(const sdmm_ctx* ctx);
+
+/* Build meshes, interfaces and mortar maps (Section 3.1, 3.3), the KL
+ * modes of every region (Section 2.1, eq. Fred with the separable kernel
+ * of eq. covariance), the collocation points, weights and global->local
+ * index table (Section 4; Step 4 of Method S3), and upload the Darcy KL
+ * tables and Stokes operators.  Replaces any previous problem.  EINVAL
+ * when subdomains do not tile, a region is not a union of Darcy
+ * subdomains, a mortar has more DOFs per interface than the fine trace, or
+ * p_bottom != 0. */
+int sdmm_set_problem(sdmm_ctx* ctx, const sdmm_problem* p);
+int sdmm_get_sizes(sdmm_ctx* ctx, sdmm_sizes* out);
+/* Copy an integer index map (SDMM_MAP_*) to host `out` (capacity cap
+ * entries); *n_out receives its length.  EINVAL if cap is too small. */
+int sdmm_get_index_map(sdmm_ctx* ctx, int kind, int64_t* out, int64_t cap, int64_t* n_out);
+/* Collocation points (n_real x n_term, row-major) and weights (n_real) to
+ * host memory; either pointer may be NULL. */
+int sdmm_get_collocation(sdmm_ctx* ctx, double* points, double* weights);
+/* KL eigenvalues sigma^2 lambda_a lambda_b of the kept modes of one region
+ * and their 1-D mode indices (a, b) (host arrays of nterm and 2 nterm). */
+int sdmm_get_kl(sdmm_ctx* ctx, int region, double* lam, int32_t* modes);
+
+/* Method S3 pre-computation loop (Section 5.4): for every Darcy subdomain
+ * and every local realization k of its region, build K (eq. KLapprox),
+ * the RT0-Q0 operator and its banded factor, solve for every mortar basis
+ * function (eqs. starDproblem1-2) and store S_{H,i}^{(k)}; for every Stokes
+ * subdomain do the same once (eqs. starSproblem1-2) together with the
+ * complementary solution (eqs. barSproblem1-2) that gives g_H.
+ * precision: SDMM_PREC_FP64 or SDMM_PREC_MIXED. */
+int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream);
+/* Copy S_{H,i}^{(k)} (R_i x R_i, column-major with leading dimension ld,
+ * host) of subdomain `sub` and local realization k (k = 0 for Stokes).
+ * The signs of Stokes-Stokes mortar DOFs are included. */
+int sdmm_get_basis(sdmm_ctx* ctx, int sub, int k, double* S, int64_t ld);
+
+/* Solve S_H lambda = g_H (Section 5.1) for n global collocation points
+ * with indices gidx (device int64, n), by CG with S_H applied from the
+ * basis cache (Section 5.3, linear combinations of phi) and, with floating
+ * Stokes subdomains, the FETI projection.  lambda_0 = 0; a realization
+ * stops when ||r_k|| <= rtol ||r_0||.  Outputs (device): lambda (n x M,
+ * row-major), iters (int32 n), relres (double n), status (int32 n,
+ * SDMM_CG_*); iters/relres/status may be NULL.  Returns ENOTCONV when some
+ * realization hit max_iter (outputs still filled). */
+int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol,
+                         int32_t max_iter, double* lambda, int32_t* iters, double* relres,
+                         int32_t* status, void* stream);
+/* Add n realizations to the moment accumulators (Section 2, Step 6 of
+ * Method S3): gidx (device int64 n), lambda (device n x M from
+ * sdmm_solve_interface), weights (device double n, or NULL for the
+ * collocation weights of the points). */
+int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const double* lambda,
+                            const double* weights, void* stream);
+/* Mean and variance (host arrays of field_size[field]) of one field. */
+int sdmm_get_moments(sdmm_ctx* ctx, int field, double* mean, double* var);
+int sdmm_reset_moments(sdmm_ctx* ctx);
+int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDMM_H */

@@ -1,0 +1,977 @@
+// C ABI of the flux basis library: host orchestration of the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sdmm.h"
+#include "kernels.hpp"
+#include "problem.hpp"
+
+using namespace sdmm;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+}  // namespace
+
+struct sdmm_ctx {
+    int device = 0;
+    bool host_only = false;  // device -1: problem setup and maps only
+    std::string err;
+    bool have_problem = false;
+    bool basis_built = false;
+    bool stokes_built = false;
+    int built_precision = -1;
+    Problem P;
+    // sizes
+    int max_b = 0, max_R = 0, max_Rd = 0, max_ext = 0;
+    int64_t n_units = 0;
+    std::vector<UnitDev> units;
+    std::vector<int64_t> sub_Sbase, sub_Abase;
+    std::vector<int> sub_R, sub_region, sub_ker, sub_Gcol, sub_nlocal;
+    std::vector<StokesDev> sdev;
+    int max_nblk = 0, max_w = 0, max_ncol = 0, max_nout_d = 0, max_nout_s = 0, max_units_per_d = 0;
+    int64_t n_trip = 0;
+    int64_t S_total = 0, X_total = 0, L_total = 0, T_total = 0, A_total = 0;
+    int64_t field_size[5] = {0, 0, 0, 0, 0};
+    std::vector<int64_t> cell_out_off, edge_out_off, u_out_off, p_out_off;
+    std::vector<int> pair_sub, pair_k;
+    // device buffers
+    DevBuf d_dar, d_units, d_be_cell, d_be_kind, d_be_len, d_be_hperp, d_be_medge, d_be_sgn, d_cell_be, d_Pi, d_phi,
+        d_xi, d_supp_ptr, d_supp_e, d_supp_v, d_me_cell;
+    DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_refine;
+    DevBuf d_sdev, d_tiles, d_rhs, d_U, d_P, d_bmap, d_Z, d_q_ptr, d_q_col, d_q_val, d_uD, d_uD_off, d_tr_sub, d_tr_r,
+        d_tr_c, d_tr_v;
+    DevBuf d_g, d_G, d_GtGinv;
+    DevBuf d_sub_R, d_sub_dof_ptr, d_sub_dofs, d_sub_region, d_sub_Sbase, d_g2l, d_weights;
+    DevBuf d_sub_ker, d_sub_Gcol, d_sub_Abase, d_sub_nlocal, d_pair_sub, d_pair_k, d_acc, d_lam1, d_lam2, d_wsum;
+    DevBuf d_unit_of_dk, d_dnlocal, d_dAbase, d_cell_out, d_edge_out, d_sAbase, d_u_out, d_p_out;
+    DevBuf d_mom;  // p1 p2 u1 u2 for moments output
+    // CG workspace
+    DevBuf w_r, w_p, w_Ap, w_rr, w_r0, w_iters, w_relres, w_status, w_active, w_any, w_alpha, w_Slam;
+    int64_t w_cap = 0;
+    sdmm_counters counters{};
+    hipEvent_t ev[6] = {};
+};
+
+namespace {
+
+int fail(sdmm_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, SDMM_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+int alloc(sdmm_ctx* ctx, DevBuf& b, size_t bytes) {
+    b.release();
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(ctx, SDMM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    b.bytes = bytes;
+    return SDMM_OK;
+}
+
+template <class T>
+int upload(sdmm_ctx* ctx, DevBuf& b, const std::vector<T>& v) {
+    int rc = alloc(ctx, b, v.size() * sizeof(T));
+    if (rc) return rc;
+    if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return SDMM_OK;
+}
+
+DarcyTables darcy_tables(sdmm_ctx* c) {
+    DarcyTables t;
+    t.dar = c->d_dar.as<DarcyDev>();
+    t.units = c->d_units.as<UnitDev>();
+    t.be_cell = c->d_be_cell.as<int>();
+    t.be_kind = c->d_be_kind.as<int>();
+    t.be_len = c->d_be_len.as<double>();
+    t.be_hperp = c->d_be_hperp.as<double>();
+    t.be_medge = c->d_be_medge.as<int>();
+    t.be_sgn = c->d_be_sgn.as<int>();
+    t.cell_be = c->d_cell_be.as<int>();
+    t.Pi = c->d_Pi.as<double>();
+    t.phi = c->d_phi.as<double>();
+    t.xi = c->d_xi.as<double>();
+    t.supp_ptr = c->d_supp_ptr.as<int>();
+    t.supp_e = c->d_supp_e.as<int>();
+    t.supp_v = c->d_supp_v.as<double>();
+    t.me_cell = c->d_me_cell.as<int>();
+    return t;
+}
+
+int setup_device(sdmm_ctx* ctx) {
+    Problem& P = ctx->P;
+    const int nsub = (int)P.subs.size();
+    // ---- Darcy tables and units
+    std::vector<DarcyDev> dar;
+    std::vector<int> be_cell, be_kind, be_medge, be_sgn, cell_be, supp_ptr, supp_e, me_cell;
+    std::vector<double> be_len, be_hperp, Pi, phi, supp_v;
+    std::vector<double> xi;
+    std::vector<int64_t> region_xi_off(P.n_region);
+    for (int r = 0; r < P.n_region; ++r) {
+        region_xi_off[r] = (int64_t)xi.size();
+        for (int k = 0; k < P.nlocal[r]; ++k)
+            for (int s = 0; s < P.region_nterm[r]; ++s)
+                xi.push_back(P.node_x[P.local_ids[r][(size_t)k * P.region_nterm[r] + s]]);
+    }
+    if (xi.empty()) xi.push_back(0.0);
+    ctx->units.clear();
+    ctx->sub_Sbase.assign(nsub, 0);
+    ctx->sub_R.assign(nsub, 0);
+    ctx->sub_region.assign(nsub, -1);
+    ctx->sub_ker.assign(nsub, 0);
+    ctx->sub_Gcol.assign(nsub, 0);
+    ctx->sub_nlocal.assign(nsub, 1);
+    ctx->sub_Abase.assign(nsub, 0);
+    int64_t S_off = 0, X_off = 0, L_off = 0, T_off = 0, A_off = 0;
+    ctx->max_b = 0;
+    ctx->max_R = 0;
+    ctx->max_Rd = 0;
+    ctx->max_nout_d = 0;
+    ctx->max_units_per_d = 0;
+    ctx->cell_out_off.clear();
+    ctx->edge_out_off.clear();
+    int64_t cell_tot = 0, edge_tot = 0;
+    std::vector<int> unit_of_dk, dnlocal;
+    std::vector<int64_t> dAbase;
+    for (size_t di = 0; di < P.darcy.size(); ++di)
+        ctx->max_units_per_d = std::max(ctx->max_units_per_d, P.nlocal[P.subs[P.darcy[di].sub].region]);
+    for (size_t di = 0; di < P.darcy.size(); ++di) {
+        const DarcyHost& h = P.darcy[di];
+        DarcyDev d{};
+        d.nx = h.nx;
+        d.ny = h.ny;
+        d.N = h.N;
+        d.swap = h.swap;
+        d.b = h.b;
+        d.R = h.R;
+        d.nterm = h.nterm;
+        d.n_medge = h.n_medge;
+        d.hx = h.hx;
+        d.hy = h.hy;
+        d.nu = P.in.nu_d;
+        d.mean_logk = h.mean_logk;
+        d.off_be = (int64_t)be_cell.size();
+        d.off_cellbe = (int64_t)cell_be.size();
+        d.off_Pi = (int64_t)Pi.size();
+        d.off_phi = (int64_t)phi.size();
+        d.off_dofs = P.sub_ptr[h.sub];
+        d.off_supp = (int64_t)supp_ptr.size();
+        d.off_me = (int64_t)me_cell.size();
+        be_cell.insert(be_cell.end(), h.be_cell.begin(), h.be_cell.end());
+        be_kind.insert(be_kind.end(), h.be_kind.begin(), h.be_kind.end());
+        be_medge.insert(be_medge.end(), h.be_medge.begin(), h.be_medge.end());
+        be_sgn.insert(be_sgn.end(), h.be_sgn.begin(), h.be_sgn.end());
+        be_len.insert(be_len.end(), h.be_len.begin(), h.be_len.end());
+        be_hperp.insert(be_hperp.end(), h.be_hperp.begin(), h.be_hperp.end());
+        Pi.insert(Pi.end(), h.Pi.begin(), h.Pi.end());
+        phi.insert(phi.end(), h.phi.begin(), h.phi.end());
+        std::vector<int> cb((size_t)2 * h.N, -1);
+        me_cell.resize(me_cell.size() + h.n_medge);
+        for (size_t e = 0; e < h.be_cell.size(); ++e) {
+            int c = h.be_cell[e];
+            if (cb[2 * c] < 0) cb[2 * c] = (int)e;
+            else cb[2 * c + 1] = (int)e;
+            if (h.be_medge[e] >= 0) {
+                int ci = h.swap ? (c % h.nx) * h.ny + c / h.nx : c;
+                me_cell[d.off_me + h.be_medge[e]] = ci;
+            }
+        }
+        cell_be.insert(cell_be.end(), cb.begin(), cb.end());
+        // support lists: for every mortar DOF, the mortar edges where its average is non-zero
+        int base = (int)supp_e.size();
+        std::vector<std::vector<std::pair<int, double>>> sl(h.R);
+        for (int e = 0; e < h.n_medge; ++e)
+            for (int m = 0; m < h.R; ++m) {
+                double v = h.Pi[(size_t)e * h.R + m];
+                if (v != 0.0) sl[m].push_back({e, v});
+            }
+        for (int m = 0; m < h.R; ++m) {
+            supp_ptr.push_back(base);
+            for (auto& pr : sl[m]) {
+                supp_e.push_back(pr.first);
+                supp_v.push_back(pr.second);
+                ++base;
+            }
+        }
+        supp_ptr.push_back(base);
+        dar.push_back(d);
+        const int i = h.sub;
+        const int r = P.subs[i].region;
+        ctx->sub_R[i] = h.R;
+        ctx->sub_region[i] = r;
+        ctx->sub_nlocal[i] = P.nlocal[r];
+        ctx->sub_Sbase[i] = S_off;
+        ctx->sub_Abase[i] = A_off;
+        dAbase.push_back(A_off);
+        dnlocal.push_back(P.nlocal[r]);
+        for (int k = 0; k < ctx->max_units_per_d; ++k) unit_of_dk.push_back(k < P.nlocal[r] ? (int)ctx->units.size() + k : -1);
+        for (int k = 0; k < P.nlocal[r]; ++k) {
+            UnitDev u{};
+            u.d = (int)di;
+            u.k = k;
+            u.sub = i;
+            u.off_xi = region_xi_off[r] + (int64_t)k * P.region_nterm[r];
+            u.off_S = S_off;
+            u.off_X = X_off;
+            u.off_L = L_off;
+            u.off_T = T_off;
+            S_off += (int64_t)h.R * h.R;
+            X_off += (int64_t)h.N * h.R;
+            L_off += (int64_t)h.N * (h.b + 1);
+            T_off += (int64_t)4 * h.N + h.n_medge;
+            A_off += (int64_t)h.R + (int64_t)h.R * h.R;
+            ctx->units.push_back(u);
+            ctx->pair_sub.push_back(i);
+            ctx->pair_k.push_back(k);
+        }
+        ctx->max_b = std::max(ctx->max_b, h.b);
+        ctx->max_R = std::max(ctx->max_R, h.R);
+        ctx->max_Rd = std::max(ctx->max_Rd, h.R);
+        int nout = h.N + (h.nx + 1) * h.ny + h.nx * (h.ny + 1);
+        ctx->max_nout_d = std::max(ctx->max_nout_d, nout);
+        ctx->cell_out_off.push_back(cell_tot);
+        ctx->edge_out_off.push_back(edge_tot);
+        cell_tot += h.N;
+        edge_tot += (int64_t)(h.nx + 1) * h.ny + (int64_t)h.nx * (h.ny + 1);
+    }
+    ctx->n_units = (int64_t)ctx->units.size();
+    if ((size_t)(ctx->max_b + 2) * (ctx->max_b + 1 + ctx->max_Rd) * 8 > 160 * 1024)
+        return fail(ctx, SDMM_EINVAL, "a Darcy subdomain's band window does not fit in LDS (shorter side too long)");
+    // ---- Stokes
+    ctx->sdev.clear();
+    std::vector<int> tr_sub, tr_r, tr_c, bmap, q_ptr, q_col;
+    std::vector<double> tr_v, Zc, q_val, uD;
+    std::vector<int64_t> uD_off;
+    int64_t tiles_off = 0, rhs_off = 0, U_off = 0, P_off = 0;
+    int gcol = 0;
+    ctx->max_nblk = ctx->max_w = ctx->max_ncol = 0;
+    ctx->max_nout_s = 0;
+    ctx->u_out_off.clear();
+    ctx->p_out_off.clear();
+    int64_t u_tot = 0, p_tot = 0;
+    std::vector<int64_t> sAbase;
+    for (size_t si = 0; si < P.stokes.size(); ++si) {
+        const StokesHost& h = P.stokes[si];
+        StokesDev s{};
+        s.nband = h.nband;
+        s.nblk = (h.nband + 63) / 64;
+        s.w = (h.bw + 63) / 64;
+        s.ncol = h.R + 1;
+        s.nvel = h.nvel;
+        s.npre = h.npre;
+        s.R = h.R;
+        s.nker = h.nker;
+        s.off_tiles = tiles_off;
+        s.off_rhs = rhs_off;
+        s.off_U = U_off;
+        s.off_P = P_off;
+        s.off_map = (int64_t)bmap.size();
+        s.off_Z = (int64_t)Zc.size();
+        s.off_q = (int64_t)q_ptr.size();
+        s.off_S = S_off;
+        s.off_dofs = P.sub_ptr[h.sub];
+        s.off_G = gcol;
+        tiles_off += (int64_t)s.nblk * (s.w + 1) * 4096;
+        rhs_off += (int64_t)s.nblk * 64 * s.ncol;
+        U_off += (int64_t)s.nvel * s.ncol;
+        P_off += (int64_t)s.npre * s.ncol;
+        for (int q = 0; q < h.nband; ++q) bmap.push_back(h.band_kind[q] == 0 ? h.band_raw[q] : -1 - h.band_raw[q]);
+        Zc.insert(Zc.end(), h.Z.begin(), h.Z.end());
+        int qb = (int)q_col.size();
+        for (int m = 0; m <= h.R; ++m) q_ptr.push_back(qb + h.q_ptr[m]);
+        q_col.insert(q_col.end(), h.q_col.begin(), h.q_col.end());
+        q_val.insert(q_val.end(), h.q_val.begin(), h.q_val.end());
+        uD_off.push_back((int64_t)uD.size());
+        uD.insert(uD.end(), h.uD.begin(), h.uD.end());
+        for (size_t q = 0; q < h.ar.size(); ++q) {
+            tr_sub.push_back((int)si);
+            tr_r.push_back(h.ar[q]);
+            tr_c.push_back(h.ac[q]);
+            tr_v.push_back(h.av[q]);
+        }
+        const int i = h.sub;
+        ctx->sub_R[i] = h.R;
+        ctx->sub_region[i] = -1;
+        ctx->sub_ker[i] = h.nker;
+        ctx->sub_Gcol[i] = gcol;
+        ctx->sub_nlocal[i] = 1;
+        ctx->sub_Sbase[i] = S_off;
+        ctx->sub_Abase[i] = A_off;
+        sAbase.push_back(A_off);
+        const int ext = h.R + h.nker;
+        A_off += (int64_t)ext + (int64_t)ext * ext;
+        S_off += (int64_t)h.R * h.R;
+        gcol += h.nker;
+        ctx->pair_sub.push_back(i);
+        ctx->pair_k.push_back(0);
+        ctx->sdev.push_back(s);
+        ctx->max_nblk = std::max(ctx->max_nblk, s.nblk);
+        ctx->max_w = std::max(ctx->max_w, s.w);
+        ctx->max_ncol = std::max(ctx->max_ncol, s.ncol);
+        ctx->max_R = std::max(ctx->max_R, h.R);
+        ctx->max_nout_s = std::max(ctx->max_nout_s, h.nvel + h.npre);
+        ctx->u_out_off.push_back(u_tot);
+        ctx->p_out_off.push_back(p_tot);
+        u_tot += h.nvel;
+        p_tot += h.npre;
+    }
+    ctx->max_ext = 0;
+    for (int i = 0; i < nsub; ++i) ctx->max_ext = std::max(ctx->max_ext, ctx->sub_R[i] + ctx->sub_ker[i]);
+    if ((size_t)64 * ctx->max_ext * 8 > 150 * 1024) return fail(ctx, SDMM_EINVAL, "too many mortar DOFs on one subdomain");
+    if (P.n_kernel > 16) return fail(ctx, SDMM_EINVAL, "more than 16 FETI kernel modes");
+    ctx->n_trip = (int64_t)tr_v.size();
+    ctx->S_total = S_off;
+    ctx->X_total = X_off;
+    ctx->L_total = L_off;
+    ctx->T_total = T_off;
+    ctx->A_total = A_off;
+    ctx->field_size[0] = P.M;
+    ctx->field_size[1] = cell_tot;
+    ctx->field_size[2] = edge_tot;
+    ctx->field_size[3] = u_tot;
+    ctx->field_size[4] = p_tot;
+    if (ctx->host_only) return SDMM_OK;
+    // ---- uploads
+    int rc;
+#define UP(buf, vec) \
+    if ((rc = upload(ctx, buf, vec))) return rc;
+    UP(ctx->d_dar, dar);
+    UP(ctx->d_units, ctx->units);
+    UP(ctx->d_be_cell, be_cell);
+    UP(ctx->d_be_kind, be_kind);
+    UP(ctx->d_be_len, be_len);
+    UP(ctx->d_be_hperp, be_hperp);
+    UP(ctx->d_be_medge, be_medge);
+    UP(ctx->d_be_sgn, be_sgn);
+    UP(ctx->d_cell_be, cell_be);
+    UP(ctx->d_Pi, Pi);
+    UP(ctx->d_phi, phi);
+    UP(ctx->d_xi, xi);
+    UP(ctx->d_supp_ptr, supp_ptr);
+    UP(ctx->d_supp_e, supp_e);
+    UP(ctx->d_supp_v, supp_v);
+    UP(ctx->d_me_cell, me_cell);
+    UP(ctx->d_sdev, ctx->sdev);
+    UP(ctx->d_bmap, bmap);
+    UP(ctx->d_Z, Zc);
+    UP(ctx->d_q_ptr, q_ptr);
+    UP(ctx->d_q_col, q_col);
+    UP(ctx->d_q_val, q_val);
+    UP(ctx->d_uD, uD);
+    UP(ctx->d_uD_off, uD_off);
+    UP(ctx->d_tr_sub, tr_sub);
+    UP(ctx->d_tr_r, tr_r);
+    UP(ctx->d_tr_c, tr_c);
+    UP(ctx->d_tr_v, tr_v);
+    std::vector<int64_t> dofs(P.sub_dofs.begin(), P.sub_dofs.end());
+    UP(ctx->d_sub_dofs, dofs);
+    UP(ctx->d_sub_dof_ptr, P.sub_ptr);
+    UP(ctx->d_sub_R, ctx->sub_R);
+    UP(ctx->d_sub_region, ctx->sub_region);
+    UP(ctx->d_sub_Sbase, ctx->sub_Sbase);
+    UP(ctx->d_sub_ker, ctx->sub_ker);
+    UP(ctx->d_sub_Gcol, ctx->sub_Gcol);
+    UP(ctx->d_sub_Abase, ctx->sub_Abase);
+    UP(ctx->d_sub_nlocal, ctx->sub_nlocal);
+    UP(ctx->d_pair_sub, ctx->pair_sub);
+    UP(ctx->d_pair_k, ctx->pair_k);
+    UP(ctx->d_g2l, P.g2l);
+    UP(ctx->d_weights, P.weights);
+    UP(ctx->d_unit_of_dk, unit_of_dk);
+    UP(ctx->d_dnlocal, dnlocal);
+    UP(ctx->d_dAbase, dAbase);
+    UP(ctx->d_cell_out, ctx->cell_out_off);
+    UP(ctx->d_edge_out, ctx->edge_out_off);
+    UP(ctx->d_sAbase, sAbase);
+    UP(ctx->d_u_out, ctx->u_out_off);
+    UP(ctx->d_p_out, ctx->p_out_off);
+#undef UP
+    if ((rc = alloc(ctx, ctx->d_S, ctx->S_total * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_X, ctx->X_total * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_L, ctx->L_total * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_T, ctx->T_total * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_tiles, tiles_off * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_rhs, rhs_off * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_U, U_off * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_P, P_off * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_g, (size_t)P.M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_G, (size_t)P.M * std::max(1, P.n_kernel) * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_GtGinv, (size_t)std::max(1, P.n_kernel * P.n_kernel) * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_acc, ctx->A_total * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_lam1, (size_t)P.M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_lam2, (size_t)P.M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_wsum, 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_refine, 16))) return rc;
+    int64_t mom = 2 * (ctx->field_size[1] + ctx->field_size[2] + ctx->field_size[3] + ctx->field_size[4]);
+    if ((rc = alloc(ctx, ctx->d_mom, (size_t)std::max<int64_t>(mom, 1) * 8))) return rc;
+    // Stokes RHS into the padded band layout
+    std::vector<double> rhs((size_t)rhs_off, 0.0);
+    for (size_t si = 0; si < P.stokes.size(); ++si) {
+        const StokesHost& h = P.stokes[si];
+        const StokesDev& s = ctx->sdev[si];
+        const int64_t ld = (int64_t)s.nblk * 64;
+        for (int c = 0; c < s.ncol; ++c)
+            for (int q = 0; q < h.nband; ++q) rhs[s.off_rhs + c * ld + q] = h.rhs[(size_t)c * h.nband + q];
+    }
+    ctx->d_rhs.release();
+    if ((rc = upload(ctx, ctx->d_rhs, rhs))) return rc;
+    HIPCHK(hipMemset(ctx->d_acc.p, 0, ctx->d_acc.bytes));
+    HIPCHK(hipMemset(ctx->d_lam1.p, 0, ctx->d_lam1.bytes));
+    HIPCHK(hipMemset(ctx->d_lam2.p, 0, ctx->d_lam2.bytes));
+    HIPCHK(hipMemset(ctx->d_wsum.p, 0, 8));
+    return SDMM_OK;
+}
+
+int build_stokes(sdmm_ctx* ctx, hipStream_t st) {
+    Problem& P = ctx->P;
+    const int ns = (int)ctx->sdev.size();
+    HIPCHK(hipMemsetAsync(ctx->d_g.p, 0, ctx->d_g.bytes, st));
+    HIPCHK(hipMemsetAsync(ctx->d_G.p, 0, ctx->d_G.bytes, st));
+    if (ns == 0) return SDMM_OK;
+    StokesDev* sd = ctx->d_sdev.as<StokesDev>();
+    double* tiles = ctx->d_tiles.as<double>();
+    HIPCHK(hipMemsetAsync(ctx->d_tiles.p, 0, ctx->d_tiles.bytes, st));
+    HIPCHK(launch_stokes_scatter(sd, ns, ctx->d_tr_sub.as<int>(), ctx->d_tr_r.as<int>(), ctx->d_tr_c.as<int>(),
+                                 ctx->d_tr_v.as<double>(), ctx->n_trip, tiles, st));
+    HIPCHK(launch_stokes_pad_identity(sd, ns, ctx->max_nblk, tiles, st));
+    for (int J = 0; J < ctx->max_nblk; ++J) HIPCHK(launch_stokes_ldl_step(sd, ns, J, ctx->max_w, tiles, st));
+    HIPCHK(launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, ctx->d_rhs.as<double>(), st));
+    HIPCHK(launch_stokes_finish(sd, ns, ctx->max_ncol, ctx->max_R, ctx->d_rhs.as<double>(), ctx->d_bmap.as<int>(),
+                                ctx->d_uD.as<double>(), ctx->d_uD_off.as<int64_t>(), ctx->d_Z.as<double>(),
+                                ctx->d_q_ptr.as<int>(), ctx->d_q_col.as<int>(), ctx->d_q_val.as<double>(),
+                                ctx->d_sub_dofs.as<int64_t>(), ctx->d_U.as<double>(), ctx->d_P.as<double>(),
+                                ctx->d_S.as<double>(), ctx->d_g.as<double>(), ctx->d_G.as<double>(), P.M, st));
+    // FETI coarse matrix (G^T G)^{-1}: n_kernel x n_kernel, inverted on the host
+    const int nk = P.n_kernel;
+    if (nk > 0) {
+        std::vector<double> G((size_t)P.M * nk);
+        HIPCHK(hipMemcpyAsync(G.data(), ctx->d_G.p, G.size() * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<double> A((size_t)nk * nk), Inv((size_t)nk * nk, 0.0);
+        for (int a = 0; a < nk; ++a)
+            for (int b = 0; b < nk; ++b) {
+                double s = 0;
+                for (int m = 0; m < P.M; ++m) s += G[(size_t)a * P.M + m] * G[(size_t)b * P.M + m];
+                A[a * nk + b] = s;
+            }
+        for (int a = 0; a < nk; ++a) Inv[a * nk + a] = 1.0;
+        for (int c = 0; c < nk; ++c) {  // Gauss-Jordan with partial pivoting
+            int piv = c;
+            for (int r = c + 1; r < nk; ++r)
+                if (std::fabs(A[r * nk + c]) > std::fabs(A[piv * nk + c])) piv = r;
+            if (std::fabs(A[piv * nk + c]) < 1e-300) return fail(ctx, SDMM_EINVAL, "singular FETI coarse matrix");
+            for (int k = 0; k < nk; ++k) {
+                std::swap(A[c * nk + k], A[piv * nk + k]);
+                std::swap(Inv[c * nk + k], Inv[piv * nk + k]);
+            }
+            double d = A[c * nk + c];
+            for (int k = 0; k < nk; ++k) {
+                A[c * nk + k] /= d;
+                Inv[c * nk + k] /= d;
+            }
+            for (int r = 0; r < nk; ++r)
+                if (r != c) {
+                    double f = A[r * nk + c];
+                    for (int k = 0; k < nk; ++k) {
+                        A[r * nk + k] -= f * A[c * nk + k];
+                        Inv[r * nk + k] -= f * Inv[c * nk + k];
+                    }
+                }
+        }
+        HIPCHK(hipMemcpy(ctx->d_GtGinv.p, Inv.data(), Inv.size() * 8, hipMemcpyHostToDevice));
+    }
+    return SDMM_OK;
+}
+
+CgArgs cg_args(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double* lam) {
+    CgArgs a{};
+    a.n = n;
+    a.M = ctx->P.M;
+    a.nsub = (int)ctx->P.subs.size();
+    a.nregion = ctx->P.n_region;
+    a.nker = ctx->P.n_kernel;
+    a.gidx = gidx;
+    a.g2l = ctx->d_g2l.as<int32_t>();
+    a.sub_R = ctx->d_sub_R.as<int>();
+    a.sub_dof_ptr = ctx->d_sub_dof_ptr.as<int64_t>();
+    a.sub_dofs = ctx->d_sub_dofs.as<int64_t>();
+    a.sub_region = ctx->d_sub_region.as<int>();
+    a.sub_Sbase = ctx->d_sub_Sbase.as<int64_t>();
+    a.S_cache = ctx->d_S.as<double>();
+    a.g = ctx->d_g.as<double>();
+    a.G = ctx->d_G.as<double>();
+    a.GtGinv = ctx->d_GtGinv.as<double>();
+    a.lam = lam;
+    a.r = ctx->w_r.as<double>();
+    a.p = ctx->w_p.as<double>();
+    a.Ap = ctx->w_Ap.as<double>();
+    a.rr = ctx->w_rr.as<double>();
+    a.r0 = ctx->w_r0.as<double>();
+    a.iters = ctx->w_iters.as<int32_t>();
+    a.relres = ctx->w_relres.as<double>();
+    a.status = ctx->w_status.as<int32_t>();
+    a.active = ctx->w_active.as<int32_t>();
+    a.any_active = ctx->w_any.as<int32_t>();
+    return a;
+}
+
+// Every global index must address a collocation point; checked on the
+// device before any kernel dereferences the global->local table.
+int check_indices(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
+    int32_t bad = 0;
+    HIPCHK(hipMemsetAsync(ctx->w_any.p, 0, 4, st));
+    HIPCHK(launch_validate_index(gidx, n, ctx->P.nreal, ctx->w_any.as<int32_t>(), st));
+    HIPCHK(hipMemcpyAsync(&bad, ctx->w_any.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad) return fail(ctx, SDMM_EINVAL, "a global collocation index is out of range");
+    return SDMM_OK;
+}
+
+int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
+    if (n <= ctx->w_cap) return SDMM_OK;
+    const size_t M = ctx->P.M;
+    int rc;
+    if ((rc = alloc(ctx, ctx->w_r, n * M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_p, n * M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_Ap, n * M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_Slam, n * M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_rr, n * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_r0, n * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_iters, n * 4))) return rc;
+    if ((rc = alloc(ctx, ctx->w_relres, n * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_status, n * 4))) return rc;
+    if ((rc = alloc(ctx, ctx->w_active, n * 4))) return rc;
+    if ((rc = alloc(ctx, ctx->w_any, 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_alpha, n * std::max(1, ctx->P.n_kernel) * 8))) return rc;
+    ctx->w_cap = n;
+    return SDMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdmm_create(int device, sdmm_ctx** out) {
+    if (!out) return SDMM_EINVAL;
+    *out = nullptr;
+    if (device == -1) {
+        sdmm_ctx* c = new (std::nothrow) sdmm_ctx();
+        if (!c) return SDMM_ENOMEM;
+        c->device = -1;
+        c->host_only = true;
+        *out = c;
+        return SDMM_OK;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SDMM_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SDMM_EDEVICE;
+    sdmm_ctx* c = new (std::nothrow) sdmm_ctx();
+    if (!c) return SDMM_ENOMEM;
+    c->device = device;
+    for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return SDMM_EDEVICE;
+        }
+    *out = c;
+    return SDMM_OK;
+}
+
+int sdmm_destroy(sdmm_ctx* ctx) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) {
+        delete ctx;
+        return SDMM_OK;
+    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return SDMM_OK;
+}
+
+const char* sdmm_last_error(const sdmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sdmm_set_problem(sdmm_ctx* ctx, const sdmm_problem* p) {
+    if (!ctx || !p) return fail(ctx, SDMM_EINVAL, "null argument");
+    if (!ctx->host_only) {
+        HIPCHK(hipSetDevice(ctx->device));
+        HIPCHK(hipDeviceSynchronize());
+    }
+    ctx->have_problem = false;
+    ctx->basis_built = false;
+    ctx->stokes_built = false;
+    std::string err = build_problem(*p, ctx->P);
+    if (!err.empty()) return fail(ctx, SDMM_EINVAL, err);
+    ctx->w_cap = 0;
+    ctx->pair_sub.clear();
+    ctx->pair_k.clear();
+    int rc = setup_device(ctx);
+    if (rc) return rc;
+    ctx->counters = sdmm_counters{};
+    ctx->have_problem = true;
+    return SDMM_OK;
+}
+
+int sdmm_get_sizes(sdmm_ctx* ctx, sdmm_sizes* o) {
+    if (!ctx || !o) return fail(ctx, SDMM_EINVAL, "null argument");
+    if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
+    const Problem& P = ctx->P;
+    *o = sdmm_sizes{};
+    o->n_sub = (int64_t)P.subs.size();
+    o->n_stokes = P.n_stokes;
+    o->n_darcy = P.n_darcy;
+    o->n_iface = (int64_t)P.ifaces.size();
+    o->M = P.M;
+    o->n_real = P.nreal;
+    o->n_term = P.nterm;
+    o->n_region = P.n_region;
+    o->n_units = ctx->n_units;
+    int nf = 0;
+    for (auto& s : P.stokes) nf += s.floating;
+    o->n_floating = nf;
+    o->n_kernel = P.n_kernel;
+    for (int k = 0; k < 5; ++k) o->field_size[k] = ctx->field_size[k];
+    o->basis_bytes = ctx->S_total * 8;
+    o->response_bytes = ctx->X_total * 8;
+    o->max_R = ctx->max_R;
+    int64_t fl = 0;
+    for (auto& u : ctx->units) {
+        const DarcyHost& h = P.darcy[u.d];
+        fl += (int64_t)h.N * h.b * h.b + 4LL * h.N * h.b * h.R;
+    }
+    o->darcy_flops = fl;
+    return SDMM_OK;
+}
+
+int sdmm_get_index_map(sdmm_ctx* ctx, int kind, int64_t* out, int64_t cap, int64_t* n_out) {
+    if (!ctx || !n_out) return fail(ctx, SDMM_EINVAL, "null argument");
+    if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
+    const Problem& P = ctx->P;
+    std::vector<int64_t> v;
+    switch (kind) {
+        case SDMM_MAP_INTERFACES:
+            for (auto& f : P.ifaces) {
+                v.push_back(f.i);
+                v.push_back(f.j);
+                v.push_back(f.kind);
+                v.push_back(f.ndof);
+                v.push_back(f.off);
+            }
+            break;
+        case SDMM_MAP_SUB_PTR: v.assign(P.sub_ptr.begin(), P.sub_ptr.end()); break;
+        case SDMM_MAP_SUB_DOFS: v.assign(P.sub_dofs.begin(), P.sub_dofs.end()); break;
+        case SDMM_MAP_SUB_SIGN: v.assign(P.sub_sign.begin(), P.sub_sign.end()); break;
+        case SDMM_MAP_G2L: v.assign(P.g2l.begin(), P.g2l.end()); break;
+        case SDMM_MAP_NLOCAL: v.assign(P.nlocal.begin(), P.nlocal.end()); break;
+        case SDMM_MAP_NODE_IDS: v.assign(P.ids.begin(), P.ids.end()); break;
+        default: return fail(ctx, SDMM_EINVAL, "unknown map kind");
+    }
+    *n_out = (int64_t)v.size();
+    if (!out) return SDMM_OK;
+    if (cap < (int64_t)v.size()) return fail(ctx, SDMM_EINVAL, "output capacity too small");
+    std::copy(v.begin(), v.end(), out);
+    return SDMM_OK;
+}
+
+int sdmm_get_collocation(sdmm_ctx* ctx, double* points, double* weights) {
+    if (!ctx) return SDMM_EINVAL;
+    if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
+    const Problem& P = ctx->P;
+    if (points)
+        for (size_t q = 0; q < P.ids.size(); ++q) points[q] = P.node_x[P.ids[q]];
+    if (weights) std::copy(P.weights.begin(), P.weights.end(), weights);
+    return SDMM_OK;
+}
+
+int sdmm_get_kl(sdmm_ctx* ctx, int region, double* lam, int32_t* modes) {
+    if (!ctx) return SDMM_EINVAL;
+    if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
+    if (region < 0 || region >= ctx->P.n_region) return fail(ctx, SDMM_EINVAL, "bad region");
+    const KLRegion& K = ctx->P.kl[region];
+    for (size_t t = 0; t < K.lam.size(); ++t) {
+        if (lam) lam[t] = K.lam[t];
+        if (modes) {
+            modes[2 * t] = K.ma[t];
+            modes[2 * t + 1] = K.mb[t];
+        }
+    }
+    return SDMM_OK;
+}
+
+int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
+    if (precision != SDMM_PREC_FP64 && precision != SDMM_PREC_MIXED) return fail(ctx, SDMM_EINVAL, "bad precision");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    DarcyTables t = darcy_tables(ctx);
+    HIPCHK(hipEventRecord(ctx->ev[0], st));
+    if (precision == SDMM_PREC_FP64) {
+        HIPCHK(launch_darcy_basis_fp64(t, (int)ctx->n_units, ctx->max_b, ctx->max_Rd, ctx->d_S.as<double>(),
+                                       ctx->d_X.as<double>(), ctx->d_L.as<double>(), ctx->d_T.as<double>(), st));
+    } else {
+        int rc;
+        if (!ctx->d_L32.p && (rc = alloc(ctx, ctx->d_L32, ctx->L_total * 4))) return rc;
+        if (!ctx->d_W32.p && (rc = alloc(ctx, ctx->d_W32, ctx->X_total * 4))) return rc;
+        HIPCHK(hipMemsetAsync(ctx->d_refine.p, 0, 16, st));
+        double* max_res = ctx->d_refine.as<double>();
+        int* steps = reinterpret_cast<int*>(ctx->d_refine.as<char>() + 8);
+        HIPCHK(launch_darcy_basis_mixed(t, (int)ctx->n_units, ctx->max_b, ctx->max_Rd, ctx->d_S.as<double>(),
+                                        ctx->d_X.as<double>(), ctx->d_L32.as<float>(), ctx->d_T.as<double>(),
+                                        ctx->d_W32.as<float>(), nullptr, 3, 1e-13, max_res, steps, st));
+    }
+    HIPCHK(hipEventRecord(ctx->ev[1], st));
+    if (!ctx->stokes_built) {
+        int rc = build_stokes(ctx, st);
+        if (rc) return rc;
+        ctx->stokes_built = true;
+    }
+    HIPCHK(hipEventRecord(ctx->ev[2], st));
+    ctx->built_precision = precision;
+    ctx->basis_built = true;
+    int64_t sd = 0, ss = 0;
+    for (auto& u : ctx->units) sd += ctx->P.darcy[u.d].R;
+    for (auto& s : ctx->P.stokes) ss += s.R;
+    ctx->counters.basis_solves_darcy += sd;
+    ctx->counters.basis_solves_stokes = ss;
+    ctx->counters.complementary_solves = (int64_t)ctx->P.stokes.size();
+    ctx->counters.units_built += ctx->n_units;
+    return SDMM_OK;
+}
+
+int sdmm_get_basis(sdmm_ctx* ctx, int sub, int k, double* S, int64_t ld) {
+    if (!ctx || !S) return fail(ctx, SDMM_EINVAL, "null argument");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    if (sub < 0 || sub >= (int)ctx->P.subs.size()) return fail(ctx, SDMM_EINVAL, "bad subdomain");
+    const int R = ctx->sub_R[sub];
+    if (k < 0 || k >= ctx->sub_nlocal[sub] || ld < R) return fail(ctx, SDMM_EINVAL, "bad local index or ld");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<double> tmp((size_t)R * R);
+    HIPCHK(hipMemcpy(tmp.data(), ctx->d_S.as<double>() + ctx->sub_Sbase[sub] + (int64_t)k * R * R, tmp.size() * 8,
+                     hipMemcpyDeviceToHost));
+    for (int j = 0; j < R; ++j)
+        for (int m = 0; m < R; ++m) S[(int64_t)j * ld + m] = tmp[(size_t)j * R + m];
+    return SDMM_OK;
+}
+
+int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, double* lambda,
+                         int32_t* iters, double* relres, int32_t* status, void* stream) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    if (n < 0 || (n > 0 && (!gidx || !lambda)) || !(rtol > 0) || max_iter < 1)
+        return fail(ctx, SDMM_EINVAL, "invalid arguments");
+    if (n == 0) return SDMM_OK;
+    if (n > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    int rc = ensure_workspace(ctx, n);
+    if (rc) return rc;
+    if ((rc = check_indices(ctx, gidx, n, st))) return rc;
+    CgArgs a = cg_args(ctx, n, gidx, lambda);
+    a.rtol = rtol;
+    a.max_iter = max_iter;
+    HIPCHK(hipEventRecord(ctx->ev[3], st));
+    HIPCHK(launch_cg_init(a, st));
+    int it = 0;
+    int32_t any = 1;
+    const int group = 8;
+    while (it < max_iter) {
+        HIPCHK(hipMemsetAsync(a.any_active, 0, 4, st));
+        for (int q = 0; q < group && it < max_iter; ++q, ++it) {
+            HIPCHK(launch_cg_apply(a, a.p, a.Ap, ctx->max_R, true, st));
+            HIPCHK(launch_cg_update(a, it, st));
+        }
+        HIPCHK(hipMemcpyAsync(&any, a.any_active, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!any) break;
+    }
+    HIPCHK(launch_cg_finish(a, lambda, iters, relres, status, st));
+    HIPCHK(hipEventRecord(ctx->ev[4], st));
+    std::vector<int32_t> stv(n), itv(n);
+    HIPCHK(hipMemcpyAsync(stv.data(), a.status, n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(itv.data(), a.iters, n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t tot = 0;
+    bool bad = false, brk = false;
+    for (int64_t l = 0; l < n; ++l) {
+        tot += itv[l];
+        bad |= stv[l] != SDMM_CG_CONVERGED;
+        brk |= stv[l] == SDMM_CG_BREAKDOWN;
+    }
+    ctx->counters.cg_iterations += tot;
+    ctx->counters.realizations += n;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, ctx->ev[3], ctx->ev[4]) == hipSuccess) ctx->counters.ms_solve = ms;
+    if (brk) return fail(ctx, SDMM_EBREAKDOWN, "CG breakdown in some realization");
+    if (bad) return fail(ctx, SDMM_ENOTCONV, "some realization reached max_iter");
+    return SDMM_OK;
+}
+
+int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const double* lambda, const double* weights,
+                            void* stream) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    if (n < 0 || (n > 0 && (!gidx || !lambda))) return fail(ctx, SDMM_EINVAL, "invalid arguments");
+    if (n == 0) return SDMM_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    int rc = ensure_workspace(ctx, n);
+    if (rc) return rc;
+    if ((rc = check_indices(ctx, gidx, n, st))) return rc;
+    CgArgs a = cg_args(ctx, n, gidx, const_cast<double*>(lambda));
+    if (ctx->P.n_kernel > 0) {
+        HIPCHK(hipMemsetAsync(ctx->w_Slam.p, 0, (size_t)n * ctx->P.M * 8, st));
+        HIPCHK(launch_cg_apply(a, lambda, ctx->w_Slam.as<double>(), ctx->max_R, false, st));
+        HIPCHK(launch_alpha(a, ctx->w_Slam.as<double>(), ctx->w_alpha.as<double>(), st));
+    }
+    MomArgs m{};
+    m.n = n;
+    m.M = ctx->P.M;
+    m.nsub = (int)ctx->P.subs.size();
+    m.nregion = ctx->P.n_region;
+    m.nker = ctx->P.n_kernel;
+    m.gidx = gidx;
+    m.g2l = ctx->d_g2l.as<int32_t>();
+    m.weights = weights;
+    m.colloc_w = ctx->d_weights.as<double>();
+    m.lam = lambda;
+    m.sub_R = ctx->d_sub_R.as<int>();
+    m.sub_dof_ptr = ctx->d_sub_dof_ptr.as<int64_t>();
+    m.sub_dofs = ctx->d_sub_dofs.as<int64_t>();
+    m.sub_region = ctx->d_sub_region.as<int>();
+    m.sub_ker = ctx->d_sub_ker.as<int>();
+    m.sub_Gcol = ctx->d_sub_Gcol.as<int>();
+    m.sub_Abase = ctx->d_sub_Abase.as<int64_t>();
+    m.sub_nlocal = ctx->d_sub_nlocal.as<int>();
+    m.alpha = ctx->w_alpha.as<double>();
+    m.acc = ctx->d_acc.as<double>();
+    m.lam1 = ctx->d_lam1.as<double>();
+    m.lam2 = ctx->d_lam2.as<double>();
+    m.wsum = ctx->d_wsum.as<double>();
+    HIPCHK(launch_accumulate_pairs(m, ctx->d_pair_sub.as<int>(), ctx->d_pair_k.as<int>(), (int)ctx->pair_sub.size(),
+                                   ctx->max_ext, st));
+    return SDMM_OK;
+}
+
+int sdmm_reset_moments(sdmm_ctx* ctx) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemset(ctx->d_acc.p, 0, ctx->d_acc.bytes));
+    HIPCHK(hipMemset(ctx->d_lam1.p, 0, ctx->d_lam1.bytes));
+    HIPCHK(hipMemset(ctx->d_lam2.p, 0, ctx->d_lam2.bytes));
+    HIPCHK(hipMemset(ctx->d_wsum.p, 0, 8));
+    return SDMM_OK;
+}
+
+int sdmm_get_moments(sdmm_ctx* ctx, int field, double* mean, double* var) {
+    if (!ctx || !mean || !var) return fail(ctx, SDMM_EINVAL, "null argument");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    if (field < 0 || field > 4) return fail(ctx, SDMM_EINVAL, "bad field");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    const int64_t n = ctx->field_size[field];
+    std::vector<double> m1(n), m2(n);
+    if (field == SDMM_FIELD_LAMBDA) {
+        HIPCHK(hipMemcpy(m1.data(), ctx->d_lam1.p, n * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(m2.data(), ctx->d_lam2.p, n * 8, hipMemcpyDeviceToHost));
+    } else {
+        double* base = ctx->d_mom.as<double>();
+        double* p1 = base;
+        double* p2 = p1 + ctx->field_size[1];
+        double* u1 = p2 + ctx->field_size[1];
+        double* u2 = u1 + ctx->field_size[2];
+        double* su1 = u2 + ctx->field_size[2];
+        double* su2 = su1 + ctx->field_size[3];
+        double* sp1 = su2 + ctx->field_size[3];
+        double* sp2 = sp1 + ctx->field_size[4];
+        if (field <= SDMM_FIELD_DARCY_U) {
+            DarcyTables t = darcy_tables(ctx);
+            HIPCHK(launch_darcy_moments_impl(t, ctx->d_unit_of_dk.as<int>(), ctx->d_dnlocal.as<int>(),
+                                             (int)ctx->P.darcy.size(), ctx->max_nout_d, ctx->max_units_per_d,
+                                             ctx->d_dAbase.as<int64_t>(), ctx->d_acc.as<double>(),
+                                             ctx->d_X.as<double>(), ctx->max_Rd, ctx->d_cell_out.as<int64_t>(),
+                                             ctx->d_edge_out.as<int64_t>(), p1, p2, u1, u2, 0));
+        } else {
+            HIPCHK(launch_stokes_moments_impl(ctx->d_sdev.as<StokesDev>(), (int)ctx->sdev.size(), ctx->max_nout_s,
+                                              ctx->d_sAbase.as<int64_t>(), ctx->d_acc.as<double>(),
+                                              ctx->d_wsum.as<double>(), ctx->d_U.as<double>(), ctx->d_P.as<double>(),
+                                              ctx->d_Z.as<double>(), ctx->d_u_out.as<int64_t>(),
+                                              ctx->d_p_out.as<int64_t>(), ctx->max_ext, su1, su2, sp1, sp2, 0));
+        }
+        HIPCHK(hipDeviceSynchronize());
+        double* s1 = field == 1 ? p1 : field == 2 ? u1 : field == 3 ? su1 : sp1;
+        double* s2 = field == 1 ? p2 : field == 2 ? u2 : field == 3 ? su2 : sp2;
+        HIPCHK(hipMemcpy(m1.data(), s1, n * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(m2.data(), s2, n * 8, hipMemcpyDeviceToHost));
+    }
+    for (int64_t q = 0; q < n; ++q) {
+        mean[q] = m1[q];
+        var[q] = m2[q] - m1[q] * m1[q];
+    }
+    return SDMM_OK;
+}
+
+int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out) {
+    if (!ctx || !out) return fail(ctx, SDMM_EINVAL, "null argument");
+    if (ctx->host_only) {
+        *out = ctx->counters;
+        return SDMM_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    float ms = 0;
+    if (ctx->basis_built) {
+        if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->counters.ms_basis_darcy = ms;
+        if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->counters.ms_basis_stokes = ms;
+        if (ctx->built_precision == SDMM_PREC_MIXED && ctx->d_refine.p) {
+            double mr;
+            int steps;
+            HIPCHK(hipMemcpy(&mr, ctx->d_refine.p, 8, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(&steps, ctx->d_refine.as<char>() + 8, 4, hipMemcpyDeviceToHost));
+            ctx->counters.max_refine_residual = mr;
+            ctx->counters.refinement_steps = steps;
+        }
+    }
+    *out = ctx->counters;
+    return SDMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1355 @@
+// HIP kernels of the stochastic multiscale flux basis library (gfx950).
+//
+//   darcy_basis_fp64   Method S3 pre-computation loop for Darcy subdomains
+//                      (Section 5.4): per (subdomain, local realization) unit,
+//                      K = exp(Y) from the KL expansion (eq. KLapprox), the
+//                      RT0-Q0 cell-centred operator, its band Cholesky factor,
+//                      the solves for every mortar basis function (eqs.
+//                      starDproblem1-2) and the flux basis S_{H,i}^{(k)}.
+//   stokes_*           the same for Stokes subdomains (eqs. starSproblem1-2,
+//                      barSproblem1-2) with a tiled band LDL^T of the
+//                      Taylor-Hood saddle matrix.
+//   cg_*               CG on S_H lambda = g_H (Section 5.1) batched over
+//                      collocation points, S_H applied as linear combinations
+//                      of the basis (Section 5.3).
+//   accumulate / *_moments   weighted moments (Section 2, Step 6 of S3).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+#include "../../include/sdmm.h"
+
+namespace sdmm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTile = 64;
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum (fixed order for a fixed block size).  `red` holds
+// at least blockDim.x / 64 doubles.  The result is returned to every thread.
+__device__ inline double block_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < nw; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+__device__ inline int cell_of_internal(int c, int nx, int ny, int swap) {
+    if (!swap) return c;
+    const int ix = c / ny, iy = c - ix * ny;
+    return iy * nx + ix;
+}
+
+__device__ inline int internal_of_cell(int cell, int nx, int ny, int swap) {
+    if (!swap) return cell;
+    const int iy = cell / nx, ix = cell - iy * nx;
+    return ix * ny + iy;
+}
+
+__device__ inline double darcy_K(const DarcyTables& t, const DarcyDev& D, const double* xi, int cell) {
+    double y = D.mean_logk;
+    const double* phi = t.phi + D.off_phi;
+    for (int s = 0; s < D.nterm; ++s) y += xi[s] * phi[(int64_t)s * D.N + cell];
+    return exp(y);
+}
+
+// Transmissibilities of one unit (the RT0-Q0 operator with trapezoidal mass):
+//   Tf[c]  between internal cells c and c+1 (0 at the end of a line)
+//   Ts[c]  between internal cells c and c+b (0 on the last line)
+//   Tb[c]  sum of Dirichlet / mortar boundary-edge terms of cell c
+//   Tm[e]  the term of mortar edge e
+__device__ void darcy_transmissibilities(const DarcyTables& t, const DarcyDev& D, const double* xi, double* Ksc,
+                                         double* Tf, double* Ts, double* Tb, double* Tm) {
+    const int N = D.N, b = D.b;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) Ksc[c] = darcy_K(t, D, xi, cell_of_internal(c, D.nx, D.ny, D.swap));
+    __syncthreads();
+    const double nu = D.nu;
+    // edges along the fast direction have length h_slow and normal spacing h_fast
+    const double hf = D.swap ? D.hy : D.hx, hs = D.swap ? D.hx : D.hy;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+        const double kc = Ksc[c];
+        double tf = 0.0, ts = 0.0;
+        if ((c % b) != b - 1) tf = hs / (nu * (0.5 * hf) * (1.0 / kc + 1.0 / Ksc[c + 1]));
+        if (c + b < N) ts = hf / (nu * (0.5 * hs) * (1.0 / kc + 1.0 / Ksc[c + b]));
+        Tf[c] = tf;
+        Ts[c] = ts;
+        const int cell = cell_of_internal(c, D.nx, D.ny, D.swap);
+        double tb = 0.0;
+        for (int q = 0; q < 2; ++q) {
+            const int e = t.cell_be[D.off_cellbe + 2 * cell + q];
+            if (e < 0) continue;
+            const int kind = t.be_kind[D.off_be + e];
+            if (kind == 2) continue;
+            const double T = 2.0 * t.be_len[D.off_be + e] * kc / (nu * t.be_hperp[D.off_be + e]);
+            tb += T;
+            if (kind == 0) Tm[t.be_medge[D.off_be + e]] = T;
+        }
+        Tb[c] = tb;
+    }
+    __syncthreads();
+}
+
+__device__ inline double band_entry(const double* Tf, const double* Ts, const double* Tb, int col, int d, int b,
+                                    int N) {
+    if (col >= N) return 0.0;
+    double v = 0.0;
+    if (d == 0) {
+        v = Tf[col] + Ts[col] + Tb[col];
+        if (col % b) v += Tf[col - 1];
+        if (col >= b) v += Ts[col - b];
+    }
+    if (d == 1) v -= Tf[col];
+    if (d == b) v -= Ts[col];
+    return v;
+}
+
+// E[row, r]: mortar boundary loads of the cell at internal index row.
+__device__ inline double rhs_entry(const DarcyTables& t, const DarcyDev& D, const double* Tm, int row, int r) {
+    if (row >= D.N) return 0.0;
+    const int cell = cell_of_internal(row, D.nx, D.ny, D.swap);
+    double v = 0.0;
+    for (int q = 0; q < 2; ++q) {
+        const int e = t.cell_be[D.off_cellbe + 2 * cell + q];
+        if (e < 0 || t.be_kind[D.off_be + e] != 0) continue;
+        const int me = t.be_medge[D.off_be + e];
+        v += Tm[me] * t.Pi[D.off_Pi + (int64_t)me * D.R + r];
+    }
+    return v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Darcy basis, FP64.  One workgroup per (subdomain, local realization).
+// The band (half width b = the shorter side) is factored column by column
+// in a sliding LDS window of b + 2 columns (right-looking, one barrier per
+// column); the R right-hand sides ride along in the same window (forward
+// solve fused with the factorisation), then a backward sweep gives the fine
+// pressure responses X = P^{-1} E, and S = Pi^T T Pi - E^T X.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void darcy_basis_fp64_kernel(DarcyTables t, double* __restrict__ S_cache,
+                                                                    double* __restrict__ X, double* __restrict__ Lscr,
+                                                                    double* __restrict__ Tscr) {
+    extern __shared__ double sm[];
+    const UnitDev U = t.units[blockIdx.x];
+    const DarcyDev D = t.dar[U.d];
+    const int N = D.N, b = D.b, R = D.R;
+    const int nslot = b + 2, bw = b + 1;
+    double* band = sm;                    // nslot x (b + 1)
+    double* rhs = band + nslot * bw;      // nslot x R
+    double* Ksc = Tscr + U.off_T;
+    double* Tf = Ksc + N;
+    double* Ts = Tf + N;
+    double* Tb = Ts + N;
+    double* Tm = Tb + N;
+    const double* xi = t.xi + U.off_xi;
+    darcy_transmissibilities(t, D, xi, Ksc, Tf, Ts, Tb, Tm);
+
+    double* L = Lscr + U.off_L;
+    double* Xu = X + U.off_X;
+    const int tid = threadIdx.x;
+    // initial window: columns / rows 0 .. b
+    for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
+        const int col = idx / bw, d = idx - col * bw;
+        band[col * bw + d] = band_entry(Tf, Ts, Tb, col, d, b, N);
+    }
+    for (int idx = tid; idx < (b + 1) * R; idx += blockDim.x) {
+        const int row = idx / R, r = idx - row * R;
+        rhs[row * R + r] = rhs_entry(t, D, Tm, row, r);
+    }
+    __syncthreads();
+    int sj = 0;  // slot of column j
+    for (int j = 0; j < N; ++j) {
+        const double* colj = band + sj * bw;
+        const double dj = colj[0];
+        const double dinv = 1.0 / dj;
+        const double rinv = rsqrt(dj);
+        // rank-1 update of the trailing window: A[j+i, j+m] -= a_i a_m / d
+        for (int idx = tid; idx < b * b; idx += blockDim.x) {
+            const int m = 1 + idx / b, i = 1 + idx - (m - 1) * b;
+            if (m > i) continue;
+            int sm_ = sj + m;
+            if (sm_ >= nslot) sm_ -= nslot;
+            band[sm_ * bw + (i - m)] -= colj[i] * colj[m] * dinv;
+        }
+        // forward substitution of the right-hand sides
+        const double* rj = rhs + sj * R;
+        for (int idx = tid; idx < b * R; idx += blockDim.x) {
+            const int i = 1 + idx / R, r = idx - (i - 1) * R;
+            int si = sj + i;
+            if (si >= nslot) si -= nslot;
+            rhs[si * R + r] -= colj[i] * rj[r] * dinv;
+        }
+        // outputs: column j of L and row j of W = L^{-1} E
+        for (int d = tid; d < bw; d += blockDim.x) L[(int64_t)j * bw + d] = (d == 0) ? dj * rinv : colj[d] * rinv;
+        for (int r = tid; r < R; r += blockDim.x) Xu[(int64_t)j * R + r] = rj[r] * rinv;
+        // load column / row j + b + 1 into the free slot
+        int sn = sj + b + 1;
+        if (sn >= nslot) sn -= nslot;
+        for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = band_entry(Tf, Ts, Tb, j + b + 1, d, b, N);
+        for (int r = tid; r < R; r += blockDim.x) rhs[sn * R + r] = rhs_entry(t, D, Tm, j + b + 1, r);
+        __syncthreads();
+        sj = (sj + 1 == nslot) ? 0 : sj + 1;
+    }
+    // backward sweep: X = L^{-T} W, columns of L from the scratch
+    {
+        // window holds columns / rows N-1-b .. N-1 at slot col mod nslot
+        for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
+            const int q = idx / bw, d = idx - q * bw;
+            const int col = N - 1 - q;
+            if (col >= 0) band[(col % nslot) * bw + d] = L[(int64_t)col * bw + d];
+        }
+        for (int idx = tid; idx < (b + 1) * R; idx += blockDim.x) {
+            const int q = idx / R, r = idx - q * R;
+            const int row = N - 1 - q;
+            if (row >= 0) rhs[(row % nslot) * R + r] = Xu[(int64_t)row * R + r];
+        }
+        __syncthreads();
+        for (int j = N - 1; j >= 0; --j) {
+            const int s = j % nslot;
+            const double linv = 1.0 / band[s * bw];
+            for (int idx = tid; idx < b * R; idx += blockDim.x) {
+                const int i = 1 + idx / R, r = idx - (i - 1) * R;
+                const int row = j - i;
+                if (row < 0) continue;
+                const int sr = row % nslot;
+                rhs[sr * R + r] -= band[sr * bw + i] * rhs[s * R + r] * linv;
+            }
+            for (int r = tid; r < R; r += blockDim.x) Xu[(int64_t)j * R + r] = rhs[s * R + r] * linv;
+            const int col = j - b - 1;
+            if (col >= 0) {
+                const int sn = col % nslot;
+                for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = L[(int64_t)col * bw + d];
+                for (int r = tid; r < R; r += blockDim.x) rhs[sn * R + r] = Xu[(int64_t)col * R + r];
+            }
+            __syncthreads();
+        }
+    }
+    // flux basis: S[m, jj] = sum_{e in supp(m)} Pi[e, m] T_e (Pi[e, jj] - X[cell(e), jj])
+    double* S = S_cache + U.off_S;
+    const int* sp = t.supp_ptr + D.off_supp;
+    const double* Pi = t.Pi + D.off_Pi;
+    const int* mec = t.me_cell + D.off_me;
+    for (int o = tid; o < R * R; o += blockDim.x) {
+        const int m = o % R, jj = o / R;
+        double s = 0.0;
+        for (int q = sp[m]; q < sp[m + 1]; ++q) {
+            const int e = t.supp_e[q];
+            s += t.supp_v[q] * Tm[e] * (Pi[(int64_t)e * R + jj] - Xu[(int64_t)mec[e] * R + jj]);
+        }
+        S[(int64_t)jj * R + m] = s;
+    }
+}
+
+hipError_t launch_darcy_basis_fp64(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
+                                   double* X, double* Lscr, double* Tscr, hipStream_t stream) {
+    if (n_units <= 0) return hipSuccess;
+    const size_t lds = (size_t)(max_b + 2) * (max_b + 1 + max_R) * sizeof(double);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(darcy_basis_fp64_kernel, dim3(n_units), dim3(kThreads), lds, stream, t, S_cache, X, Lscr, Tscr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Darcy basis, mixed precision: FP32 band factor and FP32 triangular sweeps,
+// FP64 residuals r = E - P X on the 5-point operator, corrections solved with
+// the FP32 factor until max|r| <= tol max|E| (or max_refine sweeps); S and X
+// in FP64.
+// ---------------------------------------------------------------------------
+__device__ void sweep_solve_fp32(const DarcyDev& D, const float* __restrict__ L, float* __restrict__ W,
+                                 float* band, float* rhs) {
+    // in-place solve L L^T y = W (W: N x R, internal order) with L in FP32 scratch
+    const int N = D.N, b = D.b, R = D.R, nslot = b + 2, bw = b + 1;
+    const int tid = threadIdx.x;
+    // forward: y = L^{-1} W, window of L columns j .. j + b
+    for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
+        const int col = idx / bw, d = idx - col * bw;
+        band[col * bw + d] = col < N ? L[(int64_t)col * bw + d] : 0.0f;
+    }
+    for (int idx = tid; idx < (b + 1) * R; idx += blockDim.x) {
+        const int row = idx / R, r = idx - row * R;
+        rhs[row * R + r] = row < N ? W[(int64_t)row * R + r] : 0.0f;
+    }
+    __syncthreads();
+    int sj = 0;
+    for (int j = 0; j < N; ++j) {
+        const float* colj = band + sj * bw;
+        const float linv = 1.0f / colj[0];
+        const float* rj = rhs + sj * R;
+        for (int idx = tid; idx < b * R; idx += blockDim.x) {
+            const int i = 1 + idx / R, r = idx - (i - 1) * R;
+            int si = sj + i;
+            if (si >= nslot) si -= nslot;
+            rhs[si * R + r] -= colj[i] * rj[r] * linv;
+        }
+        for (int r = tid; r < R; r += blockDim.x) W[(int64_t)j * R + r] = rj[r] * linv;
+        int sn = sj + b + 1;
+        if (sn >= nslot) sn -= nslot;
+        const int col = j + b + 1;
+        for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = col < N ? L[(int64_t)col * bw + d] : 0.0f;
+        for (int r = tid; r < R; r += blockDim.x) rhs[sn * R + r] = col < N ? W[(int64_t)col * R + r] : 0.0f;
+        __syncthreads();
+        sj = (sj + 1 == nslot) ? 0 : sj + 1;
+    }
+    // backward
+    for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
+        const int q = idx / bw, d = idx - q * bw;
+        const int col = N - 1 - q;
+        if (col >= 0) band[(col % nslot) * bw + d] = L[(int64_t)col * bw + d];
+    }
+    for (int idx = tid; idx < (b + 1) * R; idx += blockDim.x) {
+        const int q = idx / R, r = idx - q * R;
+        const int row = N - 1 - q;
+        if (row >= 0) rhs[(row % nslot) * R + r] = W[(int64_t)row * R + r];
+    }
+    __syncthreads();
+    for (int j = N - 1; j >= 0; --j) {
+        const int s = j % nslot;
+        const float linv = 1.0f / band[s * bw];
+        for (int idx = tid; idx < b * R; idx += blockDim.x) {
+            const int i = 1 + idx / R, r = idx - (i - 1) * R;
+            const int row = j - i;
+            if (row < 0) continue;
+            const int sr = row % nslot;
+            rhs[sr * R + r] -= band[sr * bw + i] * rhs[s * R + r] * linv;
+        }
+        for (int r = tid; r < R; r += blockDim.x) W[(int64_t)j * R + r] = rhs[s * R + r] * linv;
+        const int col = j - b - 1;
+        if (col >= 0) {
+            const int sn = col % nslot;
+            for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = L[(int64_t)col * bw + d];
+            for (int r = tid; r < R; r += blockDim.x) rhs[sn * R + r] = W[(int64_t)col * R + r];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void darcy_basis_mixed_kernel(DarcyTables t, double* __restrict__ S_cache,
+                                                                     double* __restrict__ X, float* __restrict__ L32,
+                                                                     double* __restrict__ Tscr, float* __restrict__ W32,
+                                                                     int max_refine, double tol, double* max_res,
+                                                                     int* steps) {
+    extern __shared__ double smd[];
+    float* sm = reinterpret_cast<float*>(smd);
+    __shared__ double red[kThreads / 64];
+    const UnitDev U = t.units[blockIdx.x];
+    const DarcyDev D = t.dar[U.d];
+    const int N = D.N, b = D.b, R = D.R;
+    const int nslot = b + 2, bw = b + 1;
+    float* band = sm;
+    float* rhs = band + nslot * bw;
+    double* Ksc = Tscr + U.off_T;
+    double* Tf = Ksc + N;
+    double* Ts = Tf + N;
+    double* Tb = Ts + N;
+    double* Tm = Tb + N;
+    const double* xi = t.xi + U.off_xi;
+    darcy_transmissibilities(t, D, xi, Ksc, Tf, Ts, Tb, Tm);
+    float* L = L32 + U.off_L;
+    float* W = W32 + U.off_X;
+    double* Xu = X + U.off_X;
+    const int tid = threadIdx.x;
+    // FP32 factorisation (no right-hand sides in the window)
+    for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
+        const int col = idx / bw, d = idx - col * bw;
+        band[col * bw + d] = (float)band_entry(Tf, Ts, Tb, col, d, b, N);
+    }
+    __syncthreads();
+    int sj = 0;
+    for (int j = 0; j < N; ++j) {
+        const float* colj = band + sj * bw;
+        const float dj = colj[0];
+        const float dinv = 1.0f / dj;
+        const float rinv = rsqrtf(dj);
+        for (int idx = tid; idx < b * b; idx += blockDim.x) {
+            const int m = 1 + idx / b, i = 1 + idx - (m - 1) * b;
+            if (m > i) continue;
+            int sm_ = sj + m;
+            if (sm_ >= nslot) sm_ -= nslot;
+            band[sm_ * bw + (i - m)] -= colj[i] * colj[m] * dinv;
+        }
+        for (int d = tid; d < bw; d += blockDim.x) L[(int64_t)j * bw + d] = (d == 0) ? dj * rinv : colj[d] * rinv;
+        int sn = sj + b + 1;
+        if (sn >= nslot) sn -= nslot;
+        for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = (float)band_entry(Tf, Ts, Tb, j + b + 1, d, b, N);
+        __syncthreads();
+        sj = (sj + 1 == nslot) ? 0 : sj + 1;
+    }
+    // X = 0; residual r = E - P X in FP64; W = (float) r; solve; X += W
+    double emax = 0.0;
+    for (int idx = tid; idx < N * R; idx += blockDim.x) {
+        const int row = idx / R, r = idx - row * R;
+        const double e = rhs_entry(t, D, Tm, row, r);
+        Xu[idx] = 0.0;
+        W[idx] = (float)e;
+        emax = fmax(emax, fabs(e));
+    }
+    // block max through the sum helper on a one-hot scheme: use a max reduction
+    {
+        double v = emax;
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        emax = 0.0;
+        for (int k = 0; k < kThreads / 64; ++k) emax = fmax(emax, red[k]);
+        __syncthreads();
+    }
+    int it = 0;
+    double rmax = emax;
+    while (true) {
+        sweep_solve_fp32(D, L, W, band, rhs);
+        // X += W; residual in FP64
+        for (int idx = tid; idx < N * R; idx += blockDim.x) Xu[idx] += (double)W[idx];
+        __syncthreads();
+        ++it;
+        double lmax = 0.0;
+        for (int idx = tid; idx < N * R; idx += blockDim.x) {
+            const int c = idx / R, r = idx - c * R;
+            double v = rhs_entry(t, D, Tm, c, r);
+            double diag = Tf[c] + Ts[c] + Tb[c];
+            if (c % b) diag += Tf[c - 1];
+            if (c >= b) diag += Ts[c - b];
+            v -= diag * Xu[idx];
+            if ((c % b) != b - 1) v += Tf[c] * Xu[idx + R];
+            if (c % b) v += Tf[c - 1] * Xu[idx - R];
+            if (c + b < N) v += Ts[c] * Xu[idx + (int64_t)b * R];
+            if (c >= b) v += Ts[c - b] * Xu[idx - (int64_t)b * R];
+            W[idx] = (float)v;
+            lmax = fmax(lmax, fabs(v));
+        }
+        double v = lmax;
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        rmax = 0.0;
+        for (int k = 0; k < kThreads / 64; ++k) rmax = fmax(rmax, red[k]);
+        __syncthreads();
+        if (rmax <= tol * emax || it > max_refine) break;
+    }
+    if (tid == 0) {
+        atomicAdd(steps, it - 1);
+        const double rel = emax > 0 ? rmax / emax : 0.0;
+        // non-negative doubles order like their bit patterns
+        atomicMax(reinterpret_cast<unsigned long long*>(max_res), (unsigned long long)__double_as_longlong(rel));
+    }
+    double* S = S_cache + U.off_S;
+    const int* sp = t.supp_ptr + D.off_supp;
+    const double* Pi = t.Pi + D.off_Pi;
+    const int* mec = t.me_cell + D.off_me;
+    for (int o = tid; o < R * R; o += blockDim.x) {
+        const int m = o % R, jj = o / R;
+        double s = 0.0;
+        for (int q = sp[m]; q < sp[m + 1]; ++q) {
+            const int e = t.supp_e[q];
+            s += t.supp_v[q] * Tm[e] * (Pi[(int64_t)e * R + jj] - Xu[(int64_t)mec[e] * R + jj]);
+        }
+        S[(int64_t)jj * R + m] = s;
+    }
+}
+
+hipError_t launch_darcy_basis_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
+                                    double* X, float* Lscr32, double* Tscr, float* W32, double* /*Rres*/,
+                                    int max_refine, double refine_tol, double* max_res, int* steps,
+                                    hipStream_t stream) {
+    if (n_units <= 0) return hipSuccess;
+    const size_t lds = (size_t)(max_b + 2) * (max_b + 1 + max_R) * sizeof(float);
+    if (lds > 150 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(darcy_basis_mixed_kernel, dim3(n_units), dim3(kThreads), lds, stream, t, S_cache, X, Lscr32,
+                       Tscr, W32, max_refine, refine_tol, max_res, steps);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stokes: tiled band LDL^T.  Block column J holds tiles I = J .. J + w, each
+// 64 x 64 column-major; tile (I, J) at off_tiles + (J (w+1) + I - J) 4096.
+// ---------------------------------------------------------------------------
+__device__ inline double* tile_ptr(double* base, const StokesDev& s, int I, int J) {
+    return base + s.off_tiles + ((int64_t)J * (s.w + 1) + (I - J)) * (kTile * kTile);
+}
+__device__ inline const double* tile_ptr(const double* base, const StokesDev& s, int I, int J) {
+    return base + s.off_tiles + ((int64_t)J * (s.w + 1) + (I - J)) * (kTile * kTile);
+}
+
+__global__ void stokes_scatter_kernel(const StokesDev* sd, const int* tr_sub, const int* tr_r, const int* tr_c,
+                                      const double* tr_v, int64_t ntrip, double* tiles) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ntrip) return;
+    const StokesDev s = sd[tr_sub[q]];
+    const int r = tr_r[q], c = tr_c[q];
+    const int I = r / kTile, J = c / kTile;
+    double* T = tile_ptr(tiles, s, I, J);
+    T[(c % kTile) * kTile + (r % kTile)] = tr_v[q];
+}
+
+__global__ void stokes_pad_kernel(const StokesDev* sd, double* tiles) {
+    const StokesDev s = sd[blockIdx.y];
+    const int J = blockIdx.x;
+    if (J >= s.nblk) return;
+    for (int d = threadIdx.x; d < kTile; d += blockDim.x) {
+        const int row = J * kTile + d;
+        if (row >= s.nband) tile_ptr(tiles, s, J, J)[d * kTile + d] = 1.0;
+    }
+}
+
+hipError_t launch_stokes_scatter(const StokesDev* sd, int ns, const int* tr_sub, const int* tr_r, const int* tr_c,
+                                 const double* tr_v, int64_t ntrip, double* tiles, hipStream_t stream) {
+    if (ntrip <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stokes_scatter_kernel, dim3((unsigned)((ntrip + 255) / 256)), dim3(256), 0, stream, sd, tr_sub,
+                       tr_r, tr_c, tr_v, ntrip, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_stokes_pad_identity(const StokesDev* sd, int ns, int max_nblk, double* tiles, hipStream_t stream) {
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stokes_pad_kernel, dim3(max_nblk, ns), dim3(64), 0, stream, sd, tiles);
+    return hipGetLastError();
+}
+
+// Factor the diagonal tile of block column J: A = L D L^T in place (D on the
+// diagonal, unit L strictly below).
+__global__ __launch_bounds__(kThreads) void stokes_ldl_diag_kernel(const StokesDev* sd, int J, double* tiles) {
+    __shared__ double A[kTile * (kTile + 1)];
+    const StokesDev s = sd[blockIdx.x];
+    if (J >= s.nblk) return;
+    double* T = tile_ptr(tiles, s, J, J);
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
+        const int c = idx / kTile, r = idx % kTile;
+        A[c * (kTile + 1) + r] = T[idx];
+    }
+    __syncthreads();
+    for (int c = 0; c < kTile; ++c) {
+        const double d = A[c * (kTile + 1) + c];
+        const double dinv = 1.0 / d;
+        // trailing update with the unscaled column: A[r][k] -= A[r][c] A[k][c] / d
+        for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
+            const int k = idx / kTile, r = idx % kTile;
+            if (k <= c || r < k) continue;
+            A[k * (kTile + 1) + r] -= A[c * (kTile + 1) + r] * A[c * (kTile + 1) + k] * dinv;
+        }
+        __syncthreads();
+        for (int r = c + 1 + tid; r < kTile; r += blockDim.x) A[c * (kTile + 1) + r] *= dinv;
+        __syncthreads();
+    }
+    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
+        const int c = idx / kTile, r = idx % kTile;
+        T[idx] = r >= c ? A[c * (kTile + 1) + r] : 0.0;
+    }
+}
+
+// Panel: L(I, J) = A(I, J) L(J, J)^{-T} D^{-1} for I = J+1 .. J+w.
+__global__ __launch_bounds__(kThreads) void stokes_ldl_panel_kernel(const StokesDev* sd, int J, double* tiles) {
+    __shared__ double Ld[kTile * (kTile + 1)];
+    __shared__ double B[kTile * (kTile + 1)];
+    const StokesDev s = sd[blockIdx.y];
+    const int I = J + 1 + blockIdx.x;
+    if (J >= s.nblk || blockIdx.x >= s.w || I >= s.nblk) return;
+    const double* Td = tile_ptr(tiles, s, J, J);
+    double* T = tile_ptr(tiles, s, I, J);
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
+        const int c = idx / kTile, r = idx % kTile;
+        Ld[c * (kTile + 1) + r] = Td[idx];
+        B[c * (kTile + 1) + r] = T[idx];
+    }
+    __syncthreads();
+    // each row r: Y[r][c] = B[r][c] - sum_{k<c} Y[r][k] L[c][k]; then / D[c]
+    if (tid < kTile) {
+        const int r = tid;
+        for (int c = 0; c < kTile; ++c) {
+            double v = B[c * (kTile + 1) + r];
+            for (int k = 0; k < c; ++k) v -= B[k * (kTile + 1) + r] * Ld[k * (kTile + 1) + c];
+            B[c * (kTile + 1) + r] = v;  // Y = L(I,J) D
+        }
+        for (int c = 0; c < kTile; ++c) B[c * (kTile + 1) + r] /= Ld[c * (kTile + 1) + c];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
+        const int c = idx / kTile, r = idx % kTile;
+        T[idx] = B[c * (kTile + 1) + r];
+    }
+}
+
+// Trailing update: A(I, K) -= L(I, J) D_J L(K, J)^T for J < K <= I <= J + w.
+__global__ __launch_bounds__(kThreads) void stokes_ldl_update_kernel(const StokesDev* sd, int J, double* tiles) {
+    __shared__ double LI[kTile * (kTile + 1)];
+    __shared__ double LK[kTile * (kTile + 1)];
+    __shared__ double Dd[kTile];
+    const StokesDev s = sd[blockIdx.y];
+    if (J >= s.nblk) return;
+    // decode the pair index p -> (a, c) with 1 <= c <= a <= w
+    int p = blockIdx.x, a = 1;
+    while (p >= a) {
+        p -= a;
+        ++a;
+    }
+    const int c = p + 1;
+    if (a > s.w) return;
+    const int I = J + a, K = J + c;
+    if (I >= s.nblk) return;
+    const double* TI = tile_ptr(tiles, s, I, J);
+    const double* TK = tile_ptr(tiles, s, K, J);
+    const double* Td = tile_ptr(tiles, s, J, J);
+    double* Tt = tile_ptr(tiles, s, I, K);
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
+        const int cc = idx / kTile, r = idx % kTile;
+        LI[cc * (kTile + 1) + r] = TI[idx];
+        LK[cc * (kTile + 1) + r] = TK[idx];
+    }
+    if (tid < kTile) Dd[tid] = Td[tid * kTile + tid];
+    __syncthreads();
+    // thread computes a 4 x 4 block of the 64 x 64 target
+    const int br = (tid % 16) * 4, bc = (tid / 16) * 4;
+    double acc[4][4] = {};
+    for (int k = 0; k < kTile; ++k) {
+        const double dk = Dd[k];
+        double li[4], lk[4];
+        for (int q = 0; q < 4; ++q) {
+            li[q] = LI[k * (kTile + 1) + br + q] * dk;
+            lk[q] = LK[k * (kTile + 1) + bc + q];
+        }
+        for (int x = 0; x < 4; ++x)
+            for (int y = 0; y < 4; ++y) acc[x][y] += li[x] * lk[y];
+    }
+    for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y) {
+            const int r = br + x, cc = bc + y;
+            if (I == K && r < cc) continue;
+            Tt[cc * kTile + r] -= acc[x][y];
+        }
+}
+
+hipError_t launch_stokes_ldl_step(const StokesDev* sd, int ns, int J, int max_w, double* tiles, hipStream_t stream) {
+    hipLaunchKernelGGL(stokes_ldl_diag_kernel, dim3(ns), dim3(kThreads), 0, stream, sd, J, tiles);
+    if (max_w > 0) {
+        hipLaunchKernelGGL(stokes_ldl_panel_kernel, dim3(max_w, ns), dim3(kThreads), 0, stream, sd, J, tiles);
+        hipLaunchKernelGGL(stokes_ldl_update_kernel, dim3(max_w * (max_w + 1) / 2, ns), dim3(kThreads), 0, stream, sd,
+                           J, tiles);
+    }
+    return hipGetLastError();
+}
+
+// Solves: forward L y = f, y /= D, backward L^T x = y, on 64-column chunks.
+__global__ __launch_bounds__(kThreads) void stokes_fwd_diag_kernel(const StokesDev* sd, int J, const double* tiles,
+                                                                   double* rhs) {
+    __shared__ double Ld[kTile * (kTile + 1)];
+    const StokesDev s = sd[blockIdx.y];
+    const int c0 = blockIdx.x * kTile;
+    if (J >= s.nblk || c0 >= s.ncol) return;
+    const double* Td = tile_ptr(tiles, s, J, J);
+    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x)
+        Ld[(idx / kTile) * (kTile + 1) + idx % kTile] = Td[idx];
+    __syncthreads();
+    const int col = c0 + threadIdx.x;
+    if (threadIdx.x < kTile && col < s.ncol) {
+        const int64_t ld = (int64_t)s.nblk * kTile;
+        double* x = rhs + s.off_rhs + (int64_t)col * ld + (int64_t)J * kTile;
+        double v[kTile];
+        for (int r = 0; r < kTile; ++r) v[r] = x[r];
+        for (int k = 0; k < kTile; ++k)
+            for (int r = k + 1; r < kTile; ++r) v[r] -= Ld[k * (kTile + 1) + r] * v[k];
+        for (int r = 0; r < kTile; ++r) x[r] = v[r];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void stokes_fwd_update_kernel(const StokesDev* sd, int J, const double* tiles,
+                                                                     double* rhs) {
+    // X(I) -= L(I, J) X(J), I = J + 1 + blockIdx.x, 64 columns from blockIdx.z
+    __shared__ double Lt[kTile * (kTile + 1)];
+    __shared__ double Xj[kTile * (kTile + 1)];
+    const StokesDev s = sd[blockIdx.y];
+    const int I = J + 1 + blockIdx.x;
+    const int c0 = blockIdx.z * kTile;
+    if (J >= s.nblk || blockIdx.x >= s.w || I >= s.nblk || c0 >= s.ncol) return;
+    const int64_t ld = (int64_t)s.nblk * kTile;
+    const double* T = tile_ptr(tiles, s, I, J);
+    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
+        const int c = idx / kTile, r = idx % kTile;
+        Lt[c * (kTile + 1) + r] = T[idx];
+        Xj[c * (kTile + 1) + r] = (c0 + c < s.ncol) ? rhs[s.off_rhs + (int64_t)(c0 + c) * ld + (int64_t)J * kTile + r] : 0.0;
+    }
+    __syncthreads();
+    const int br = (threadIdx.x % 16) * 4, bc = (threadIdx.x / 16) * 4;
+    double acc[4][4] = {};
+    for (int k = 0; k < kTile; ++k) {
+        double l[4], x[4];
+        for (int q = 0; q < 4; ++q) {
+            l[q] = Lt[k * (kTile + 1) + br + q];
+            x[q] = Xj[(bc + q) * (kTile + 1) + k];
+        }
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) acc[a][b] += l[a] * x[b];
+    }
+    for (int b = 0; b < 4; ++b) {
+        const int col = c0 + bc + b;
+        if (col >= s.ncol) continue;
+        double* xi = rhs + s.off_rhs + (int64_t)col * ld + (int64_t)I * kTile;
+        for (int a = 0; a < 4; ++a) xi[br + a] -= acc[a][b];
+    }
+}
+
+__global__ void stokes_dscale_kernel(const StokesDev* sd, const double* tiles, double* rhs) {
+    const StokesDev s = sd[blockIdx.z];
+    const int64_t ld = (int64_t)s.nblk * kTile;
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int col = blockIdx.y;
+    if (row >= ld || col >= s.ncol) return;
+    const int J = (int)(row / kTile), d = (int)(row % kTile);
+    const double D = tile_ptr(tiles, s, J, J)[d * kTile + d];
+    rhs[s.off_rhs + (int64_t)col * ld + row] /= D;
+}
+
+__global__ __launch_bounds__(kThreads) void stokes_bwd_kernel(const StokesDev* sd, int J, const double* tiles,
+                                                              double* rhs) {
+    // X(J) -= sum_{I = J+1 .. J+w} L(I, J)^T X(I); then X(J) = L(J, J)^{-T} X(J)
+    __shared__ double Lt[kTile * (kTile + 1)];
+    __shared__ double Xi[kTile * (kTile + 1)];
+    const StokesDev s = sd[blockIdx.y];
+    const int c0 = blockIdx.x * kTile;
+    if (J >= s.nblk || c0 >= s.ncol) return;
+    const int64_t ld = (int64_t)s.nblk * kTile;
+    const int br = (threadIdx.x % 16) * 4, bc = (threadIdx.x / 16) * 4;
+    double acc[4][4] = {};
+    for (int a = 1; a <= s.w; ++a) {
+        const int I = J + a;
+        if (I >= s.nblk) break;
+        const double* T = tile_ptr(tiles, s, I, J);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
+            const int c = idx / kTile, r = idx % kTile;
+            Lt[c * (kTile + 1) + r] = T[idx];
+            Xi[c * (kTile + 1) + r] = (c0 + c < s.ncol) ? rhs[s.off_rhs + (int64_t)(c0 + c) * ld + (int64_t)I * kTile + r] : 0.0;
+        }
+        __syncthreads();
+        // out[r][col] += sum_k L(I,J)[k][r] X(I)[k][col]
+        for (int k = 0; k < kTile; ++k) {
+            double l[4], x[4];
+            for (int q = 0; q < 4; ++q) {
+                l[q] = Lt[(br + q) * (kTile + 1) + k];
+                x[q] = Xi[(bc + q) * (kTile + 1) + k];
+            }
+            for (int x1 = 0; x1 < 4; ++x1)
+                for (int y1 = 0; y1 < 4; ++y1) acc[x1][y1] += l[x1] * x[y1];
+        }
+    }
+    __syncthreads();
+    // gather X(J) - acc into Xi (reuse), then triangular solve with L(J,J)^T
+    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
+        const int c = idx / kTile, r = idx % kTile;
+        Xi[c * (kTile + 1) + r] = (c0 + c < s.ncol) ? rhs[s.off_rhs + (int64_t)(c0 + c) * ld + (int64_t)J * kTile + r] : 0.0;
+    }
+    const double* Td = tile_ptr(tiles, s, J, J);
+    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x)
+        Lt[(idx / kTile) * (kTile + 1) + idx % kTile] = Td[idx];
+    __syncthreads();
+    for (int x1 = 0; x1 < 4; ++x1)
+        for (int y1 = 0; y1 < 4; ++y1) Xi[(bc + y1) * (kTile + 1) + br + x1] -= acc[x1][y1];
+    __syncthreads();
+    const int col = c0 + threadIdx.x;
+    if (threadIdx.x < kTile && col < s.ncol) {
+        double v[kTile];
+        for (int r = 0; r < kTile; ++r) v[r] = Xi[threadIdx.x * (kTile + 1) + r];
+        for (int r = kTile - 1; r >= 0; --r)
+            for (int k = r + 1; k < kTile; ++k) v[r] -= Lt[r * (kTile + 1) + k] * v[k];
+        double* x = rhs + s.off_rhs + (int64_t)col * ld + (int64_t)J * kTile;
+        for (int r = 0; r < kTile; ++r) x[r] = v[r];
+    }
+}
+
+hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol, const double* tiles,
+                               double* rhs, hipStream_t stream) {
+    const int nchunk = (max_ncol + kTile - 1) / kTile;
+    for (int J = 0; J < max_nblk; ++J) {
+        hipLaunchKernelGGL(stokes_fwd_diag_kernel, dim3(nchunk, ns), dim3(kThreads), 0, stream, sd, J, tiles, rhs);
+        if (max_w > 0)
+            hipLaunchKernelGGL(stokes_fwd_update_kernel, dim3(max_w, ns, nchunk), dim3(kThreads), 0, stream, sd, J,
+                               tiles, rhs);
+    }
+    hipLaunchKernelGGL(stokes_dscale_kernel, dim3((max_nblk * kTile + 255) / 256, max_ncol, ns), dim3(256), 0, stream,
+                       sd, tiles, rhs);
+    for (int J = max_nblk - 1; J >= 0; --J)
+        hipLaunchKernelGGL(stokes_bwd_kernel, dim3(nchunk, ns), dim3(kThreads), 0, stream, sd, J, tiles, rhs);
+    return hipGetLastError();
+}
+
+// Scatter the band solutions to raw velocity / pressure layouts, project the
+// floating subdomains' responses onto the complement of the rigid motions,
+// then S = -Q U (basis columns), g += Q u_bar and the FETI traces G = Q Z.
+__global__ __launch_bounds__(kThreads) void stokes_fill_kernel(const StokesDev* sd, const double* uD,
+                                                               const int64_t* uD_off, double* U) {
+    // velocity defaults: Dirichlet values for the complementary column, 0 otherwise
+    const StokesDev s = sd[blockIdx.z];
+    const int col = blockIdx.y;
+    if (col >= s.ncol) return;
+    double* Uc = U + s.off_U + (int64_t)col * s.nvel;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < s.nvel; q += (int64_t)gridDim.x * blockDim.x)
+        Uc[q] = (col == s.R) ? uD[uD_off[blockIdx.z] + q] : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void stokes_unpack_kernel(const StokesDev* sd, const double* rhs,
+                                                                 const int* bmap, double* U, double* P) {
+    const StokesDev s = sd[blockIdx.z];
+    const int col = blockIdx.y;
+    if (col >= s.ncol) return;
+    const int64_t ld = (int64_t)s.nblk * kTile;
+    double* Uc = U + s.off_U + (int64_t)col * s.nvel;
+    double* Pc = P + s.off_P + (int64_t)col * s.npre;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < s.nband; q += (int64_t)gridDim.x * blockDim.x) {
+        const int m = bmap[s.off_map + q];
+        const double v = rhs[s.off_rhs + (int64_t)col * ld + q];
+        if (m >= 0) Uc[m] = v;
+        else Pc[-1 - m] = v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void stokes_project_kernel(const StokesDev* sd, const double* Z, double* U) {
+    __shared__ double red[kThreads / 64];
+    const StokesDev s = sd[blockIdx.y];
+    const int col = blockIdx.x;
+    if (col >= s.ncol || s.nker == 0) return;
+    double* Uc = U + s.off_U + (int64_t)col * s.nvel;
+    for (int k = 0; k < s.nker; ++k) {
+        const double* z = Z + s.off_Z + (int64_t)k * s.nvel;
+        double part = 0.0;
+        for (int q = threadIdx.x; q < s.nvel; q += blockDim.x) part += z[q] * Uc[q];
+        const double dot = block_sum(part, red);
+        for (int q = threadIdx.x; q < s.nvel; q += blockDim.x) Uc[q] -= dot * z[q];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void stokes_traces_kernel(const StokesDev* sd, const int* q_ptr, const int* q_col,
+                                                                 const double* q_val, const int64_t* dofs,
+                                                                 const double* U, const double* Z, double* S_cache,
+                                                                 double* g, double* G, int M) {
+    const StokesDev s = sd[blockIdx.y];
+    const int col = blockIdx.x;   // 0..R-1 basis, R complementary, R+1.. kernel columns
+    if (col >= s.ncol + s.nker) return;
+    const int* qp = q_ptr + s.off_q;
+    for (int m = threadIdx.x; m < s.R; m += blockDim.x) {
+        const double* u = (col < s.ncol) ? U + s.off_U + (int64_t)col * s.nvel : Z + s.off_Z + (int64_t)(col - s.ncol) * s.nvel;
+        double v = 0.0;
+        for (int q = qp[m]; q < qp[m + 1]; ++q) v += q_val[q] * u[q_col[q]];
+        const int64_t gd = dofs[s.off_dofs + m];
+        if (col < s.R) S_cache[s.off_S + (int64_t)col * s.R + m] = -v;
+        else if (col == s.R) atomicAdd(&g[gd], v);
+        else G[(int64_t)(s.off_G + col - s.ncol) * M + gd] = v;
+    }
+}
+
+hipError_t launch_stokes_finish(const StokesDev* sd, int ns, int max_ncol, int max_R, const double* rhs, const int* bmap,
+                                const double* uD, const int64_t* uD_off, const double* Z, const int* q_ptr,
+                                const int* q_col, const double* q_val, const int64_t* dofs, double* U, double* P,
+                                double* S_cache, double* g, double* G, int M, hipStream_t stream) {
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stokes_fill_kernel, dim3(64, max_ncol, ns), dim3(kThreads), 0, stream, sd, uD, uD_off, U);
+    hipLaunchKernelGGL(stokes_unpack_kernel, dim3(64, max_ncol, ns), dim3(kThreads), 0, stream, sd, rhs, bmap, U, P);
+    hipLaunchKernelGGL(stokes_project_kernel, dim3(max_ncol, ns), dim3(kThreads), 0, stream, sd, Z, U);
+    hipLaunchKernelGGL(stokes_traces_kernel, dim3(max_ncol + 8, ns), dim3(kThreads), 0, stream, sd, q_ptr, q_col, q_val,
+                       dofs, U, Z, S_cache, g, G, M);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched interface CG.  One workgroup per realization for the vector work;
+// the operator y = sum_i R_i^T S_i^{(k_i(l))} R_i x is applied by one
+// workgroup per (realization, subdomain).  Every mortar DOF receives exactly
+// two contributions on a zeroed vector, so the atomic adds are order
+// independent and results are bit-reproducible for any batch composition.
+// ---------------------------------------------------------------------------
+__device__ void feti_project_row(const CgArgs& a, double* v, double* red, double* coef) {
+    // v <- v - G (G^T G)^{-1} G^T v   (coef: scratch of 2 nker doubles in LDS)
+    const int nk = a.nker;
+    for (int k = 0; k < nk; ++k) {
+        double part = 0.0;
+        for (int m = threadIdx.x; m < a.M; m += blockDim.x) part += a.G[(int64_t)k * a.M + m] * v[m];
+        const double s = block_sum(part, red);
+        if (threadIdx.x == 0) coef[k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < nk; ++k) {
+            double d = 0.0;
+            for (int q = 0; q < nk; ++q) d += a.GtGinv[k * nk + q] * coef[q];
+            coef[nk + k] = d;
+        }
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
+        double c = 0.0;
+        for (int k = 0; k < nk; ++k) c += a.G[(int64_t)k * a.M + m] * coef[nk + k];
+        v[m] -= c;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
+    __shared__ double red[kThreads / 64];
+    __shared__ double coef[32];
+    const int64_t l = blockIdx.x;
+    double* r = a.r + l * a.M;
+    double* p = a.p + l * a.M;
+    double* lam = a.lam + l * a.M;
+    double* Ap = a.Ap + l * a.M;
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
+        r[m] = a.g[m];
+        lam[m] = 0.0;
+        Ap[m] = 0.0;
+    }
+    __syncthreads();
+    if (a.nker > 0) feti_project_row(a, r, red, coef);
+    double part = 0.0;
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
+        p[m] = r[m];
+        part += r[m] * r[m];
+    }
+    const double rr = block_sum(part, red);
+    if (threadIdx.x == 0) {
+        a.rr[l] = rr;
+        a.r0[l] = sqrt(rr);
+        a.iters[l] = 0;
+        a.relres[l] = rr > 0 ? 1.0 : 0.0;
+        a.status[l] = rr > 0 ? SDMM_CG_MAXITER : SDMM_CG_CONVERGED;
+        a.active[l] = rr > 0 ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void cg_apply_kernel(CgArgs a, const double* __restrict__ x, double* __restrict__ y,
+                                                            int masked) {
+    extern __shared__ double xs[];
+    const int64_t l = blockIdx.x;
+    const int i = blockIdx.y;
+    if (masked && !a.active[l]) return;
+    const int R = a.sub_R[i];
+    const int reg = a.sub_region[i];
+    const int k = reg >= 0 ? a.g2l[a.gidx[l] * a.nregion + reg] : 0;
+    const double* S = a.S_cache + a.sub_Sbase[i] + (int64_t)k * R * R;
+    const int64_t* dofs = a.sub_dofs + a.sub_dof_ptr[i];
+    const double* xl = x + l * a.M;
+    for (int j = threadIdx.x; j < R; j += blockDim.x) xs[j] = xl[dofs[j]];
+    __syncthreads();
+    for (int m = threadIdx.x; m < R; m += blockDim.x) {
+        double v = 0.0;
+        for (int j = 0; j < R; ++j) v += S[(int64_t)j * R + m] * xs[j];
+        atomicAdd(&y[l * a.M + dofs[m]], v);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void cg_update_kernel(CgArgs a, int iter) {
+    __shared__ double red[kThreads / 64];
+    __shared__ double coef[32];
+    const int64_t l = blockIdx.x;
+    if (!a.active[l]) return;
+    double* r = a.r + l * a.M;
+    double* p = a.p + l * a.M;
+    double* lam = a.lam + l * a.M;
+    double* Ap = a.Ap + l * a.M;
+    if (a.nker > 0) feti_project_row(a, Ap, red, coef);
+    double part = 0.0;
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) part += p[m] * Ap[m];
+    const double pAp = block_sum(part, red);
+    const double rr = a.rr[l];
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+        if (threadIdx.x == 0) {
+            a.status[l] = SDMM_CG_BREAKDOWN;
+            a.active[l] = 0;
+            a.iters[l] = iter;
+            a.relres[l] = a.r0[l] > 0 ? sqrt(rr) / a.r0[l] : 0.0;
+        }
+        return;
+    }
+    const double alpha = rr / pAp;
+    part = 0.0;
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
+        lam[m] += alpha * p[m];
+        const double rv = r[m] - alpha * Ap[m];
+        r[m] = rv;
+        part += rv * rv;
+    }
+    const double rrn = block_sum(part, red);
+    const double rel = sqrt(rrn) / a.r0[l];
+    const bool conv = rel <= a.rtol;
+    const bool last = iter + 1 >= a.max_iter;
+    if (conv || last) {
+        if (threadIdx.x == 0) {
+            a.status[l] = conv ? SDMM_CG_CONVERGED : SDMM_CG_MAXITER;
+            a.active[l] = 0;
+            a.iters[l] = iter + 1;
+            a.relres[l] = rel;
+        }
+        return;
+    }
+    const double beta = rrn / rr;
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
+        p[m] = r[m] + beta * p[m];
+        Ap[m] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        a.rr[l] = rrn;
+        a.iters[l] = iter + 1;
+        a.relres[l] = rel;
+        *a.any_active = 1;
+    }
+}
+
+__global__ void cg_finish_kernel(CgArgs a, int32_t* iters_out, double* relres_out, int32_t* status_out) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= a.n) return;
+    if (iters_out) iters_out[l] = a.iters[l];
+    if (relres_out) relres_out[l] = a.relres[l];
+    if (status_out) status_out[l] = a.status[l];
+}
+
+__global__ void validate_index_kernel(const int64_t* gidx, int64_t n, int64_t nreal, int32_t* bad) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n && (gidx[l] < 0 || gidx[l] >= nreal)) *bad = 1;
+}
+
+hipError_t launch_validate_index(const int64_t* gidx, int64_t n, int64_t nreal, int32_t* bad, hipStream_t stream) {
+    hipLaunchKernelGGL(validate_index_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, gidx, n, nreal,
+                       bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const CgArgs& a, hipStream_t stream) {
+    hipLaunchKernelGGL(cg_init_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_apply(const CgArgs& a, const double* x, double* y, int max_R, bool masked, hipStream_t stream) {
+    hipLaunchKernelGGL(cg_apply_kernel, dim3((unsigned)a.n, a.nsub), dim3(kThreads), max_R * sizeof(double), stream, a,
+                       x, y, masked ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const CgArgs& a, int iter, hipStream_t stream) {
+    hipLaunchKernelGGL(cg_update_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(const CgArgs& a, double* /*lam_out*/, int32_t* iters_out, double* relres_out,
+                            int32_t* status_out, hipStream_t stream) {
+    hipLaunchKernelGGL(cg_finish_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, stream, a, iters_out,
+                       relres_out, status_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Moments.  Per realization the fine fields are linear in the local mortar
+// coefficients c = R_i lambda (plus the FETI kernel coefficients alpha of
+// floating Stokes subdomains): u = Phi_{i,k} c + u_bar.  The accumulators
+// keep, per (subdomain, local realization k), a = sum w c and
+// Mc = sum w c c^T; the mean and E[u^2] of every fine DOF are then
+// Phi a (+ W u_bar) and diag(Phi Mc Phi^T) (+ cross terms), the same sums
+// Section 2 defines, regrouped by local realization.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void alpha_kernel(CgArgs a, const double* Slam, double* alpha) {
+    __shared__ double red[kThreads / 64];
+    __shared__ double coef[32];
+    const int64_t l = blockIdx.x;
+    const double* s = Slam + l * a.M;
+    const int nk = a.nker;
+    for (int k = 0; k < nk; ++k) {
+        double part = 0.0;
+        for (int m = threadIdx.x; m < a.M; m += blockDim.x) part += a.G[(int64_t)k * a.M + m] * (s[m] - a.g[m]);
+        const double v = block_sum(part, red);
+        if (threadIdx.x == 0) coef[k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nk; ++k) {
+            double d = 0.0;
+            for (int q = 0; q < nk; ++q) d += a.GtGinv[k * nk + q] * coef[q];
+            alpha[l * nk + k] = d;
+        }
+}
+
+hipError_t launch_alpha(const CgArgs& a, const double* Slam, double* alpha, hipStream_t stream) {
+    if (a.nker == 0) return hipSuccess;
+    hipLaunchKernelGGL(alpha_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, Slam, alpha);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void accumulate_kernel(MomArgs m, const int* pair_sub, const int* pair_k) {
+    extern __shared__ double cs[];
+    const int i = pair_sub[blockIdx.x], k = pair_k[blockIdx.x];
+    const int R = m.sub_R[i], nk = m.sub_ker[i], ext = R + nk;
+    const int reg = m.sub_region[i];
+    const int64_t* dofs = m.sub_dofs + m.sub_dof_ptr[i];
+    double* acc = m.acc + m.sub_Abase[i] + (int64_t)k * (ext + ext * ext);
+    // each thread owns fixed entries of a (ext) and Mc (ext x ext)
+    for (int64_t l = 0; l < m.n; ++l) {
+        const int kl = reg >= 0 ? m.g2l[m.gidx[l] * m.nregion + reg] : 0;
+        if (kl != k) continue;
+        const double w = m.weights ? m.weights[l] : m.colloc_w[m.gidx[l]];
+        __syncthreads();
+        for (int q = threadIdx.x; q < ext; q += blockDim.x)
+            cs[q] = q < R ? m.lam[l * m.M + dofs[q]] : m.alpha[l * m.nker + m.sub_Gcol[i] + (q - R)];
+        __syncthreads();
+        for (int q = threadIdx.x; q < ext + ext * ext; q += blockDim.x) {
+            if (q < ext) acc[q] += w * cs[q];
+            else {
+                const int e = q - ext, a = e % ext, b = e / ext;
+                acc[q] += w * cs[a] * cs[b];
+            }
+        }
+    }
+}
+
+__global__ void lam_moments_kernel(MomArgs m) {
+    const int dof = blockIdx.x * blockDim.x + threadIdx.x;
+    if (dof < m.M) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int64_t l = 0; l < m.n; ++l) {
+            const double w = m.weights ? m.weights[l] : m.colloc_w[m.gidx[l]];
+            const double v = m.lam[l * m.M + dof];
+            s1 += w * v;
+            s2 += w * v * v;
+        }
+        m.lam1[dof] += s1;
+        m.lam2[dof] += s2;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double ws = 0.0;
+        for (int64_t l = 0; l < m.n; ++l) ws += m.weights ? m.weights[l] : m.colloc_w[m.gidx[l]];
+        *m.wsum += ws;
+    }
+}
+
+hipError_t launch_accumulate_pairs(const MomArgs& m, const int* pair_sub, const int* pair_k, int npairs, int max_ext,
+                                   hipStream_t stream) {
+    if (npairs > 0)
+        hipLaunchKernelGGL(accumulate_kernel, dim3(npairs), dim3(kThreads), max_ext * sizeof(double), stream, m,
+                           pair_sub, pair_k);
+    hipLaunchKernelGGL(lam_moments_kernel, dim3((m.M + 255) / 256), dim3(256), 0, stream, m);
+    return hipGetLastError();
+}
+
+// Darcy fine moments: outputs are the N cells then the RT0 edges of one
+// subdomain; grid (chunk of 64 outputs, Darcy subdomain).
+__device__ inline int darcy_response_row(const DarcyTables& t, const DarcyDev& D, const double* xi, const double* X,
+                                         int o, double* F) {
+    // fills F (R values) with the response row of output o; returns 0 when zero
+    const int R = D.R, nx = D.nx, ny = D.ny, N = D.N;
+    if (o < N) {
+        const int ci = internal_of_cell(o, nx, ny, D.swap);
+        for (int a = 0; a < R; ++a) F[a] = X[(int64_t)ci * R + a];
+        return 1;
+    }
+    const int e = o - N;
+    const int nv = (nx + 1) * ny;
+    int c1 = -1, c2 = -1, be = -1;
+    double len, hperp;
+    if (e < nv) {
+        const int iy = e / (nx + 1), ix = e - iy * (nx + 1);
+        len = D.hy;
+        hperp = D.hx;
+        if (ix > 0 && ix < nx) {
+            c1 = iy * nx + ix - 1;
+            c2 = iy * nx + ix;
+        } else {
+            be = (ix == 0) ? 2 * nx + iy : 2 * nx + ny + iy;
+        }
+    } else {
+        const int q = e - nv, iy = q / nx, ix = q - iy * nx;
+        len = D.hx;
+        hperp = D.hy;
+        if (iy > 0 && iy < ny) {
+            c1 = (iy - 1) * nx + ix;
+            c2 = iy * nx + ix;
+        } else {
+            be = (iy == 0) ? ix : nx + ix;
+        }
+    }
+    if (be < 0) {
+        const double k1 = darcy_K(t, D, xi, c1), k2 = darcy_K(t, D, xi, c2);
+        const double T = len / (D.nu * (0.5 * hperp) * (1.0 / k1 + 1.0 / k2));
+        const int i1 = internal_of_cell(c1, nx, ny, D.swap), i2 = internal_of_cell(c2, nx, ny, D.swap);
+        for (int a = 0; a < R; ++a) F[a] = T / len * (X[(int64_t)i1 * R + a] - X[(int64_t)i2 * R + a]);
+        return 1;
+    }
+    const int kind = t.be_kind[D.off_be + be];
+    if (kind == 2) return 0;
+    const int cell = t.be_cell[D.off_be + be];
+    const double kc = darcy_K(t, D, xi, cell);
+    const double T = 2.0 * len * kc / (D.nu * hperp);
+    const double sg = (double)t.be_sgn[D.off_be + be];
+    const int ic = internal_of_cell(cell, nx, ny, D.swap);
+    if (kind == 1) {
+        for (int a = 0; a < R; ++a) F[a] = sg * T / len * X[(int64_t)ic * R + a];
+    } else {
+        const int me = t.be_medge[D.off_be + be];
+        const double* Pi = t.Pi + D.off_Pi + (int64_t)me * R;
+        for (int a = 0; a < R; ++a) F[a] = sg * T / len * (X[(int64_t)ic * R + a] - Pi[a]);
+    }
+    return 1;
+}
+
+__global__ __launch_bounds__(kThreads) void darcy_moments_kernel(DarcyTables t, const int* unit_of_dk, const int* d_nlocal,
+                                                                 const int64_t* d_Abase, const double* acc,
+                                                                 const double* X, const int64_t* cell_out_off,
+                                                                 const int64_t* edge_out_off, double* p1, double* p2,
+                                                                 double* u1, double* u2, int max_units_per_d) {
+    extern __shared__ double F[];   // 64 outputs x R
+    __shared__ double part[kThreads];
+    const int d = blockIdx.y;
+    const DarcyDev D = t.dar[d];
+    const int R = D.R;
+    const int nout = D.N + (D.nx + 1) * D.ny + D.nx * (D.ny + 1);
+    const int o0 = blockIdx.x * 64;
+    if (o0 >= nout) return;
+    const int sub_o = threadIdx.x & 63, quarter = threadIdx.x >> 6;
+    const int o = o0 + sub_o;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < d_nlocal[d]; ++k) {
+        const int u = unit_of_dk[d * max_units_per_d + k];
+        const UnitDev U = t.units[u];
+        const double* xi = t.xi + U.off_xi;
+        const double* Xu = X + U.off_X;
+        const double* av = acc + d_Abase[d] + (int64_t)k * (R + R * R);
+        const double* Mc = av + R;
+        __syncthreads();
+        if (quarter == 0 && o < nout) {
+            if (!darcy_response_row(t, D, xi, Xu, o, F + sub_o * R))
+                for (int a = 0; a < R; ++a) F[sub_o * R + a] = 0.0;
+        }
+        __syncthreads();
+        if (o < nout) {
+            const double* f = F + sub_o * R;
+            double q = 0.0, lin = 0.0;
+            for (int a = quarter; a < R; a += 4) {
+                double v = 0.0;
+                for (int b = 0; b < R; ++b) v += Mc[(int64_t)b * R + a] * f[b];
+                q += f[a] * v;
+                lin += f[a] * av[a];
+            }
+            s1 += lin;
+            s2 += q;
+        }
+    }
+    // combine the four partial sums of every output in a fixed order
+    __syncthreads();
+    part[threadIdx.x] = s1;
+    __syncthreads();
+    double m1 = 0.0;
+    if (quarter == 0) m1 = part[sub_o] + part[64 + sub_o] + part[128 + sub_o] + part[192 + sub_o];
+    __syncthreads();
+    part[threadIdx.x] = s2;
+    __syncthreads();
+    if (quarter == 0 && o < nout) {
+        const double m2 = part[sub_o] + part[64 + sub_o] + part[128 + sub_o] + part[192 + sub_o];
+        if (o < D.N) {
+            p1[cell_out_off[d] + o] = m1;
+            p2[cell_out_off[d] + o] = m2;
+        } else {
+            u1[edge_out_off[d] + o - D.N] = m1;
+            u2[edge_out_off[d] + o - D.N] = m2;
+        }
+    }
+}
+
+hipError_t launch_darcy_moments_impl(const DarcyTables& t, const int* unit_of_dk, const int* d_nlocal, int n_darcy,
+                                     int max_nout, int max_units_per_d, const int64_t* d_Abase, const double* acc,
+                                     const double* X, int max_R, const int64_t* cell_out_off,
+                                     const int64_t* edge_out_off, double* p1, double* p2, double* u1, double* u2,
+                                     hipStream_t stream) {
+    if (n_darcy <= 0) return hipSuccess;
+    hipLaunchKernelGGL(darcy_moments_kernel, dim3((max_nout + 63) / 64, n_darcy), dim3(kThreads),
+                       64 * max_R * sizeof(double), stream, t, unit_of_dk, d_nlocal, d_Abase, acc, X, cell_out_off,
+                       edge_out_off, p1, p2, u1, u2, max_units_per_d);
+    return hipGetLastError();
+}
+
+// Stokes fine moments: u = [U_basis, Z] c' + u_bar, p = P_basis c + p_bar.
+__global__ __launch_bounds__(kThreads) void stokes_moments_kernel(const StokesDev* sd, const int64_t* s_Abase,
+                                                                  const double* acc, const double* wsum,
+                                                                  const double* U, const double* P, const double* Z,
+                                                                  const int64_t* u_out_off, const int64_t* p_out_off,
+                                                                  double* u1, double* u2, double* p1, double* p2) {
+    extern __shared__ double F[];
+    __shared__ double part[kThreads];
+    const int si = blockIdx.y;
+    const StokesDev s = sd[si];
+    const int R = s.R, nk = s.nker, ext = R + nk;
+    const int nout = s.nvel + s.npre;
+    const int o0 = blockIdx.x * 64;
+    if (o0 >= nout) return;
+    const int sub_o = threadIdx.x & 63, quarter = threadIdx.x >> 6;
+    const int o = o0 + sub_o;
+    const double* av = acc + s_Abase[si];
+    const double* Mc = av + ext;
+    const double W = *wsum;
+    double cbar = 0.0;
+    if (quarter == 0 && o < nout) {
+        double* f = F + sub_o * ext;
+        if (o < s.nvel) {
+            for (int a = 0; a < R; ++a) f[a] = U[s.off_U + (int64_t)a * s.nvel + o];
+            for (int a = 0; a < nk; ++a) f[R + a] = Z[s.off_Z + (int64_t)a * s.nvel + o];
+            cbar = U[s.off_U + (int64_t)R * s.nvel + o];
+        } else {
+            const int q = o - s.nvel;
+            for (int a = 0; a < R; ++a) f[a] = P[s.off_P + (int64_t)a * s.npre + q];
+            for (int a = 0; a < nk; ++a) f[R + a] = 0.0;
+            cbar = P[s.off_P + (int64_t)R * s.npre + q];
+        }
+    }
+    __syncthreads();
+    double qv = 0.0, lin = 0.0;
+    if (o < nout) {
+        const double* f = F + sub_o * ext;
+        for (int a = quarter; a < ext; a += 4) {
+            double v = 0.0;
+            for (int b = 0; b < ext; ++b) v += Mc[(int64_t)b * ext + a] * f[b];
+            qv += f[a] * v;
+            lin += f[a] * av[a];
+        }
+    }
+    part[threadIdx.x] = lin;
+    __syncthreads();
+    double L1 = 0.0;
+    if (quarter == 0) L1 = part[sub_o] + part[64 + sub_o] + part[128 + sub_o] + part[192 + sub_o];
+    __syncthreads();
+    part[threadIdx.x] = qv;
+    __syncthreads();
+    if (quarter == 0 && o < nout) {
+        const double Q = part[sub_o] + part[64 + sub_o] + part[128 + sub_o] + part[192 + sub_o];
+        const double m1 = L1 + W * cbar;
+        const double m2 = Q + 2.0 * cbar * L1 + W * cbar * cbar;
+        if (o < s.nvel) {
+            u1[u_out_off[si] + o] = m1;
+            u2[u_out_off[si] + o] = m2;
+        } else {
+            p1[p_out_off[si] + o - s.nvel] = m1;
+            p2[p_out_off[si] + o - s.nvel] = m2;
+        }
+    }
+}
+
+hipError_t launch_stokes_moments_impl(const StokesDev* sd, int ns, int max_nout, const int64_t* s_Abase,
+                                      const double* acc, const double* wsum, const double* U, const double* P,
+                                      const double* Z, const int64_t* u_out_off, const int64_t* p_out_off, int max_ext,
+                                      double* u1, double* u2, double* p1, double* p2, hipStream_t stream) {
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stokes_moments_kernel, dim3((max_nout + 63) / 64, ns), dim3(kThreads),
+                       64 * max_ext * sizeof(double), stream, sd, s_Abase, acc, wsum, U, P, Z, u_out_off, p_out_off,
+                       u1, u2, p1, p2);
+    return hipGetLastError();
+}
+
+}  // namespace sdmm

@@ -1,0 +1,158 @@
+// Device kernels of the flux basis library and their launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sdmm {
+
+// Per Darcy subdomain (device-resident table entry).
+struct DarcyDev {
+    int nx, ny, N, swap, b, R, nterm, n_medge;
+    double hx, hy, nu, mean_logk;
+    int64_t off_be;     // boundary-edge arrays (2 (nx + ny) entries)
+    int64_t off_cellbe; // 2 entries per cell (row-major): boundary edge ids or -1
+    int64_t off_Pi;     // n_medge x R
+    int64_t off_phi;    // nterm x N
+    int64_t off_dofs;   // into the concatenated local->global mortar list
+    int64_t off_supp;   // CSR pointer base (R + 1 entries) into supp arrays
+    int64_t off_me;     // internal cell index of every mortar edge (n_medge)
+};
+
+// One basis-build unit: Darcy subdomain d, local realization k.
+struct UnitDev {
+    int d, k, sub, pad;
+    int64_t off_xi;     // region-local collocation point (nterm values)
+    int64_t off_S;      // S (R x R, column-major) in the basis cache
+    int64_t off_X;      // fine responses X (N x R, internal cell order)
+    int64_t off_L;      // band factor scratch (N x (b + 1))
+    int64_t off_T;      // K / transmissibility scratch (4 N + n_medge)
+};
+
+struct DarcyTables {
+    const DarcyDev* dar;
+    const UnitDev* units;
+    const int* be_cell;
+    const int* be_kind;
+    const double* be_len;
+    const double* be_hperp;
+    const int* be_medge;
+    const int* be_sgn;
+    const int* cell_be;
+    const double* Pi;
+    const double* phi;
+    const double* xi;
+    const int* supp_ptr;
+    const int* supp_e;
+    const double* supp_v;
+    const int* me_cell;
+};
+
+// Launchers (all enqueue on `stream`).
+hipError_t launch_darcy_basis_fp64(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
+                                   double* X, double* Lscr, double* Tscr, hipStream_t stream);
+hipError_t launch_darcy_basis_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
+                                    double* X, float* Lscr32, double* Tscr, float* W32, double* Rres,
+                                    int max_refine, double refine_tol, double* max_res, int* steps,
+                                    hipStream_t stream);
+
+// Stokes: tiled band LDL^T (tile 64) of several subdomains at once.
+struct StokesDev {
+    int nband, nblk, w, ncol;   // ncol = R + 1
+    int nvel, npre, R, nker;
+    int64_t off_tiles;  // tiled band storage
+    int64_t off_rhs;    // nblk*64 x ncol column-major
+    int64_t off_U;      // nvel x ncol (raw velocity responses)
+    int64_t off_P;      // npre x ncol
+    int64_t off_map;    // band -> raw map (nband entries; pressure encoded as -1 - q)
+    int64_t off_Z;      // nker x nvel
+    int64_t off_q;      // CSR pointer base of the trace rows (R + 1)
+    int64_t off_S;      // basis cache offset
+    int64_t off_dofs;   // local->global mortar DOFs
+    int64_t off_G;      // first column of this subdomain's kernel traces in G
+};
+
+hipError_t launch_stokes_scatter(const StokesDev* sd, int ns, const int* tr_sub, const int* tr_r, const int* tr_c,
+                                 const double* tr_v, int64_t ntrip, double* tiles, hipStream_t stream);
+hipError_t launch_stokes_pad_identity(const StokesDev* sd, int ns, int max_nblk, double* tiles, hipStream_t stream);
+hipError_t launch_stokes_ldl_step(const StokesDev* sd, int ns, int J, int max_w, double* tiles, hipStream_t stream);
+hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol, const double* tiles,
+                               double* rhs, hipStream_t stream);
+hipError_t launch_stokes_finish(const StokesDev* sd, int ns, int max_ncol, int max_R, const double* rhs, const int* bmap,
+                                const double* uD, const int64_t* uD_off, const double* Z, const int* q_ptr,
+                                const int* q_col, const double* q_val, const int64_t* dofs, double* U, double* P,
+                                double* S_cache, double* g, double* G, int M, hipStream_t stream);
+
+// Interface CG
+struct CgArgs {
+    int64_t n;            // realizations in the batch
+    int M, nsub, nregion, nker;
+    const int64_t* gidx;
+    const int32_t* g2l;   // n_real x n_region
+    const int* sub_R;
+    const int64_t* sub_dof_ptr;
+    const int64_t* sub_dofs;
+    const int* sub_region;   // -1 for Stokes
+    const int64_t* sub_Sbase;
+    const double* S_cache;
+    const double* g;
+    const double* G;         // M x nker (column-major)
+    const double* GtGinv;    // nker x nker
+    double* lam;
+    double* r;
+    double* p;
+    double* Ap;
+    double* rr;
+    double* r0;
+    int32_t* iters;
+    double* relres;
+    int32_t* status;
+    int32_t* active;
+    int32_t* any_active;
+    double rtol;
+    int max_iter;
+};
+
+hipError_t launch_validate_index(const int64_t* gidx, int64_t n, int64_t nreal, int32_t* bad, hipStream_t stream);
+hipError_t launch_cg_init(const CgArgs& a, hipStream_t stream);
+hipError_t launch_cg_apply(const CgArgs& a, const double* x, double* y, int max_R, bool masked, hipStream_t stream);
+hipError_t launch_cg_update(const CgArgs& a, int iter, hipStream_t stream);
+hipError_t launch_cg_finish(const CgArgs& a, double* lam_out, int32_t* iters_out, double* relres_out,
+                            int32_t* status_out, hipStream_t stream);
+
+// Moments
+struct MomArgs {
+    int64_t n;
+    int M, nsub, nregion, nker;
+    const int64_t* gidx;
+    const int32_t* g2l;
+    const double* weights;   // n (or null: use colloc weights)
+    const double* colloc_w;
+    const double* lam;       // n x M
+    const int* sub_R;
+    const int64_t* sub_dof_ptr;
+    const int64_t* sub_dofs;
+    const int* sub_region;
+    const int* sub_ker;      // kernel columns of each subdomain (0 if not floating)
+    const int* sub_Gcol;     // first column in alpha of each subdomain
+    const int64_t* sub_Abase;   // accumulator base of each subdomain (a and M for every local k)
+    const int* sub_nlocal;
+    const double* alpha;     // n x nker
+    double* acc;             // accumulators
+    double* lam1;
+    double* lam2;
+    double* wsum;
+};
+hipError_t launch_alpha(const CgArgs& a, const double* Slam, double* alpha, hipStream_t stream);
+hipError_t launch_accumulate_pairs(const MomArgs& m, const int* pair_sub, const int* pair_k, int npairs, int max_ext,
+                                   hipStream_t stream);
+hipError_t launch_darcy_moments_impl(const DarcyTables& t, const int* unit_of_dk, const int* d_nlocal, int n_darcy,
+                                     int max_nout, int max_units_per_d, const int64_t* d_Abase, const double* acc,
+                                     const double* X, int max_R, const int64_t* cell_out_off,
+                                     const int64_t* edge_out_off, double* p1, double* p2, double* u1, double* u2,
+                                     hipStream_t stream);
+hipError_t launch_stokes_moments_impl(const StokesDev* sd, int ns, int max_nout, const int64_t* s_Abase,
+                                      const double* acc, const double* wsum, const double* U, const double* P,
+                                      const double* Z, const int64_t* u_out_off, const int64_t* p_out_off, int max_ext,
+                                      double* u1, double* u2, double* p1, double* p2, hipStream_t stream);
+
+}  // namespace sdmm

@@ -1,0 +1,258 @@
+"""ctypes binding of libsdmm.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels; this module converts
+problem dicts into the C structure, torch device tensors into pointers and
+the results back into numpy arrays.  It fails loudly when the library is not
+built or no GPU is present.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdmm.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, ESTATE = 0, -1, -2, -3, -4, -5, -6
+PREC = {"fp64": 0, "mixed": 1}
+FIELDS = {"lambda": 0, "darcy_p": 1, "darcy_u": 2, "stokes_u": 3, "stokes_p": 4}
+MAPS = {"interfaces": 0, "sub_ptr": 1, "sub_dofs": 2, "sub_sign": 3, "g2l": 4, "nlocal": 5, "node_ids": 6}
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [("nu_s", ctypes.c_double), ("nu_d", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("k_bjs", ctypes.c_double), ("inflow_x", ctypes.c_double), ("inflow_y", ctypes.c_double),
+                ("p_bottom", ctypes.c_double), ("domain", ctypes.c_double * 4),
+                ("n_sub", ctypes.c_int32), ("sub_type", _i32p), ("sub_rect", _f64p), ("sub_n", _i32p),
+                ("sub_region", _i32p), ("mortar_degree", ctypes.c_int32), ("mortar_elements", ctypes.c_int32),
+                ("n_region", ctypes.c_int32), ("region_rect", _f64p), ("region_nterm", _i32p),
+                ("region_sigma2", _f64p), ("region_eta", _f64p), ("region_mean_logk", _f64p),
+                ("rule_kind", ctypes.c_int32), ("rule_m", ctypes.c_int32), ("rule_level", ctypes.c_int32),
+                ("rule_growth", ctypes.c_int32)]
+
+
+class CSizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_sub", "n_stokes", "n_darcy", "n_iface", "M", "n_real", "n_term",
+                                              "n_region", "n_units", "n_floating", "n_kernel")] + \
+               [("field_size", ctypes.c_int64 * 5)] + \
+               [(n, ctypes.c_int64) for n in ("basis_bytes", "response_bytes", "max_R", "darcy_flops")]
+
+
+class CCounters(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("basis_solves_darcy", "basis_solves_stokes", "complementary_solves",
+                                              "units_built", "refinement_steps", "cg_iterations", "realizations")] + \
+               [(n, ctypes.c_double) for n in ("ms_basis_darcy", "ms_basis_stokes", "ms_solve", "max_refine_residual")]
+
+
+EXPORTS = {
+    "sdmm_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "sdmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sdmm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "sdmm_set_problem": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CProblem)]),
+    "sdmm_get_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSizes)]),
+    "sdmm_get_index_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i64p, ctypes.c_int64, _i64p]),
+    "sdmm_get_collocation": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
+    "sdmm_get_kl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _f64p, _i32p]),
+    "sdmm_build_flux_basis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "sdmm_get_basis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _f64p, ctypes.c_int64]),
+    "sdmm_solve_interface": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "sdmm_accumulate_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "sdmm_get_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _f64p, _f64p]),
+    "sdmm_reset_moments": (ctypes.c_int, [ctypes.c_void_p]),
+    "sdmm_get_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CCounters)]),
+}
+
+_LIB = None
+
+
+def load():
+    """Load libsdmm.so and declare its signatures (no GPU call is made)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsdmm.so is not built; run paper_1802_06263_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+class SdmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("sdmm error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (must live on the GPU)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Context:
+    """One library context on one GPU."""
+
+    def __init__(self, device=0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        rc = self.lib.sdmm_create(int(device), ctypes.byref(h))
+        if rc != OK:
+            raise SdmmError(rc, "sdmm_create failed (no usable GPU %d?)" % device)
+        self.h = h
+        self._keep = None
+
+    def close(self):
+        if self.h:
+            self.lib.sdmm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != OK and rc not in allow:
+            raise SdmmError(rc, self.lib.sdmm_last_error(self.h).decode())
+        return rc
+
+    # ---- problem -------------------------------------------------------------
+    def set_problem(self, prob):
+        subs = prob["subdomains"]
+        ph = prob["physics"]
+        regs = prob["regions"]
+        rule = prob["rule"]
+        keep = {
+            "sub_type": _arr([0 if s["type"] == "stokes" else 1 for s in subs], np.int32),
+            "sub_rect": _arr([s["rect"] for s in subs], np.float64),
+            "sub_n": _arr([s["n"] for s in subs], np.int32),
+            "sub_region": _arr([s["region"] if s["type"] == "darcy" else -1 for s in subs], np.int32),
+            "region_rect": _arr([r["rect"] for r in regs], np.float64),
+            "region_nterm": _arr([r["nterm"] for r in regs], np.int32),
+            "region_sigma2": _arr([r["sigma2"] for r in regs], np.float64),
+            "region_eta": _arr([r["eta"] for r in regs], np.float64),
+            "region_mean_logk": _arr([r["mean_logk"] for r in regs], np.float64),
+        }
+        c = CProblem()
+        c.nu_s, c.nu_d, c.alpha, c.k_bjs = ph["nu_s"], ph["nu_d"], ph["alpha"], ph["k_bjs"]
+        c.inflow_x, c.inflow_y = ph["inflow"]
+        c.p_bottom = ph["p_bottom"]
+        for k in range(4):
+            c.domain[k] = prob["domain"][k]
+        c.n_sub = len(subs)
+        c.sub_type = _ptr(keep["sub_type"], ctypes.c_int32)
+        c.sub_rect = _ptr(keep["sub_rect"], ctypes.c_double)
+        c.sub_n = _ptr(keep["sub_n"], ctypes.c_int32)
+        c.sub_region = _ptr(keep["sub_region"], ctypes.c_int32)
+        c.mortar_degree = prob["mortar"]["degree"]
+        c.mortar_elements = prob["mortar"]["elements"]
+        c.n_region = len(regs)
+        c.region_rect = _ptr(keep["region_rect"], ctypes.c_double)
+        c.region_nterm = _ptr(keep["region_nterm"], ctypes.c_int32)
+        c.region_sigma2 = _ptr(keep["region_sigma2"], ctypes.c_double)
+        c.region_eta = _ptr(keep["region_eta"], ctypes.c_double)
+        c.region_mean_logk = _ptr(keep["region_mean_logk"], ctypes.c_double)
+        c.rule_kind = 0 if rule["kind"] == "tensor" else 1
+        c.rule_m = int(rule.get("m", 0))
+        c.rule_level = int(rule.get("level", 0))
+        c.rule_growth = 0 if rule.get("growth", "paper") == "paper" else 1
+        self._check(self.lib.sdmm_set_problem(self.h, ctypes.byref(c)))
+        self._sizes = self.sizes()
+
+    def sizes(self):
+        s = CSizes()
+        self._check(self.lib.sdmm_get_sizes(self.h, ctypes.byref(s)))
+        out = {n: getattr(s, n) for n, _ in CSizes._fields_ if n != "field_size"}
+        out["field_size"] = [s.field_size[k] for k in range(5)]
+        return out
+
+    def index_map(self, kind):
+        n = ctypes.c_int64()
+        k = MAPS[kind]
+        self._check(self.lib.sdmm_get_index_map(self.h, k, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.int64)
+        self._check(self.lib.sdmm_get_index_map(self.h, k, _ptr(out, ctypes.c_int64), out.size, ctypes.byref(n)))
+        return out[:n.value]
+
+    def collocation(self):
+        s = self._sizes
+        pts = np.zeros((s["n_real"], max(s["n_term"], 1)))
+        w = np.zeros(s["n_real"])
+        self._check(self.lib.sdmm_get_collocation(self.h, _ptr(pts, ctypes.c_double), _ptr(w, ctypes.c_double)))
+        return pts[:, :s["n_term"]], w
+
+    def kl(self, region, nterm):
+        lam = np.zeros(nterm)
+        modes = np.zeros(2 * nterm, dtype=np.int32)
+        self._check(self.lib.sdmm_get_kl(self.h, region, _ptr(lam, ctypes.c_double), _ptr(modes, ctypes.c_int32)))
+        return lam, modes.reshape(nterm, 2)
+
+    # ---- hot path --------------------------------------------------------------
+    def build_flux_basis(self, precision="fp64", stream=None):
+        self._check(self.lib.sdmm_build_flux_basis(self.h, PREC[precision], _stream(stream)))
+
+    def get_basis(self, sub, k, R):
+        S = np.zeros((R, R), order="F")
+        self._check(self.lib.sdmm_get_basis(self.h, sub, k, _ptr(S, ctypes.c_double), R))
+        return S
+
+    def solve_interface(self, gidx, lam, rtol=1e-8, max_iter=None, iters=None, relres=None, status=None,
+                        stream=None, allow_notconv=False):
+        """gidx: int64 device tensor (n); lam: float64 device tensor (n x M)."""
+        n = gidx.numel()
+        if max_iter is None:
+            max_iter = 10 * self._sizes["M"]
+        rc = self.lib.sdmm_solve_interface(self.h, n, _dptr(gidx), float(rtol), int(max_iter), _dptr(lam),
+                                           _dptr(iters), _dptr(relres), _dptr(status), _stream(stream))
+        return self._check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+
+    def accumulate_moments(self, gidx, lam, weights=None, stream=None):
+        self._check(self.lib.sdmm_accumulate_moments(self.h, gidx.numel(), _dptr(gidx), _dptr(lam),
+                                                     _dptr(weights), _stream(stream)))
+
+    def get_moments(self, field):
+        n = self._sizes["field_size"][FIELDS[field]]
+        mean = np.zeros(n)
+        var = np.zeros(n)
+        self._check(self.lib.sdmm_get_moments(self.h, FIELDS[field], _ptr(mean, ctypes.c_double),
+                                              _ptr(var, ctypes.c_double)))
+        return mean, var
+
+    def reset_moments(self):
+        self._check(self.lib.sdmm_reset_moments(self.h))
+
+    def counters(self):
+        c = CCounters()
+        self._check(self.lib.sdmm_get_counters(self.h, ctypes.byref(c)))
+        return {n: getattr(c, n) for n, _ in CCounters._fields_}

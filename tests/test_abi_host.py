@@ -1,0 +1,88 @@
+"""C-ABI checks that need no GPU: symbols, host-only setup, bit-exact maps."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.collocation import Grid
+from oracle.geometry import Layout, index_maps
+from oracle.kl import region_modes
+from workloads import problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1802_06263_amd import sdmm
+    return sdmm
+
+
+def test_library_exports_every_declared_symbol():
+    sdmm = _lib()
+    lib = sdmm.load()
+    hdr = open(os.path.join(ROOT, "include", "sdmm.h")).read()
+    names = sorted(set(re.findall(r"\b(sdmm_[a-z_]+)\s*\(", hdr)))
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sdmm.EXPORTS)
+
+
+def test_device_calls_fail_cleanly_without_gpu():
+    sdmm = _lib()
+    lib = sdmm.load()
+    h = ctypes.c_void_p()
+    assert lib.sdmm_create(-1, ctypes.byref(h)) == 0
+    assert lib.sdmm_build_flux_basis(h, 0, None) == sdmm.ESTATE  # no problem yet
+    assert lib.sdmm_destroy(h) == 0
+
+
+@pytest.mark.parametrize("name", ["cfg0", "cfg1", "cfg2", "cfg3"])
+def test_index_maps_bit_exact(name):
+    sdmm = _lib()
+    p = problem(name)
+    ctx = sdmm.Context(-1)
+    ctx.set_problem(p)
+    L = Layout(p)
+    ref = index_maps(L)
+    assert np.array_equal(ctx.index_map("interfaces").reshape(-1, 5), ref["interfaces"])
+    assert np.array_equal(ctx.index_map("sub_ptr"), ref["sub_ptr"])
+    assert np.array_equal(ctx.index_map("sub_dofs"), ref["sub_dofs"])
+    assert np.array_equal(ctx.index_map("sub_sign"), ref["sub_sign"])
+    g = Grid(p["regions"], p["rule"])
+    assert np.array_equal(ctx.index_map("node_ids").reshape(g.nreal, g.N), g.ids)
+    assert np.array_equal(ctx.index_map("g2l").reshape(g.nreal, -1), g.g2l)
+    assert np.array_equal(ctx.index_map("nlocal"), np.array(g.nlocal))
+    s = ctx.sizes()
+    assert s["M"] == L.M and s["n_real"] == g.nreal
+    assert s["n_units"] == sum(g.nlocal[sub["region"]] for sub in p["subdomains"] if sub["type"] == "darcy")
+    pts, w = ctx.collocation()
+    assert np.abs(pts - g.points).max() < 1e-14
+    assert np.abs(w - g.weights).max() < 1e-13 * max(1.0, np.abs(g.weights).max())
+    for r, reg in enumerate(p["regions"]):
+        lam, modes = ctx.kl(r, reg["nterm"])
+        om, *_ = region_modes(reg)
+        assert [tuple(m) for m in modes] == [(m["a"], m["b"]) for m in om]
+        assert np.allclose(lam, [m["lam"] for m in om], rtol=1e-13, atol=0)
+    ctx.close()
+
+
+def test_set_problem_rejects_bad_input():
+    sdmm = _lib()
+    ctx = sdmm.Context(-1)
+    p = problem("cfg0")
+    p["physics"]["p_bottom"] = 1.0
+    with pytest.raises(sdmm.SdmmError) as e:
+        ctx.set_problem(p)
+    assert e.value.code == sdmm.EINVAL
+    p = problem("cfg0")
+    p["subdomains"][1]["rect"] = [0.0, 0.4, 0.0, 1.0]
+    with pytest.raises(sdmm.SdmmError):
+        ctx.set_problem(p)
+    p = problem("cfg0")
+    p["mortar"] = {"degree": 2, "elements": 8}
+    with pytest.raises(sdmm.SdmmError):
+        ctx.set_problem(p)
+    ctx.close()

@@ -1,0 +1,146 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances (derived from the arithmetic):
+  S_{H,i}^{(k)} FP64     1e-11 relative to max|S| (banded Cholesky vs sparse LU,
+                         condition numbers of the local operators ~1e4)
+  lambda at rtol 1e-12   1e-9 relative (CG stopping error times the interface
+                         condition number)
+  moments at rtol 1e-12  1e-9 relative per field (the spec bar)
+  mixed precision        S 1e-10, moments 1e-8 (FP32 factor, FP64 refinement
+                         to 1e-13 relative residual)
+"""
+import numpy as np
+import pytest
+
+from oracle.methods import FIELDS, Oracle
+from workloads import problem
+
+from gpu_helpers import gpu_ctx, gpu_solve, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_feti():
+    return problem("cfg2", stokes_mesh=(8, 8), darcy_mesh=(4, 4), mortar={"degree": 1, "elements": 2})
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    o = Oracle(problem("cfg0"))
+    o.stochastic_basis()
+    return o
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 1e-10)])
+def test_basis_parity_cfg0(cfg0, precision, tol):
+    print("case: cfg0 basis", precision, flush=True)
+    ctx = gpu_ctx(cfg0.prob, precision)
+    for (i, k), S in cfg0.s3_table.items():
+        Sg = ctx.get_basis(i, k, S.shape[0])
+        assert rel(Sg, S) < tol, (i, k, rel(Sg, S))
+    ctx.close()
+
+
+def test_solve_and_moments_parity_cfg0(cfg0):
+    print("case: cfg0 solve + moments fp64", flush=True)
+    ctx = gpu_ctx(cfg0.prob, "fp64")
+    n = cfg0.grid.nreal
+    g, lam, it, rr, st, rc = gpu_solve(ctx, np.arange(n), rtol=1e-12)
+    assert (st == 0).all() and (rr <= 1e-12).all()
+    mom, info = cfg0.run("S3", rtol=1e-12)
+    lam_o = np.stack([d["lambda"] for d in info])
+    assert rel(lam.cpu().numpy(), lam_o) < 1e-9
+    assert np.abs(it - np.array([d["iters"] for d in info])).max() <= 2
+    ctx.accumulate_moments(g, lam)
+    for f in FIELDS:
+        mg, vg = ctx.get_moments(f)
+        mo, vo = mom[f]
+        assert rel(mg, mo) < 1e-9, f
+        assert np.abs(vg - vo).max() < 1e-9 * max(np.abs(vo).max(), 1e-12 * np.abs(mo).max() ** 2), f
+    ctx.close()
+
+
+def test_mixed_precision_moments_cfg0(cfg0):
+    print("case: cfg0 moments mixed", flush=True)
+    ctx = gpu_ctx(cfg0.prob, "mixed")
+    n = cfg0.grid.nreal
+    g, lam, it, rr, st, rc = gpu_solve(ctx, np.arange(n), rtol=1e-12)
+    ctx.accumulate_moments(g, lam)
+    mom, info = cfg0.run("S3", rtol=1e-12)
+    for f in FIELDS:
+        mg, vg = ctx.get_moments(f)
+        mo, vo = mom[f]
+        assert rel(mg, mo) < 1e-8, f
+        assert rel(vg, vo) < 1e-8, f
+    c = ctx.counters()
+    assert c["max_refine_residual"] <= 1e-12
+    ctx.close()
+
+
+def test_feti_floating_stokes_parity():
+    print("case: small cfg2 layout with floating Stokes subdomains", flush=True)
+    p = _small_feti()
+    o = Oracle(p)
+    o.stochastic_basis()
+    ctx = gpu_ctx(p, "fp64")
+    assert ctx.sizes()["n_kernel"] == 4
+    for (i, k), S in o.s3_table.items():
+        if i < 8 or k in (0, 4, 8):
+            assert rel(ctx.get_basis(i, k, S.shape[0]), S) < 1e-11, (i, k)
+    idx = [0, 17, 4000, 6560]
+    g, lam, it, rr, st, rc = gpu_solve(ctx, idx, rtol=1e-12)
+    w = np.array([0.1, 0.2, 0.3, 0.4])
+    mom, info = o.run("S3", indices=idx, weights=w, rtol=1e-12)
+    assert rel(lam.cpu().numpy(), np.stack([d["lambda"] for d in info])) < 1e-9
+    import torch
+    ctx.accumulate_moments(g, lam, torch.tensor(w, device="cuda"))
+    for f in FIELDS:
+        mg, vg = ctx.get_moments(f)
+        mo, vo = mom[f]
+        assert rel(mg, mo) < 1e-9, f
+    ctx.close()
+
+
+def test_results_identical_alone_and_in_a_batch(cfg0):
+    print("case: cfg0 alone vs mixed batch", flush=True)
+    ctx = gpu_ctx(cfg0.prob, "fp64")
+    _, a, *_ = gpu_solve(ctx, [3, 7], rtol=1e-8)
+    _, b, *_ = gpu_solve(ctx, [11, 3, 0, 7, 15], rtol=1e-8)
+    a = a.cpu().numpy()
+    b = b.cpu().numpy()
+    assert np.array_equal(a[0], b[1]) and np.array_equal(a[1], b[3])
+    ctx.close()
+
+
+def test_edge_cases(cfg0):
+    print("case: cfg0 edge cases", flush=True)
+    import torch
+    from paper_1802_06263_amd import sdmm
+    ctx = gpu_ctx(cfg0.prob, "fp64")
+    # empty batch
+    g = torch.zeros(0, dtype=torch.int64, device="cuda")
+    lam = torch.zeros((0, 12), dtype=torch.float64, device="cuda")
+    assert ctx.solve_interface(g, lam) == 0
+    # max_iter too small: ENOTCONV with the per-realization status filled
+    _, lam, it, rr, st, rc = gpu_solve(ctx, [0, 1], rtol=1e-12, max_iter=1, allow_notconv=True)
+    assert rc == sdmm.ENOTCONV and (st == 1).all() and (it == 1).all()
+    with pytest.raises(sdmm.SdmmError):
+        ctx.solve_interface(g, lam, rtol=-1.0)
+    with pytest.raises(sdmm.SdmmError):
+        ctx.get_basis(99, 0, 8)
+    ctx.close()
+
+
+def test_constant_permeability_closed_form():
+    print("case: cfg0 sigma2 = 0 closed form", flush=True)
+    p = problem("cfg0", sigma2=0.0)
+    ctx = gpu_ctx(p, "fp64")
+    g, lam, it, rr, st, rc = gpu_solve(ctx, np.arange(16), rtol=1e-13)
+    ctx.accumulate_moments(g, lam)
+    mu, vu = ctx.get_moments("stokes_u")
+    assert np.abs(mu[0::2]).max() < 1e-10 and np.abs(mu[1::2] + 1).max() < 1e-10
+    assert np.abs(vu).max() < 1e-12
+    mp, vp = ctx.get_moments("darcy_p")
+    yc = (np.arange(8) + 0.5) / 8
+    assert np.allclose(mp.reshape(2, 8, 8), yc[None, :, None], atol=1e-10)
+    ctx.close()
