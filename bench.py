@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--single", action="store_true", help="time only --precision (profiling runs)")
     return ap.parse_args()
 
 
@@ -135,7 +136,7 @@ def main():
     lam = torch.zeros((n, M), dtype=torch.float64, device="cuda")
     other = "fp64" if args.precision == "mixed" else "mixed"
     res = {}
-    for prec in (other, args.precision):
+    for prec in ((args.precision,) if args.single else (other, args.precision)):
         dt, bms, sms = time_path(ctx, prec, g, lam, args.rtol, args.steps, args.warmup, torch)
         c = ctx.counters()
         res[prec] = {"ms_per_step": dt * 1e3, "realizations_per_s": n / dt, "ms_basis": bms, "ms_cg": sms,
@@ -155,7 +156,7 @@ def main():
            "config": {"workload": args.workload, "n_real": n, "M": M, "basis_units": sz["n_units"],
                       "precision": args.precision, "rtol": args.rtol},
            "basis_builds_per_s": main_r["basis_builds_per_s"],
-           "fp64": res["fp64"], "mixed": res["mixed"], "stokes_basis_ms": stokes_ms,
+           "fp64": res.get("fp64"), "mixed": res.get("mixed"), "stokes_basis_ms": stokes_ms,
            "roofline": roof}
     ctx.close()
     if not args.no_cpu_baseline:

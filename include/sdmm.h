@@ -202,6 +202,17 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const
 /* Mean and variance (host arrays of field_size[field]) of one field. */
 int sdmm_get_moments(sdmm_ctx* ctx, int field, double* mean, double* var);
 int sdmm_reset_moments(sdmm_ctx* ctx);
+
+/* Tuning knobs of the batched CG (used by the autotuner):
+ *   SDMM_OPT_CG_CHUNK  realizations per internal CG chunk (0 = sized so the
+ *                      chunk's vectors fit a ~96 MB cache budget)
+ *   SDMM_OPT_CG_CHECK  iterations between host convergence checks (1..1024)
+ *   SDMM_OPT_CG_GRAPH  1 = replay the iteration group as a captured HIP graph
+ * Results do not depend on any of them. */
+#define SDMM_OPT_CG_CHUNK 0
+#define SDMM_OPT_CG_CHECK 1
+#define SDMM_OPT_CG_GRAPH 2
+int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value);
 int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out);
 
 #ifdef __cplusplus

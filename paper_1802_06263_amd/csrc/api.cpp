@@ -65,9 +65,22 @@ struct sdmm_ctx {
     DevBuf d_sub_ker, d_sub_Gcol, d_sub_Abase, d_sub_nlocal, d_pair_sub, d_pair_k, d_acc, d_lam1, d_lam2, d_wsum;
     DevBuf d_unit_of_dk, d_dnlocal, d_dAbase, d_cell_out, d_edge_out, d_sAbase, d_u_out, d_p_out;
     DevBuf d_mom;  // p1 p2 u1 u2 for moments output
+    DevBuf d_flag; // index validation flag
     // CG workspace
     DevBuf w_r, w_p, w_Ap, w_rr, w_r0, w_iters, w_relres, w_status, w_active, w_any, w_alpha, w_Slam;
     int64_t w_cap = 0;
+    // realization groups of the current chunk (grouped operator)
+    DevBuf d_work, d_perm, d_awork, d_slot, d_part, d_item0, d_pos, w_Y;
+    std::vector<int4> h_work, h_awork;
+    std::vector<int> h_perm, h_item0;
+    std::vector<int64_t> h_gidx, h_slot;
+    int nwork = 0, nawork = 0;
+    int64_t SR = 0, part_total = 0;
+    // tuning options (sdmm_set_option)
+    int64_t opt_chunk = 0;   // realizations per CG chunk, 0 = from the cache budget
+    int opt_check = 16;      // iterations between convergence checks
+    int opt_graph = 1;       // capture the iteration group in a HIP graph
+    hipStream_t cap_stream = nullptr;
     sdmm_counters counters{};
     hipEvent_t ev[6] = {};
 };
@@ -348,6 +361,9 @@ int setup_device(sdmm_ctx* ctx) {
     for (int i = 0; i < nsub; ++i) ctx->max_ext = std::max(ctx->max_ext, ctx->sub_R[i] + ctx->sub_ker[i]);
     if ((size_t)64 * ctx->max_ext * 8 > 150 * 1024) return fail(ctx, SDMM_EINVAL, "too many mortar DOFs on one subdomain");
     if (P.n_kernel > 16) return fail(ctx, SDMM_EINVAL, "more than 16 FETI kernel modes");
+    if (P.M > 256 * 8) return fail(ctx, SDMM_EINVAL, "more than 2048 mortar DOFs");
+    if ((size_t)(64 * (ctx->max_R + 1) + 64 * ctx->max_R) * 8 > 160 * 1024)
+        return fail(ctx, SDMM_EINVAL, "too many mortar DOFs on one subdomain for the grouped operator");
     ctx->n_trip = (int64_t)tr_v.size();
     ctx->S_total = S_off;
     ctx->X_total = X_off;
@@ -395,6 +411,20 @@ int setup_device(sdmm_ctx* ctx) {
     std::vector<int64_t> dofs(P.sub_dofs.begin(), P.sub_dofs.end());
     UP(ctx->d_sub_dofs, dofs);
     UP(ctx->d_sub_dof_ptr, P.sub_ptr);
+    {
+        // the two subdomain-local positions of every mortar DOF, lower subdomain first
+        std::vector<int> pos((size_t)2 * P.M, -1);
+        for (size_t q = 0; q < P.sub_dofs.size(); ++q) {
+            const int64_t m = P.sub_dofs[q];
+            if (pos[2 * m] < 0) pos[2 * m] = (int)q;
+            else if (pos[2 * m + 1] < 0) pos[2 * m + 1] = (int)q;
+            else return fail(ctx, SDMM_EINVAL, "a mortar DOF belongs to more than two subdomains");
+        }
+        for (int m = 0; m < P.M; ++m)
+            if (pos[2 * m + 1] < 0) return fail(ctx, SDMM_EINVAL, "a mortar DOF belongs to one subdomain only");
+        UP(ctx->d_pos, pos);
+        ctx->SR = P.sub_ptr[nsub];
+    }
     UP(ctx->d_sub_R, ctx->sub_R);
     UP(ctx->d_sub_region, ctx->sub_region);
     UP(ctx->d_sub_Sbase, ctx->sub_Sbase);
@@ -431,6 +461,7 @@ int setup_device(sdmm_ctx* ctx) {
     if ((rc = alloc(ctx, ctx->d_lam2, (size_t)P.M * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_wsum, 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_refine, 16))) return rc;
+    if ((rc = alloc(ctx, ctx->d_flag, 8))) return rc;
     int64_t mom = 2 * (ctx->field_size[1] + ctx->field_size[2] + ctx->field_size[3] + ctx->field_size[4]);
     if ((rc = alloc(ctx, ctx->d_mom, (size_t)std::max<int64_t>(mom, 1) * 8))) return rc;
     // Stokes RHS into the padded band layout
@@ -548,12 +579,93 @@ CgArgs cg_args(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double* lam) {
 // device before any kernel dereferences the global->local table.
 int check_indices(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
     int32_t bad = 0;
-    HIPCHK(hipMemsetAsync(ctx->w_any.p, 0, 4, st));
-    HIPCHK(launch_validate_index(gidx, n, ctx->P.nreal, ctx->w_any.as<int32_t>(), st));
-    HIPCHK(hipMemcpyAsync(&bad, ctx->w_any.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemsetAsync(ctx->d_flag.p, 0, 4, st));
+    HIPCHK(launch_validate_index(gidx, n, ctx->P.nreal, ctx->d_flag.as<int32_t>(), st));
+    HIPCHK(hipMemcpyAsync(&bad, ctx->d_flag.p, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (bad) return fail(ctx, SDMM_EINVAL, "a global collocation index is out of range");
     return SDMM_OK;
+}
+
+// Sort the batch by local realization index, region by region, and cut the
+// (subdomain, local realization) groups into chunks of at most 64
+// realizations (moment work items) and 64 rows of S (operator work items).
+int prepare_groups(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
+    const Problem& P = ctx->P;
+    ctx->h_gidx.resize(n);
+    HIPCHK(hipMemcpyAsync(ctx->h_gidx.data(), gidx, n * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->h_perm.clear();
+    ctx->h_work.clear();
+    ctx->h_awork.clear();
+    ctx->h_slot.clear();
+    ctx->h_item0.clear();
+    const int nr = P.n_region;
+    std::vector<int64_t> rbase(nr + 1);
+    std::vector<std::vector<int64_t>> goff(nr);
+    for (int r = 0; r < nr; ++r) {
+        rbase[r] = (int64_t)ctx->h_perm.size();
+        const int L = P.nlocal[r];
+        goff[r].assign(L + 1, 0);
+        for (int64_t l = 0; l < n; ++l) goff[r][P.g2l[(size_t)ctx->h_gidx[l] * nr + r] + 1]++;
+        for (int k = 0; k < L; ++k) goff[r][k + 1] += goff[r][k];
+        std::vector<int64_t> fill(goff[r].begin(), goff[r].end() - 1);
+        ctx->h_perm.resize(ctx->h_perm.size() + n);
+        for (int64_t l = 0; l < n; ++l) {
+            const int k = P.g2l[(size_t)ctx->h_gidx[l] * nr + r];
+            ctx->h_perm[rbase[r] + fill[k]++] = (int)l;
+        }
+    }
+    rbase[nr] = (int64_t)ctx->h_perm.size();
+    for (int64_t l = 0; l < n; ++l) ctx->h_perm.push_back((int)l);  // Stokes: every realization
+    if ((int64_t)ctx->h_perm.size() > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
+    int64_t slot = 0;
+    for (size_t pidx = 0; pidx < ctx->pair_sub.size(); ++pidx) {
+        const int i = ctx->pair_sub[pidx], k = ctx->pair_k[pidx];
+        const int R = ctx->sub_R[i];
+        const int r = ctx->sub_region[i];
+        const int ext = R + ctx->sub_ker[i];
+        const int64_t g0 = r >= 0 ? goff[r][k] : 0, g1 = r >= 0 ? goff[r][k + 1] : n;
+        const int64_t base = r >= 0 ? rbase[r] : rbase[nr];
+        ctx->h_item0.push_back((int)ctx->h_awork.size());
+        for (int64_t c0 = g0; c0 < g1; c0 += 64) {
+            const int cnt = (int)std::min<int64_t>(64, g1 - c0);
+            for (int row0 = 0; row0 < R; row0 += 64)
+                ctx->h_work.push_back(make_int4(i, k, row0 | (cnt << 16), (int)(base + c0)));
+            ctx->h_awork.push_back(make_int4(i, k, cnt, (int)(base + c0)));
+            ctx->h_slot.push_back(slot);
+            slot += (int64_t)ext + (int64_t)ext * ext;
+        }
+    }
+    ctx->h_item0.push_back((int)ctx->h_awork.size());
+    ctx->nwork = (int)ctx->h_work.size();
+    ctx->nawork = (int)ctx->h_awork.size();
+    ctx->part_total = slot;
+    int rc;
+    auto grow = [&](DevBuf& b, size_t bytes) { return b.bytes < bytes ? alloc(ctx, b, bytes) : SDMM_OK; };
+    if ((rc = grow(ctx->d_perm, ctx->h_perm.size() * 4))) return rc;
+    if ((rc = grow(ctx->d_work, ctx->h_work.size() * 16))) return rc;
+    if ((rc = grow(ctx->d_awork, ctx->h_awork.size() * 16))) return rc;
+    if ((rc = grow(ctx->d_slot, ctx->h_slot.size() * 8))) return rc;
+    if ((rc = grow(ctx->d_item0, ctx->h_item0.size() * 4))) return rc;
+    HIPCHK(hipMemcpyAsync(ctx->d_perm.p, ctx->h_perm.data(), ctx->h_perm.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->d_work.p, ctx->h_work.data(), ctx->h_work.size() * 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->d_awork.p, ctx->h_awork.data(), ctx->h_awork.size() * 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->d_slot.p, ctx->h_slot.data(), ctx->h_slot.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->d_item0.p, ctx->h_item0.data(), ctx->h_item0.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));  // the host vectors are reused by the next chunk
+    return SDMM_OK;
+}
+
+// Realizations per CG chunk: the chunk's vectors (lambda, r, p and the
+// subdomain-local operator results) are kept within ~96 MB so that they stay
+// resident in the 256 MB Infinity Cache across iterations.
+int64_t chunk_size(sdmm_ctx* ctx, int64_t n) {
+    if (ctx->opt_chunk > 0) return std::min<int64_t>(n, ctx->opt_chunk);
+    const int64_t per = (3 * (int64_t)ctx->P.M + ctx->SR) * 8 + 64;
+    int64_t c = std::max<int64_t>(256, (int64_t)(96.0 * 1024 * 1024) / per);
+    const int64_t nch = (n + c - 1) / c;
+    return (n + nch - 1) / nch;
 }
 
 int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
@@ -561,7 +673,7 @@ int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
     const size_t M = ctx->P.M;
     int rc;
     if ((rc = alloc(ctx, ctx->w_r, n * M * 8))) return rc;
-    if ((rc = alloc(ctx, ctx->w_p, n * M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_p, n * (size_t)std::max<int64_t>(M, ctx->SR) * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_Ap, n * M * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_Slam, n * M * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_rr, n * 8))) return rc;
@@ -572,6 +684,7 @@ int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
     if ((rc = alloc(ctx, ctx->w_active, n * 4))) return rc;
     if ((rc = alloc(ctx, ctx->w_any, 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_alpha, n * std::max(1, ctx->P.n_kernel) * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_Y, (size_t)n * ctx->SR * 8))) return rc;
     ctx->w_cap = n;
     return SDMM_OK;
 }
@@ -614,6 +727,7 @@ int sdmm_destroy(sdmm_ctx* ctx) {
     }
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
@@ -787,6 +901,106 @@ int sdmm_get_basis(sdmm_ctx* ctx, int sub, int k, double* S, int64_t ld) {
     return SDMM_OK;
 }
 
+int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value) {
+    if (!ctx) return SDMM_EINVAL;
+    switch (option) {
+        case SDMM_OPT_CG_CHUNK:
+            if (value < 0) return fail(ctx, SDMM_EINVAL, "chunk must be >= 0");
+            ctx->opt_chunk = value;
+            return SDMM_OK;
+        case SDMM_OPT_CG_CHECK:
+            if (value < 1 || value > 1024) return fail(ctx, SDMM_EINVAL, "check interval must be in 1..1024");
+            ctx->opt_check = (int)value;
+            return SDMM_OK;
+        case SDMM_OPT_CG_GRAPH:
+            ctx->opt_graph = value ? 1 : 0;
+            return SDMM_OK;
+        default:
+            return fail(ctx, SDMM_EINVAL, "unknown option");
+    }
+}
+
+namespace {
+
+// One chunk of realizations through CG (all on stream st).
+int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, double* lambda,
+                int32_t* iters, double* relres, int32_t* status, hipStream_t st, int64_t& tot_it, bool& bad,
+                bool& brk) {
+    int rc;
+    if ((rc = prepare_groups(ctx, gidx, n, st))) return rc;
+    CgArgs a = cg_args(ctx, n, gidx, lambda);
+    a.rtol = rtol;
+    a.max_iter = max_iter;
+    double* Y = ctx->w_Y.as<double>();
+    const int* pos = ctx->d_pos.as<int>();
+    HIPCHK(launch_cg_init(a, st));
+    // search direction p_0 = r_0 in the subdomain-local layout
+    HIPCHK(launch_scatter_local(a.r, ctx->SR, pos, ctx->P.M, n, a.p, st));
+    const int group = ctx->opt_check;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    auto body = [&](hipStream_t s) -> hipError_t {
+        for (int q = 0; q < group; ++q) {
+            hipError_t e = launch_cg_apply_mfma(a, a.p, Y, ctx->SR, ctx->d_work.as<int4>(), ctx->nwork,
+                                                ctx->d_perm.as<int>(), ctx->max_R, s);
+            if (e != hipSuccess) return e;
+            e = launch_cg_update2(a, Y, ctx->SR, pos, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (ctx->opt_graph) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = body(st);
+        hipError_t e2 = hipStreamEndCapture(st, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(ctx, SDMM_EDEVICE, "graph capture of the CG iterations failed");
+        }
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(ctx, SDMM_EDEVICE, "graph instantiation failed");
+        }
+    }
+    int it = 0;
+    int32_t any = 1;
+    while (it < max_iter) {
+        HIPCHK(hipMemsetAsync(a.any_active, 0, 4, st));
+        if (exec) {
+            HIPCHK(hipGraphLaunch(exec, st));
+        } else {
+            HIPCHK(body(st));
+        }
+        it += group;
+        HIPCHK(hipMemcpyAsync(&any, a.any_active, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!any) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    HIPCHK(launch_cg_finish(a, lambda, iters, relres, status, st));
+    std::vector<int32_t> stv(n), itv(n);
+    HIPCHK(hipMemcpyAsync(stv.data(), a.status, n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(itv.data(), a.iters, n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t l = 0; l < n; ++l) {
+        tot_it += itv[l];
+        bad |= stv[l] != SDMM_CG_CONVERGED;
+        brk |= stv[l] == SDMM_CG_BREAKDOWN;
+    }
+    return SDMM_OK;
+}
+
+hipStream_t work_stream(sdmm_ctx* ctx, hipStream_t user) {
+    // graph capture needs a stream other than the legacy null stream
+    if (!ctx->opt_graph) return user;
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        ctx->cap_stream = nullptr;
+    return ctx->cap_stream ? ctx->cap_stream : user;
+}
+
+}  // namespace
+
 int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, double* lambda,
                          int32_t* iters, double* relres, int32_t* status, void* stream) {
     if (!ctx) return SDMM_EINVAL;
@@ -797,41 +1011,27 @@ int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double r
     if (n == 0) return SDMM_OK;
     if (n > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
     HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
-    int rc = ensure_workspace(ctx, n);
-    if (rc) return rc;
+    hipStream_t user = (hipStream_t)stream;
+    hipStream_t st = work_stream(ctx, user);
+    HIPCHK(hipEventRecord(ctx->ev[5], user));
+    HIPCHK(hipStreamWaitEvent(st, ctx->ev[5], 0));
+    int rc;
     if ((rc = check_indices(ctx, gidx, n, st))) return rc;
-    CgArgs a = cg_args(ctx, n, gidx, lambda);
-    a.rtol = rtol;
-    a.max_iter = max_iter;
+    const int64_t chunk = chunk_size(ctx, n);
+    if ((rc = ensure_workspace(ctx, chunk))) return rc;
     HIPCHK(hipEventRecord(ctx->ev[3], st));
-    HIPCHK(launch_cg_init(a, st));
-    int it = 0;
-    int32_t any = 1;
-    const int group = 8;
-    while (it < max_iter) {
-        HIPCHK(hipMemsetAsync(a.any_active, 0, 4, st));
-        for (int q = 0; q < group && it < max_iter; ++q, ++it) {
-            HIPCHK(launch_cg_apply(a, a.p, a.Ap, ctx->max_R, true, st));
-            HIPCHK(launch_cg_update(a, it, st));
-        }
-        HIPCHK(hipMemcpyAsync(&any, a.any_active, 4, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (!any) break;
-    }
-    HIPCHK(launch_cg_finish(a, lambda, iters, relres, status, st));
-    HIPCHK(hipEventRecord(ctx->ev[4], st));
-    std::vector<int32_t> stv(n), itv(n);
-    HIPCHK(hipMemcpyAsync(stv.data(), a.status, n * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(itv.data(), a.iters, n * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
     int64_t tot = 0;
     bool bad = false, brk = false;
-    for (int64_t l = 0; l < n; ++l) {
-        tot += itv[l];
-        bad |= stv[l] != SDMM_CG_CONVERGED;
-        brk |= stv[l] == SDMM_CG_BREAKDOWN;
+    const int M = ctx->P.M;
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int64_t cn = std::min(chunk, n - c0);
+        rc = solve_chunk(ctx, cn, gidx + c0, rtol, max_iter, lambda + c0 * M, iters ? iters + c0 : nullptr,
+                         relres ? relres + c0 : nullptr, status ? status + c0 : nullptr, st, tot, bad, brk);
+        if (rc) return rc;
     }
+    HIPCHK(hipEventRecord(ctx->ev[4], st));
+    HIPCHK(hipStreamWaitEvent(user, ctx->ev[4], 0));
+    HIPCHK(hipStreamSynchronize(st));
     ctx->counters.cg_iterations += tot;
     ctx->counters.realizations += n;
     float ms = 0;
@@ -850,41 +1050,57 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const
     if (n == 0) return SDMM_OK;
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    int rc = ensure_workspace(ctx, n);
-    if (rc) return rc;
+    int rc;
     if ((rc = check_indices(ctx, gidx, n, st))) return rc;
-    CgArgs a = cg_args(ctx, n, gidx, const_cast<double*>(lambda));
-    if (ctx->P.n_kernel > 0) {
-        HIPCHK(hipMemsetAsync(ctx->w_Slam.p, 0, (size_t)n * ctx->P.M * 8, st));
-        HIPCHK(launch_cg_apply(a, lambda, ctx->w_Slam.as<double>(), ctx->max_R, false, st));
-        HIPCHK(launch_alpha(a, ctx->w_Slam.as<double>(), ctx->w_alpha.as<double>(), st));
+    const int64_t chunk = chunk_size(ctx, n);
+    if ((rc = ensure_workspace(ctx, chunk))) return rc;
+    const int M = ctx->P.M;
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int64_t cn = std::min(chunk, n - c0);
+        const int64_t* g = gidx + c0;
+        const double* lam = lambda + c0 * M;
+        if ((rc = prepare_groups(ctx, g, cn, st))) return rc;
+        CgArgs a = cg_args(ctx, cn, g, const_cast<double*>(lam));
+        if (ctx->P.n_kernel > 0) {
+            HIPCHK(launch_scatter_local(lam, ctx->SR, ctx->d_pos.as<int>(), M, cn, ctx->w_p.as<double>(), st));
+            HIPCHK(launch_cg_apply_mfma(a, ctx->w_p.as<double>(), ctx->w_Y.as<double>(), ctx->SR,
+                                        ctx->d_work.as<int4>(), ctx->nwork, ctx->d_perm.as<int>(), ctx->max_R, st));
+            HIPCHK(launch_gather_global(ctx->w_Y.as<double>(), ctx->SR, ctx->d_pos.as<int>(), M, cn,
+                                        ctx->w_Slam.as<double>(), st));
+            HIPCHK(launch_alpha(a, ctx->w_Slam.as<double>(), ctx->w_alpha.as<double>(), st));
+        }
+        if (ctx->d_part.bytes < (size_t)ctx->part_total * 8 && (rc = alloc(ctx, ctx->d_part, ctx->part_total * 8)))
+            return rc;
+        MomArgs m{};
+        m.n = cn;
+        m.M = M;
+        m.nsub = (int)ctx->P.subs.size();
+        m.nregion = ctx->P.n_region;
+        m.nker = ctx->P.n_kernel;
+        m.gidx = g;
+        m.g2l = ctx->d_g2l.as<int32_t>();
+        m.weights = weights ? weights + c0 : nullptr;
+        m.colloc_w = ctx->d_weights.as<double>();
+        m.lam = lam;
+        m.sub_R = ctx->d_sub_R.as<int>();
+        m.sub_dof_ptr = ctx->d_sub_dof_ptr.as<int64_t>();
+        m.sub_dofs = ctx->d_sub_dofs.as<int64_t>();
+        m.sub_region = ctx->d_sub_region.as<int>();
+        m.sub_ker = ctx->d_sub_ker.as<int>();
+        m.sub_Gcol = ctx->d_sub_Gcol.as<int>();
+        m.sub_Abase = ctx->d_sub_Abase.as<int64_t>();
+        m.sub_nlocal = ctx->d_sub_nlocal.as<int>();
+        m.alpha = ctx->w_alpha.as<double>();
+        m.acc = ctx->d_acc.as<double>();
+        m.lam1 = ctx->d_lam1.as<double>();
+        m.lam2 = ctx->d_lam2.as<double>();
+        m.wsum = ctx->d_wsum.as<double>();
+        HIPCHK(launch_accumulate_chunks(m, ctx->d_awork.as<int4>(), ctx->nawork, ctx->d_perm.as<int>(),
+                                        ctx->d_slot.as<int64_t>(), ctx->d_part.as<double>(), ctx->d_pair_sub.as<int>(),
+                                        ctx->d_pair_k.as<int>(), ctx->d_item0.as<int>(), (int)ctx->pair_sub.size(),
+                                        ctx->max_ext, st));
+        HIPCHK(hipStreamSynchronize(st));  // the group tables are rebuilt by the next chunk
     }
-    MomArgs m{};
-    m.n = n;
-    m.M = ctx->P.M;
-    m.nsub = (int)ctx->P.subs.size();
-    m.nregion = ctx->P.n_region;
-    m.nker = ctx->P.n_kernel;
-    m.gidx = gidx;
-    m.g2l = ctx->d_g2l.as<int32_t>();
-    m.weights = weights;
-    m.colloc_w = ctx->d_weights.as<double>();
-    m.lam = lambda;
-    m.sub_R = ctx->d_sub_R.as<int>();
-    m.sub_dof_ptr = ctx->d_sub_dof_ptr.as<int64_t>();
-    m.sub_dofs = ctx->d_sub_dofs.as<int64_t>();
-    m.sub_region = ctx->d_sub_region.as<int>();
-    m.sub_ker = ctx->d_sub_ker.as<int>();
-    m.sub_Gcol = ctx->d_sub_Gcol.as<int>();
-    m.sub_Abase = ctx->d_sub_Abase.as<int64_t>();
-    m.sub_nlocal = ctx->d_sub_nlocal.as<int>();
-    m.alpha = ctx->w_alpha.as<double>();
-    m.acc = ctx->d_acc.as<double>();
-    m.lam1 = ctx->d_lam1.as<double>();
-    m.lam2 = ctx->d_lam2.as<double>();
-    m.wsum = ctx->d_wsum.as<double>();
-    HIPCHK(launch_accumulate_pairs(m, ctx->d_pair_sub.as<int>(), ctx->d_pair_k.as<int>(), (int)ctx->pair_sub.size(),
-                                   ctx->max_ext, st));
     return SDMM_OK;
 }
 

@@ -904,21 +904,15 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
     __shared__ double coef[32];
     const int64_t l = blockIdx.x;
     double* r = a.r + l * a.M;
-    double* p = a.p + l * a.M;
     double* lam = a.lam + l * a.M;
-    double* Ap = a.Ap + l * a.M;
     for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
         r[m] = a.g[m];
         lam[m] = 0.0;
-        Ap[m] = 0.0;
     }
     __syncthreads();
     if (a.nker > 0) feti_project_row(a, r, red, coef);
     double part = 0.0;
-    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
-        p[m] = r[m];
-        part += r[m] * r[m];
-    }
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) part += r[m] * r[m];
     const double rr = block_sum(part, red);
     if (threadIdx.x == 0) {
         a.rr[l] = rr;
@@ -930,82 +924,263 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
     }
 }
 
-__global__ __launch_bounds__(kThreads) void cg_apply_kernel(CgArgs a, const double* __restrict__ x, double* __restrict__ y,
-                                                            int masked) {
-    extern __shared__ double xs[];
-    const int64_t l = blockIdx.x;
-    const int i = blockIdx.y;
-    if (masked && !a.active[l]) return;
+// Grouped operator: one workgroup per (subdomain i, local realization k,
+// 64-row block of S_{i,k}, chunk of <= 64 realizations whose local index in
+// i's KL region is k).  The row block of S and the gathered coefficients sit
+// in LDS; four waves compute the 64 x 64 product with FP64 MFMA (16x16x4,
+// 2 x 2 tiles per wave), so each S entry is read once per chunk.  Results go
+// to Y (n x sum_i R_i, subdomain-local layout) with plain stores; the CG
+// update adds the two contributions of every mortar DOF in a fixed order.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kThreads) void cg_apply_mfma_kernel(CgArgs a, const double* __restrict__ xloc,
+                                                                 double* __restrict__ Y, int64_t SR,
+                                                                 const int4* __restrict__ work,
+                                                                 const int* __restrict__ perm) {
+    constexpr int KC = 32;                       // k-chunk of S columns staged in LDS
+    __shared__ double St[KC * 64];               // St[j][r] = S[row0 + r][k0 + j]
+    __shared__ double Xs[KC * 65];               // Xs[j][c] = x_{l_c}[local DOF k0 + j], stride 65
+    __shared__ int64_t rowoff[64];
+    const int4 wk = work[blockIdx.x];   // (i, k, row0 | count << 16, perm offset)
+    const int i = wk.x, k = wk.y;
+    const int row0 = wk.z & 0xffff, count = wk.z >> 16;
     const int R = a.sub_R[i];
-    const int reg = a.sub_region[i];
-    const int k = reg >= 0 ? a.g2l[a.gidx[l] * a.nregion + reg] : 0;
+    const int nrow = min(64, R - row0);
     const double* S = a.S_cache + a.sub_Sbase[i] + (int64_t)k * R * R;
-    const int64_t* dofs = a.sub_dofs + a.sub_dof_ptr[i];
-    const double* xl = x + l * a.M;
-    for (int j = threadIdx.x; j < R; j += blockDim.x) xs[j] = xl[dofs[j]];
-    __syncthreads();
-    for (int m = threadIdx.x; m < R; m += blockDim.x) {
-        double v = 0.0;
-        for (int j = 0; j < R; ++j) v += S[(int64_t)j * R + m] * xs[j];
-        atomicAdd(&y[l * a.M + dofs[m]], v);
+    const int64_t dptr = a.sub_dof_ptr[i];
+    const int tid = threadIdx.x;
+    if (tid < 64) rowoff[tid] = tid < count ? (int64_t)perm[wk.w + tid] * SR + dptr : -1;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int cb = (wave >> 1) * 32, rb = (wave & 1) * 32;   // realizations x S-rows quadrant
+    const int li = lane & 15, lk = lane >> 4;
+    dbl4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
+    for (int k0 = 0; k0 < R; k0 += KC) {
+        __syncthreads();
+        // 8 independent loads per thread for each operand
+        double sv[8], xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + q * kThreads;
+            const int j = idx >> 6, r = idx & 63;
+            sv[q] = (k0 + j < R && r < nrow) ? S[(int64_t)(k0 + j) * R + row0 + r] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + q * kThreads;
+            const int c = idx >> 5, j = idx & 31;
+            const int64_t ro = rowoff[c];
+            xv[q] = (ro >= 0 && k0 + j < R) ? xloc[ro + k0 + j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = tid + q * kThreads;
+            St[idx] = sv[q];
+            Xs[(idx & 31) * 65 + (idx >> 5)] = xv[q];
+        }
+        __syncthreads();
+        // transposed product Y^T = X^T S^T: tile rows are realizations, columns
+        // are rows of S, so the 16 lanes of a group store 16 consecutive doubles
+#pragma unroll
+        for (int j0 = 0; j0 < KC; j0 += 4) {
+            const double x0 = Xs[(j0 + lk) * 65 + cb + li];
+            const double x1 = Xs[(j0 + lk) * 65 + cb + 16 + li];
+            const double s0 = St[(j0 + lk) * 64 + rb + li];
+            const double s1 = St[(j0 + lk) * 64 + rb + 16 + li];
+            c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, s0, c00, 0, 0, 0);
+            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, s1, c01, 0, 0, 0);
+            c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, s0, c10, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, s1, c11, 0, 0, 0);
+        }
+    }
+    // D[i][j] (i = realization, j = S row) sits at lane j + 16 (i % 4), register i / 4
+    const int jr = lane & 15, ig = lane >> 4;
+    const dbl4* tiles[4] = {&c00, &c01, &c10, &c11};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c_base = cb + (t >> 1) * 16, r = rb + (t & 1) * 16 + jr;
+        const dbl4 v = *tiles[t];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = c_base + 4 * q + ig;
+            if (c < count && r < nrow) Y[rowoff[c] + row0 + r] = v[q];
+        }
     }
 }
 
-__global__ __launch_bounds__(kThreads) void cg_update_kernel(CgArgs a, int iter) {
+hipError_t launch_cg_apply_mfma(const CgArgs& a, const double* x, double* Y, int64_t SR, const int4* work, int nwork,
+                                const int* perm, int max_R, hipStream_t stream) {
+    if (nwork <= 0) return hipSuccess;
+    (void)max_R;
+    hipLaunchKernelGGL(cg_apply_mfma_kernel, dim3(nwork), dim3(kThreads), 0, stream, a, x, Y, SR, work, perm);
+    return hipGetLastError();
+}
+
+// Scatter a global-layout vector to the subdomain-local layout (both copies
+// of every mortar DOF).
+__global__ void scatter_local_kernel(const double* __restrict__ x, int64_t SR, const int* __restrict__ pos, int M,
+                                     int64_t n, double* __restrict__ xloc) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n * M) return;
+    const int64_t l = q / M;
+    const int m = (int)(q - l * M);
+    const double v = x[q];
+    xloc[l * SR + pos[2 * m]] = v;
+    xloc[l * SR + pos[2 * m + 1]] = v;
+}
+
+hipError_t launch_scatter_local(const double* x, int64_t SR, const int* pos, int M, int64_t n, double* xloc,
+                                hipStream_t stream) {
+    const int64_t tot = n * M;
+    hipLaunchKernelGGL(scatter_local_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream, x, SR, pos, M,
+                       n, xloc);
+    return hipGetLastError();
+}
+
+
+// S x for the realizations of the batch into the global layout (used by the
+// moments for the FETI coefficients): y_m = Y[pos1(m)] + Y[pos2(m)].
+__global__ void gather_global_kernel(const double* __restrict__ Y, int64_t SR, const int* __restrict__ pos, int M,
+                                     int64_t n, double* __restrict__ y) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n * M) return;
+    const int64_t l = q / M;
+    const int m = (int)(q - l * M);
+    y[q] = Y[l * SR + pos[2 * m]] + Y[l * SR + pos[2 * m + 1]];
+}
+
+hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int M, int64_t n, double* y,
+                                hipStream_t stream) {
+    const int64_t tot = n * M;
+    hipLaunchKernelGGL(gather_global_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream, Y, SR, pos, M,
+                       n, y);
+    return hipGetLastError();
+}
+
+// CG update with the operator result gathered from Y.  One workgroup per
+// realization; the realization's iteration count lives in iters[l], so the
+// launch is identical every iteration (graph capture).  Every vector is read
+// once and kept in registers (M <= 256 * kMaxQ).
+constexpr int kMaxQ = 8;
+
+__global__ __launch_bounds__(kThreads) void cg_update2_kernel(CgArgs a, const double* __restrict__ Y, int64_t SR,
+                                                              const int* __restrict__ pos) {
     __shared__ double red[kThreads / 64];
     __shared__ double coef[32];
     const int64_t l = blockIdx.x;
     if (!a.active[l]) return;
-    double* r = a.r + l * a.M;
-    double* p = a.p + l * a.M;
-    double* lam = a.lam + l * a.M;
-    double* Ap = a.Ap + l * a.M;
-    if (a.nker > 0) feti_project_row(a, Ap, red, coef);
+    const int M = a.M, tid = threadIdx.x;
+    double* r = a.r + l * M;
+    double* pl = a.p + l * SR;   // search direction in the subdomain-local layout
+    double* lam = a.lam + l * M;
+    const double* Yl = Y + l * SR;
+    double ap[kMaxQ], pv[kMaxQ], rv[kMaxQ];
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) {
+        const int m = tid + q * kThreads;
+        ap[q] = pv[q] = rv[q] = 0.0;
+        if (m < M) {
+            ap[q] = Yl[pos[2 * m]] + Yl[pos[2 * m + 1]];
+            pv[q] = pl[pos[2 * m]];
+            rv[q] = r[m];
+        }
+    }
+    const int nk = a.nker;
+    if (nk > 0) {
+        // G^T ap: all nk sums reduced together (one pass through LDS)
+        __shared__ double redk[16][kThreads / 64];
+        for (int kk = 0; kk < nk; ++kk) {
+            double part = 0.0;
+#pragma unroll
+            for (int q = 0; q < kMaxQ; ++q) {
+                const int m = tid + q * kThreads;
+                if (m < M) part += a.G[(int64_t)kk * M + m] * ap[q];
+            }
+            part = wave_sum(part);
+            if ((tid & 63) == 0) redk[kk][tid >> 6] = part;
+        }
+        __syncthreads();
+        if (tid < nk) {
+            double s = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) s += redk[tid][w];
+            coef[tid] = s;
+        }
+        __syncthreads();
+        if (tid < nk) {
+            double d = 0.0;
+            for (int q = 0; q < nk; ++q) d += a.GtGinv[tid * nk + q] * coef[q];
+            coef[nk + tid] = d;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kMaxQ; ++q) {
+            const int m = tid + q * kThreads;
+            if (m < M) {
+                double c = 0.0;
+                for (int kk = 0; kk < nk; ++kk) c += a.G[(int64_t)kk * M + m] * coef[nk + kk];
+                ap[q] -= c;
+            }
+        }
+    }
     double part = 0.0;
-    for (int m = threadIdx.x; m < a.M; m += blockDim.x) part += p[m] * Ap[m];
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) part += pv[q] * ap[q];
     const double pAp = block_sum(part, red);
     const double rr = a.rr[l];
+    const int iter = a.iters[l];
     if (!(pAp > 0.0) || !isfinite(pAp)) {
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             a.status[l] = SDMM_CG_BREAKDOWN;
             a.active[l] = 0;
-            a.iters[l] = iter;
             a.relres[l] = a.r0[l] > 0 ? sqrt(rr) / a.r0[l] : 0.0;
         }
         return;
     }
     const double alpha = rr / pAp;
     part = 0.0;
-    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
-        lam[m] += alpha * p[m];
-        const double rv = r[m] - alpha * Ap[m];
-        r[m] = rv;
-        part += rv * rv;
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) {
+        const int m = tid + q * kThreads;
+        rv[q] -= alpha * ap[q];
+        part += rv[q] * rv[q];
+        if (m < M) {
+            lam[m] += alpha * pv[q];
+            r[m] = rv[q];
+        }
     }
     const double rrn = block_sum(part, red);
     const double rel = sqrt(rrn) / a.r0[l];
     const bool conv = rel <= a.rtol;
     const bool last = iter + 1 >= a.max_iter;
+    if (tid == 0) {
+        a.iters[l] = iter + 1;
+        a.relres[l] = rel;
+    }
     if (conv || last) {
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             a.status[l] = conv ? SDMM_CG_CONVERGED : SDMM_CG_MAXITER;
             a.active[l] = 0;
-            a.iters[l] = iter + 1;
-            a.relres[l] = rel;
         }
         return;
     }
     const double beta = rrn / rr;
-    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
-        p[m] = r[m] + beta * p[m];
-        Ap[m] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) {
+        const int m = tid + q * kThreads;
+        if (m < M) {
+            const double v = rv[q] + beta * pv[q];
+            pl[pos[2 * m]] = v;
+            pl[pos[2 * m + 1]] = v;
+        }
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         a.rr[l] = rrn;
-        a.iters[l] = iter + 1;
-        a.relres[l] = rel;
         *a.any_active = 1;
     }
+}
+
+hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream) {
+    hipLaunchKernelGGL(cg_update2_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, Y, SR, pos);
+    return hipGetLastError();
 }
 
 __global__ void cg_finish_kernel(CgArgs a, int32_t* iters_out, double* relres_out, int32_t* status_out) {
@@ -1029,17 +1204,6 @@ hipError_t launch_validate_index(const int64_t* gidx, int64_t n, int64_t nreal, 
 
 hipError_t launch_cg_init(const CgArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(cg_init_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_apply(const CgArgs& a, const double* x, double* y, int max_R, bool masked, hipStream_t stream) {
-    hipLaunchKernelGGL(cg_apply_kernel, dim3((unsigned)a.n, a.nsub), dim3(kThreads), max_R * sizeof(double), stream, a,
-                       x, y, masked ? 1 : 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_update(const CgArgs& a, int iter, hipStream_t stream) {
-    hipLaunchKernelGGL(cg_update_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, iter);
     return hipGetLastError();
 }
 
@@ -1086,29 +1250,64 @@ hipError_t launch_alpha(const CgArgs& a, const double* Slam, double* alpha, hipS
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kThreads) void accumulate_kernel(MomArgs m, const int* pair_sub, const int* pair_k) {
-    extern __shared__ double cs[];
-    const int i = pair_sub[blockIdx.x], k = pair_k[blockIdx.x];
+// Partial moment sums of one chunk of realizations that share (i, k):
+// a = sum_c w_c c and Mc = sum_c w_c c c^T over the chunk, written to the
+// chunk's own slot; moments_reduce adds the slots of every (i, k) in order.
+__global__ __launch_bounds__(kThreads) void accumulate_chunk_kernel(MomArgs m, const int4* __restrict__ awork,
+                                                                    const int* __restrict__ perm,
+                                                                    const int64_t* __restrict__ slot,
+                                                                    double* __restrict__ part) {
+    extern __shared__ double cs[];   // ext x 64 coefficients, then 64 weights
+    const int4 wk = awork[blockIdx.x];   // (i, k, count, perm offset)
+    const int i = wk.x, count = wk.z;
+    const int* pl = perm + wk.w;
     const int R = m.sub_R[i], nk = m.sub_ker[i], ext = R + nk;
-    const int reg = m.sub_region[i];
     const int64_t* dofs = m.sub_dofs + m.sub_dof_ptr[i];
-    double* acc = m.acc + m.sub_Abase[i] + (int64_t)k * (ext + ext * ext);
-    // each thread owns fixed entries of a (ext) and Mc (ext x ext)
-    for (int64_t l = 0; l < m.n; ++l) {
-        const int kl = reg >= 0 ? m.g2l[m.gidx[l] * m.nregion + reg] : 0;
-        if (kl != k) continue;
-        const double w = m.weights ? m.weights[l] : m.colloc_w[m.gidx[l]];
-        __syncthreads();
-        for (int q = threadIdx.x; q < ext; q += blockDim.x)
-            cs[q] = q < R ? m.lam[l * m.M + dofs[q]] : m.alpha[l * m.nker + m.sub_Gcol[i] + (q - R)];
-        __syncthreads();
-        for (int q = threadIdx.x; q < ext + ext * ext; q += blockDim.x) {
-            if (q < ext) acc[q] += w * cs[q];
-            else {
-                const int e = q - ext, a = e % ext, b = e / ext;
-                acc[q] += w * cs[a] * cs[b];
-            }
+    double* wc = cs + ext * 64;
+    for (int idx = threadIdx.x; idx < ext * 64; idx += blockDim.x) {
+        const int c = idx / ext, q = idx - c * ext;
+        double v = 0.0;
+        if (c < count) {
+            const int64_t l = pl[c];
+            v = q < R ? m.lam[l * m.M + dofs[q]] : m.alpha[l * m.nker + m.sub_Gcol[i] + (q - R)];
         }
+        cs[q * 64 + c] = v;
+    }
+    for (int c = threadIdx.x; c < 64; c += blockDim.x) {
+        double w = 0.0;
+        if (c < count) {
+            const int64_t l = pl[c];
+            w = m.weights ? m.weights[l] : m.colloc_w[m.gidx[l]];
+        }
+        wc[c] = w;
+    }
+    __syncthreads();
+    double* out = part + slot[blockIdx.x];
+    for (int q = threadIdx.x; q < ext + ext * ext; q += blockDim.x) {
+        double s = 0.0;
+        if (q < ext) {
+            for (int c = 0; c < count; ++c) s += wc[c] * cs[q * 64 + c];
+        } else {
+            const int e = q - ext, aa = e % ext, bb = e / ext;
+            for (int c = 0; c < count; ++c) s += wc[c] * cs[aa * 64 + c] * cs[bb * 64 + c];
+        }
+        out[q] = s;
+    }
+}
+
+__global__ void moments_reduce_kernel(MomArgs m, const int* __restrict__ pair_sub, const int* __restrict__ pair_k,
+                                      const int* __restrict__ pair_item0, const int64_t* __restrict__ slot,
+                                      const double* __restrict__ part) {
+    const int pidx = blockIdx.x;
+    const int i = pair_sub[pidx], k = pair_k[pidx];
+    const int R = m.sub_R[i], ext = R + m.sub_ker[i];
+    const int n_e = ext + ext * ext;
+    double* acc = m.acc + m.sub_Abase[i] + (int64_t)k * n_e;
+    const int it0 = pair_item0[pidx], it1 = pair_item0[pidx + 1];
+    for (int q = blockIdx.y * blockDim.x + threadIdx.x; q < n_e; q += gridDim.y * blockDim.x) {
+        double s = 0.0;
+        for (int it = it0; it < it1; ++it) s += part[slot[it] + q];
+        acc[q] += s;
     }
 }
 
@@ -1132,11 +1331,15 @@ __global__ void lam_moments_kernel(MomArgs m) {
     }
 }
 
-hipError_t launch_accumulate_pairs(const MomArgs& m, const int* pair_sub, const int* pair_k, int npairs, int max_ext,
-                                   hipStream_t stream) {
-    if (npairs > 0)
-        hipLaunchKernelGGL(accumulate_kernel, dim3(npairs), dim3(kThreads), max_ext * sizeof(double), stream, m,
-                           pair_sub, pair_k);
+hipError_t launch_accumulate_chunks(const MomArgs& m, const int4* awork, int nawork, const int* perm,
+                                    const int64_t* slot, double* part, const int* pair_sub, const int* pair_k,
+                                    const int* pair_item0, int npairs, int max_ext, hipStream_t stream) {
+    if (nawork > 0) {
+        hipLaunchKernelGGL(accumulate_chunk_kernel, dim3(nawork), dim3(kThreads), (size_t)(max_ext + 1) * 64 * 8,
+                           stream, m, awork, perm, slot, part);
+        hipLaunchKernelGGL(moments_reduce_kernel, dim3(npairs, 16), dim3(256), 0, stream, m, pair_sub, pair_k,
+                           pair_item0, slot, part);
+    }
     hipLaunchKernelGGL(lam_moments_kernel, dim3((m.M + 255) / 256), dim3(256), 0, stream, m);
     return hipGetLastError();
 }

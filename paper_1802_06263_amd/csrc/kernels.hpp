@@ -114,8 +114,13 @@ struct CgArgs {
 
 hipError_t launch_validate_index(const int64_t* gidx, int64_t n, int64_t nreal, int32_t* bad, hipStream_t stream);
 hipError_t launch_cg_init(const CgArgs& a, hipStream_t stream);
-hipError_t launch_cg_apply(const CgArgs& a, const double* x, double* y, int max_R, bool masked, hipStream_t stream);
-hipError_t launch_cg_update(const CgArgs& a, int iter, hipStream_t stream);
+hipError_t launch_cg_apply_mfma(const CgArgs& a, const double* x, double* Y, int64_t SR, const int4* work, int nwork,
+                                const int* perm, int max_R, hipStream_t stream);
+hipError_t launch_scatter_local(const double* x, int64_t SR, const int* pos, int M, int64_t n, double* xloc,
+                                hipStream_t stream);
+hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int M, int64_t n, double* y,
+                                hipStream_t stream);
+hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream);
 hipError_t launch_cg_finish(const CgArgs& a, double* lam_out, int32_t* iters_out, double* relres_out,
                             int32_t* status_out, hipStream_t stream);
 
@@ -143,8 +148,9 @@ struct MomArgs {
     double* wsum;
 };
 hipError_t launch_alpha(const CgArgs& a, const double* Slam, double* alpha, hipStream_t stream);
-hipError_t launch_accumulate_pairs(const MomArgs& m, const int* pair_sub, const int* pair_k, int npairs, int max_ext,
-                                   hipStream_t stream);
+hipError_t launch_accumulate_chunks(const MomArgs& m, const int4* awork, int nawork, const int* perm,
+                                    const int64_t* slot, double* part, const int* pair_sub, const int* pair_k,
+                                    const int* pair_item0, int npairs, int max_ext, hipStream_t stream);
 hipError_t launch_darcy_moments_impl(const DarcyTables& t, const int* unit_of_dk, const int* d_nlocal, int n_darcy,
                                      int max_nout, int max_units_per_d, const int64_t* d_Abase, const double* acc,
                                      const double* X, int max_R, const int64_t* cell_out_off,

@@ -67,7 +67,9 @@ EXPORTS = {
     "sdmm_get_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _f64p, _f64p]),
     "sdmm_reset_moments": (ctypes.c_int, [ctypes.c_void_p]),
     "sdmm_get_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CCounters)]),
+    "sdmm_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
 }
+OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2}
 
 _LIB = None
 
@@ -251,6 +253,9 @@ class Context:
 
     def reset_moments(self):
         self._check(self.lib.sdmm_reset_moments(self.h))
+
+    def set_option(self, name, value):
+        self._check(self.lib.sdmm_set_option(self.h, OPTIONS[name], int(value)))
 
     def counters(self):
         c = CCounters()

@@ -144,3 +144,16 @@ def test_constant_permeability_closed_form():
     yc = (np.arange(8) + 0.5) / 8
     assert np.allclose(mp.reshape(2, 8, 8), yc[None, :, None], atol=1e-10)
     ctx.close()
+
+
+def test_cg_options_do_not_change_results(cfg0):
+    print("case: cfg0 chunking / graph options", flush=True)
+    ctx = gpu_ctx(cfg0.prob, "fp64")
+    _, ref, *_ = gpu_solve(ctx, np.arange(16), rtol=1e-10)
+    ref = ref.cpu().numpy()
+    for opts in ({"cg_chunk": 5}, {"cg_graph": 0, "cg_check": 3}, {"cg_chunk": 1, "cg_graph": 1, "cg_check": 7}):
+        for k, v in opts.items():
+            ctx.set_option(k, v)
+        _, lam, *_ = gpu_solve(ctx, np.arange(16), rtol=1e-10)
+        assert np.array_equal(lam.cpu().numpy(), ref), opts
+    ctx.close()
