@@ -55,12 +55,14 @@ struct sdmm_ctx {
     std::vector<int64_t> cell_out_off, edge_out_off, u_out_off, p_out_off;
     std::vector<int> pair_sub, pair_k;
     // device buffers
+    DevBuf d_meint;
     DevBuf d_dar, d_units, d_be_cell, d_be_kind, d_be_len, d_be_hperp, d_be_medge, d_be_sgn, d_cell_be, d_Pi, d_phi,
         d_xi, d_supp_ptr, d_supp_e, d_supp_v, d_me_cell;
-    DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_refine;
+    DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_E, d_refine;
     DevBuf d_sdev, d_tiles, d_rhs, d_U, d_P, d_bmap, d_Z, d_q_ptr, d_q_col, d_q_val, d_uD, d_uD_off, d_tr_sub, d_tr_r,
         d_tr_c, d_tr_v;
-    DevBuf d_g, d_G, d_GtGinv;
+    DevBuf d_g, d_G, d_GtGinv, d_Grow, d_Gval;
+    int nGrow = 0;
     DevBuf d_sub_R, d_sub_dof_ptr, d_sub_dofs, d_sub_region, d_sub_Sbase, d_g2l, d_weights;
     DevBuf d_sub_ker, d_sub_Gcol, d_sub_Abase, d_sub_nlocal, d_pair_sub, d_pair_k, d_acc, d_lam1, d_lam2, d_wsum;
     DevBuf d_unit_of_dk, d_dnlocal, d_dAbase, d_cell_out, d_edge_out, d_sAbase, d_u_out, d_p_out;
@@ -145,7 +147,7 @@ int setup_device(sdmm_ctx* ctx) {
     const int nsub = (int)P.subs.size();
     // ---- Darcy tables and units
     std::vector<DarcyDev> dar;
-    std::vector<int> be_cell, be_kind, be_medge, be_sgn, cell_be, supp_ptr, supp_e, me_cell;
+    std::vector<int> be_cell, be_kind, be_medge, be_sgn, cell_be, supp_ptr, supp_e, me_cell, meint;
     std::vector<double> be_len, be_hperp, Pi, phi, supp_v;
     std::vector<double> xi;
     std::vector<int64_t> region_xi_off(P.n_region);
@@ -219,6 +221,18 @@ int setup_device(sdmm_ctx* ctx) {
             }
         }
         cell_be.insert(cell_be.end(), cb.begin(), cb.end());
+        {
+            // mortar edges of every cell in the factor's internal order
+            std::vector<int> mi((size_t)2 * h.N, -1);
+            for (size_t e = 0; e < h.be_cell.size(); ++e) {
+                if (h.be_medge[e] < 0) continue;
+                const int c = h.be_cell[e];
+                const int ci = h.swap ? (c % h.nx) * h.ny + c / h.nx : c;
+                if (mi[2 * ci] < 0) mi[2 * ci] = h.be_medge[e];
+                else mi[2 * ci + 1] = h.be_medge[e];
+            }
+            meint.insert(meint.end(), mi.begin(), mi.end());
+        }
         // support lists: for every mortar DOF, the mortar edges where its average is non-zero
         int base = (int)supp_e.size();
         std::vector<std::vector<std::pair<int, double>>> sl(h.R);
@@ -257,9 +271,11 @@ int setup_device(sdmm_ctx* ctx) {
             u.off_X = X_off;
             u.off_L = L_off;
             u.off_T = T_off;
+            // the blocked factor pads rows to a multiple of 16 and the band to bp
+            const int64_t Np = (h.N + 15) / 16 * 16, bp = (h.b + 15) / 16 * 16;
             S_off += (int64_t)h.R * h.R;
-            X_off += (int64_t)h.N * h.R;
-            L_off += (int64_t)h.N * (h.b + 1);
+            X_off += Np * h.R;
+            L_off += Np * (bp + 1);
             T_off += (int64_t)4 * h.N + h.n_medge;
             A_off += (int64_t)h.R + (int64_t)h.R * h.R;
             ctx->units.push_back(u);
@@ -277,7 +293,7 @@ int setup_device(sdmm_ctx* ctx) {
         edge_tot += (int64_t)(h.nx + 1) * h.ny + (int64_t)h.nx * (h.ny + 1);
     }
     ctx->n_units = (int64_t)ctx->units.size();
-    if ((size_t)(ctx->max_b + 2) * (ctx->max_b + 1 + ctx->max_Rd) * 8 > 160 * 1024)
+    if (darcy_blocked_lds(ctx->max_b, ctx->max_Rd, 8) > 160 * 1024)
         return fail(ctx, SDMM_EINVAL, "a Darcy subdomain's band window does not fit in LDS (shorter side too long)");
     // ---- Stokes
     ctx->sdev.clear();
@@ -389,6 +405,7 @@ int setup_device(sdmm_ctx* ctx) {
     UP(ctx->d_be_medge, be_medge);
     UP(ctx->d_be_sgn, be_sgn);
     UP(ctx->d_cell_be, cell_be);
+    UP(ctx->d_meint, meint);
     UP(ctx->d_Pi, Pi);
     UP(ctx->d_phi, phi);
     UP(ctx->d_xi, xi);
@@ -539,6 +556,20 @@ int build_stokes(sdmm_ctx* ctx, hipStream_t st) {
                 }
         }
         HIPCHK(hipMemcpy(ctx->d_GtGinv.p, Inv.data(), Inv.size() * 8, hipMemcpyHostToDevice));
+        // rows of G that are not zero (the mortar DOFs of floating subdomains)
+        std::vector<int> rows;
+        std::vector<double> vals;
+        for (int m = 0; m < P.M; ++m) {
+            bool nz = false;
+            for (int k = 0; k < nk; ++k) nz |= G[(size_t)k * P.M + m] != 0.0;
+            if (!nz) continue;
+            rows.push_back(m);
+            for (int k = 0; k < nk; ++k) vals.push_back(G[(size_t)k * P.M + m]);
+        }
+        int rc;
+        if ((rc = upload(ctx, ctx->d_Grow, rows))) return rc;
+        if ((rc = upload(ctx, ctx->d_Gval, vals))) return rc;
+        ctx->nGrow = (int)rows.size();
     }
     return SDMM_OK;
 }
@@ -572,6 +603,9 @@ CgArgs cg_args(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double* lam) {
     a.status = ctx->w_status.as<int32_t>();
     a.active = ctx->w_active.as<int32_t>();
     a.any_active = ctx->w_any.as<int32_t>();
+    a.Grow = ctx->d_Grow.as<int>();
+    a.Gval = ctx->d_Gval.as<double>();
+    a.nGrow = ctx->nGrow;
     return a;
 }
 
@@ -590,11 +624,25 @@ int check_indices(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st)
 // Sort the batch by local realization index, region by region, and cut the
 // (subdomain, local realization) groups into chunks of at most 64
 // realizations (moment work items) and 64 rows of S (operator work items).
-int prepare_groups(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
-    const Problem& P = ctx->P;
+int fetch_gidx(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
     ctx->h_gidx.resize(n);
     HIPCHK(hipMemcpyAsync(ctx->h_gidx.data(), gidx, n * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    return SDMM_OK;
+}
+
+// subset: positions (into the fetched batch) of the realizations to include;
+// null means all n.
+int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, hipStream_t st) {
+    const Problem& P = ctx->P;
+    std::vector<int> all;
+    if (!subset) {
+        all.resize(n);
+        for (int64_t l = 0; l < n; ++l) all[l] = (int)l;
+        subset = &all;
+    }
+    const std::vector<int>& sel = *subset;
+    n = (int64_t)sel.size();
     ctx->h_perm.clear();
     ctx->h_work.clear();
     ctx->h_awork.clear();
@@ -607,17 +655,17 @@ int prepare_groups(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st
         rbase[r] = (int64_t)ctx->h_perm.size();
         const int L = P.nlocal[r];
         goff[r].assign(L + 1, 0);
-        for (int64_t l = 0; l < n; ++l) goff[r][P.g2l[(size_t)ctx->h_gidx[l] * nr + r] + 1]++;
+        for (int64_t q = 0; q < n; ++q) goff[r][P.g2l[(size_t)ctx->h_gidx[sel[q]] * nr + r] + 1]++;
         for (int k = 0; k < L; ++k) goff[r][k + 1] += goff[r][k];
         std::vector<int64_t> fill(goff[r].begin(), goff[r].end() - 1);
         ctx->h_perm.resize(ctx->h_perm.size() + n);
-        for (int64_t l = 0; l < n; ++l) {
-            const int k = P.g2l[(size_t)ctx->h_gidx[l] * nr + r];
-            ctx->h_perm[rbase[r] + fill[k]++] = (int)l;
+        for (int64_t q = 0; q < n; ++q) {
+            const int k = P.g2l[(size_t)ctx->h_gidx[sel[q]] * nr + r];
+            ctx->h_perm[rbase[r] + fill[k]++] = sel[q];
         }
     }
     rbase[nr] = (int64_t)ctx->h_perm.size();
-    for (int64_t l = 0; l < n; ++l) ctx->h_perm.push_back((int)l);  // Stokes: every realization
+    for (int64_t q = 0; q < n; ++q) ctx->h_perm.push_back(sel[q]);  // Stokes: every realization
     if ((int64_t)ctx->h_perm.size() > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
     int64_t slot = 0;
     for (size_t pidx = 0; pidx < ctx->pair_sub.size(); ++pidx) {
@@ -853,18 +901,20 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
     DarcyTables t = darcy_tables(ctx);
     HIPCHK(hipEventRecord(ctx->ev[0], st));
     if (precision == SDMM_PREC_FP64) {
-        HIPCHK(launch_darcy_basis_fp64(t, (int)ctx->n_units, ctx->max_b, ctx->max_Rd, ctx->d_S.as<double>(),
-                                       ctx->d_X.as<double>(), ctx->d_L.as<double>(), ctx->d_T.as<double>(), st));
+        HIPCHK(launch_darcy_basis_blocked(t, (int)ctx->n_units, ctx->max_b, ctx->max_Rd, ctx->d_S.as<double>(),
+                                          ctx->d_X.as<double>(), ctx->d_L.as<double>(), ctx->d_T.as<double>(), st));
     } else {
         int rc;
         if (!ctx->d_L32.p && (rc = alloc(ctx, ctx->d_L32, ctx->L_total * 4))) return rc;
         if (!ctx->d_W32.p && (rc = alloc(ctx, ctx->d_W32, ctx->X_total * 4))) return rc;
+        if (!ctx->d_E.p && (rc = alloc(ctx, ctx->d_E, ctx->X_total * 8))) return rc;
         HIPCHK(hipMemsetAsync(ctx->d_refine.p, 0, 16, st));
         double* max_res = ctx->d_refine.as<double>();
         int* steps = reinterpret_cast<int*>(ctx->d_refine.as<char>() + 8);
-        HIPCHK(launch_darcy_basis_mixed(t, (int)ctx->n_units, ctx->max_b, ctx->max_Rd, ctx->d_S.as<double>(),
-                                        ctx->d_X.as<double>(), ctx->d_L32.as<float>(), ctx->d_T.as<double>(),
-                                        ctx->d_W32.as<float>(), nullptr, 3, 1e-13, max_res, steps, st));
+        HIPCHK(launch_darcy_basis_blocked_mixed(t, (int)ctx->n_units, ctx->max_b, ctx->max_Rd, ctx->d_S.as<double>(),
+                                                ctx->d_X.as<double>(), ctx->d_E.as<double>(), ctx->d_L32.as<float>(),
+                                                ctx->d_T.as<double>(), ctx->d_W32.as<float>(), 4, 1e-13, max_res, steps,
+                                                st));
     }
     HIPCHK(hipEventRecord(ctx->ev[1], st));
     if (!ctx->stokes_built) {
@@ -927,7 +977,9 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
                 int32_t* iters, double* relres, int32_t* status, hipStream_t st, int64_t& tot_it, bool& bad,
                 bool& brk) {
     int rc;
-    if ((rc = prepare_groups(ctx, gidx, n, st))) return rc;
+    if ((rc = fetch_gidx(ctx, gidx, n, st))) return rc;
+    if ((rc = build_groups(ctx, n, nullptr, st))) return rc;
+    int64_t in_work = n;   // realizations covered by the operator work list
     CgArgs a = cg_args(ctx, n, gidx, lambda);
     a.rtol = rtol;
     a.max_iter = max_iter;
@@ -949,32 +1001,56 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
         }
         return hipSuccess;
     };
-    if (ctx->opt_graph) {
+    auto capture = [&]() -> int {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        if (!ctx->opt_graph) return SDMM_OK;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         hipError_t e = body(st);
         hipError_t e2 = hipStreamEndCapture(st, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
+            graph = nullptr;
             return fail(ctx, SDMM_EDEVICE, "graph capture of the CG iterations failed");
         }
         if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
             (void)hipGraphDestroy(graph);
+            graph = nullptr;
+            exec = nullptr;
             return fail(ctx, SDMM_EDEVICE, "graph instantiation failed");
         }
-    }
+        return SDMM_OK;
+    };
+    if ((rc = capture())) return rc;
     int it = 0;
-    int32_t any = 1;
+    int32_t count = (int32_t)n;
+    std::vector<int32_t> act;
     while (it < max_iter) {
-        HIPCHK(hipMemsetAsync(a.any_active, 0, 4, st));
         if (exec) {
             HIPCHK(hipGraphLaunch(exec, st));
         } else {
             HIPCHK(body(st));
         }
         it += group;
-        HIPCHK(hipMemcpyAsync(&any, a.any_active, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(launch_count_active(a.active, n, a.any_active, st));
+        HIPCHK(hipMemcpyAsync(&count, a.any_active, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (!any) break;
+        if (count == 0) break;
+        // drop converged realizations from the operator once they are a
+        // quarter of its work (their results are final)
+        if (count < 0.75 * in_work) {
+            act.resize(n);
+            HIPCHK(hipMemcpyAsync(act.data(), a.active, n * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::vector<int> sel;
+            for (int64_t l = 0; l < n; ++l)
+                if (act[l]) sel.push_back((int)l);
+            if ((rc = build_groups(ctx, n, &sel, st))) return rc;
+            in_work = (int64_t)sel.size();
+            if ((rc = capture())) return rc;
+        }
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1059,7 +1135,8 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const
         const int64_t cn = std::min(chunk, n - c0);
         const int64_t* g = gidx + c0;
         const double* lam = lambda + c0 * M;
-        if ((rc = prepare_groups(ctx, g, cn, st))) return rc;
+        if ((rc = fetch_gidx(ctx, g, cn, st))) return rc;
+        if ((rc = build_groups(ctx, cn, nullptr, st))) return rc;
         CgArgs a = cg_args(ctx, cn, g, const_cast<double*>(lam));
         if (ctx->P.n_kernel > 0) {
             HIPCHK(launch_scatter_local(lam, ctx->SR, ctx->d_pos.as<int>(), M, cn, ctx->w_p.as<double>(), st));

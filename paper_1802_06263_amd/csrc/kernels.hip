@@ -474,6 +474,8 @@ hipError_t launch_darcy_basis_mixed(const DarcyTables& t, int n_units, int max_b
     return hipGetLastError();
 }
 
+#include "darcy_blocked.inc"
+
 // ---------------------------------------------------------------------------
 // Stokes: tiled band LDL^T.  Block column J holds tiles I = J .. J + w, each
 // 64 x 64 column-major; tile (I, J) at off_tiles + (J (w+1) + I - J) 4096.
@@ -1058,14 +1060,19 @@ hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int
 
 // CG update with the operator result gathered from Y.  One workgroup per
 // realization; the realization's iteration count lives in iters[l], so the
-// launch is identical every iteration (graph capture).  Every vector is read
-// once and kept in registers (M <= 256 * kMaxQ).
+// launch is identical every iteration (graph capture).  The operator result
+// is assembled in LDS (both subdomain contributions of every mortar DOF, in a
+// fixed order); the FETI projection touches only the rows of G that belong to
+// floating subdomains.
 constexpr int kMaxQ = 8;
+constexpr int kMaxM = kThreads * kMaxQ;
 
 __global__ __launch_bounds__(kThreads) void cg_update2_kernel(CgArgs a, const double* __restrict__ Y, int64_t SR,
                                                               const int* __restrict__ pos) {
     __shared__ double red[kThreads / 64];
+    __shared__ double redk[16][kThreads / 64];
     __shared__ double coef[32];
+    __shared__ double aps[kMaxM];
     const int64_t l = blockIdx.x;
     if (!a.active[l]) return;
     const int M = a.M, tid = threadIdx.x;
@@ -1073,36 +1080,33 @@ __global__ __launch_bounds__(kThreads) void cg_update2_kernel(CgArgs a, const do
     double* pl = a.p + l * SR;   // search direction in the subdomain-local layout
     double* lam = a.lam + l * M;
     const double* Yl = Y + l * SR;
-    double ap[kMaxQ], pv[kMaxQ], rv[kMaxQ];
+    double pv[kMaxQ], rv[kMaxQ];
 #pragma unroll
     for (int q = 0; q < kMaxQ; ++q) {
         const int m = tid + q * kThreads;
-        ap[q] = pv[q] = rv[q] = 0.0;
+        pv[q] = rv[q] = 0.0;
         if (m < M) {
-            ap[q] = Yl[pos[2 * m]] + Yl[pos[2 * m + 1]];
-            pv[q] = pl[pos[2 * m]];
+            const int p0 = pos[2 * m], p1 = pos[2 * m + 1];
+            aps[m] = Yl[p0] + Yl[p1];
+            pv[q] = pl[p0];
             rv[q] = r[m];
         }
     }
     const int nk = a.nker;
     if (nk > 0) {
-        // G^T ap: all nk sums reduced together (one pass through LDS)
-        __shared__ double redk[16][kThreads / 64];
+        __syncthreads();
+        // c = G^T ap over the rows of floating subdomains, all nk sums at once
         for (int kk = 0; kk < nk; ++kk) {
             double part = 0.0;
-#pragma unroll
-            for (int q = 0; q < kMaxQ; ++q) {
-                const int m = tid + q * kThreads;
-                if (m < M) part += a.G[(int64_t)kk * M + m] * ap[q];
-            }
+            for (int q = tid; q < a.nGrow; q += kThreads) part += a.Gval[q * nk + kk] * aps[a.Grow[q]];
             part = wave_sum(part);
             if ((tid & 63) == 0) redk[kk][tid >> 6] = part;
         }
         __syncthreads();
         if (tid < nk) {
-            double s = 0.0;
-            for (int w = 0; w < kThreads / 64; ++w) s += redk[tid][w];
-            coef[tid] = s;
+            double sum = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) sum += redk[tid][w];
+            coef[tid] = sum;
         }
         __syncthreads();
         if (tid < nk) {
@@ -1111,19 +1115,21 @@ __global__ __launch_bounds__(kThreads) void cg_update2_kernel(CgArgs a, const do
             coef[nk + tid] = d;
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kMaxQ; ++q) {
-            const int m = tid + q * kThreads;
-            if (m < M) {
-                double c = 0.0;
-                for (int kk = 0; kk < nk; ++kk) c += a.G[(int64_t)kk * M + m] * coef[nk + kk];
-                ap[q] -= c;
-            }
+        for (int q = tid; q < a.nGrow; q += kThreads) {
+            double c = 0.0;
+            for (int kk = 0; kk < nk; ++kk) c += a.Gval[q * nk + kk] * coef[nk + kk];
+            aps[a.Grow[q]] -= c;
         }
     }
+    __syncthreads();
+    double ap[kMaxQ];
     double part = 0.0;
 #pragma unroll
-    for (int q = 0; q < kMaxQ; ++q) part += pv[q] * ap[q];
+    for (int q = 0; q < kMaxQ; ++q) {
+        const int m = tid + q * kThreads;
+        ap[q] = m < M ? aps[m] : 0.0;
+        part += pv[q] * ap[q];
+    }
     const double pAp = block_sum(part, red);
     const double rr = a.rr[l];
     const int iter = a.iters[l];
@@ -1172,14 +1178,30 @@ __global__ __launch_bounds__(kThreads) void cg_update2_kernel(CgArgs a, const do
             pl[pos[2 * m + 1]] = v;
         }
     }
-    if (tid == 0) {
-        a.rr[l] = rrn;
-        *a.any_active = 1;
-    }
+    if (tid == 0) a.rr[l] = rrn;
 }
 
 hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream) {
     hipLaunchKernelGGL(cg_update2_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, Y, SR, pos);
+    return hipGetLastError();
+}
+
+// Number of realizations of the chunk still iterating (deterministic sum).
+__global__ void count_active_kernel(const int32_t* active, int64_t n, int32_t* count) {
+    __shared__ int part[256];
+    int s = 0;
+    for (int64_t l = threadIdx.x; l < n; l += blockDim.x) s += active[l];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int k = 0; k < (int)blockDim.x; ++k) t += part[k];
+        *count = t;
+    }
+}
+
+hipError_t launch_count_active(const int32_t* active, int64_t n, int32_t* count, hipStream_t stream) {
+    hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(256), 0, stream, active, n, count);
     return hipGetLastError();
 }
 

@@ -55,6 +55,13 @@ hipError_t launch_darcy_basis_mixed(const DarcyTables& t, int n_units, int max_b
                                     int max_refine, double refine_tol, double* max_res, int* steps,
                                     hipStream_t stream);
 
+size_t darcy_blocked_lds(int max_b, int max_R, size_t elem);
+hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
+                                      double* X, double* Lscr, double* Tscr, hipStream_t stream);
+hipError_t launch_darcy_basis_blocked_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
+                                            double* X, double* E, float* L32, double* Tscr, float* W32, int max_refine,
+                                            double refine_tol, double* max_res, int* steps, hipStream_t stream);
+
 // Stokes: tiled band LDL^T (tile 64) of several subdomains at once.
 struct StokesDev {
     int nband, nblk, w, ncol;   // ncol = R + 1
@@ -108,6 +115,9 @@ struct CgArgs {
     int32_t* status;
     int32_t* active;
     int32_t* any_active;
+    const int* Grow;         // rows of G with non-zero entries (floating subdomains)
+    const double* Gval;      // nGrow x nker values of those rows
+    int nGrow;
     double rtol;
     int max_iter;
 };
@@ -121,6 +131,7 @@ hipError_t launch_scatter_local(const double* x, int64_t SR, const int* pos, int
 hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int M, int64_t n, double* y,
                                 hipStream_t stream);
 hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream);
+hipError_t launch_count_active(const int32_t* active, int64_t n, int32_t* count, hipStream_t stream);
 hipError_t launch_cg_finish(const CgArgs& a, double* lam_out, int32_t* iters_out, double* relres_out,
                             int32_t* status_out, hipStream_t stream);
 
