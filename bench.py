@@ -6,21 +6,35 @@ rtol 1e-8 for every global collocation point, and the moment accumulation.
 The Stokes basis (deterministic, one local realization) is built once before
 the timed region and reported separately.
 
-Prints one JSON line (see the keys below).  --gpus above 1 is refused: this
-build runs on one GPU.
+Both precisions run on identical inputs; `value` is the one named by
+--precision.  Every CG kernel launch in the timed region is bracketed by HIP
+events on the stream it runs on; the dominant kernel's algorithmic bytes (or
+flops) per launch over its average launch duration give `roofline`.  The CPU
+baseline (the oracle, one thread, bounded sample) runs in a child process
+started before the GPU is touched.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
 import argparse
+import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64 = 78.6e12
-PEAK_FP32 = 157.3e12
+PEAK_FP64 = 78.6e12      # FP64 vector and FP64 MFMA, dense
+PEAK_FP32 = 157.3e12     # FP32 vector
 PEAK_HBM = 8.0e12
+
+METRIC = "collocation realizations/sec to CG rtol 1e-8 + basis builds/sec, FP64 vs mixed"
+
+
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -32,9 +46,88 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work in the CPU sample")
     ap.add_argument("--single", action="store_true", help="time only --precision (profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device copy first (scale reference for HBM counters)")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands
+
+
+def cpu_baseline(prob, budget_s):
+    """The oracle, untuned and single-threaded, on a bounded sample of the workload.
+
+    Sample: the Darcy flux bases that one global realization needs (one per
+    Darcy subdomain, at that realization's local indices), then that
+    realization through CG rtol 1e-8, recovery and moment accumulation,
+    repeated while the budget lasts.  Extrapolated to every (subdomain, local
+    realization) unit and every global realization.  Oracle set-up and the
+    Stokes basis are excluded, as in the GPU step; the set-up factorizes the
+    Stokes subdomains in threads to keep the run short, the timed sample is
+    single-threaded.
+    """
+    from threadpoolctl import threadpool_limits
+    from oracle.darcy import DarcyLocal
+    from oracle.methods import Oracle
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        o = Oracle(prob, threads=6, progress=lambda i: log("cpu baseline: oracle Stokes subdomain %d set up "
+                                                           "(%.0f s)" % (i, time.perf_counter() - t0)))
+        stokes = o.stokes_basis()
+        t_setup = time.perf_counter() - t0
+        log("cpu baseline: oracle set-up done (%.0f s)" % t_setup)
+        L = o.L
+        l0 = 0
+        kl = o.grid.g2l[l0]
+        table = {(i, 0): S for i, S in stokes.items()}
+        t1 = time.perf_counter()
+        for i in o.darcy_ids:
+            r = L.subs[i]["region"]
+            k = int(kl[r])
+            table[(i, k)] = DarcyLocal(L, i, o.darcy_K(i, o.grid.local_points(r)[k])).basis()
+        t_unit = (time.perf_counter() - t1) / len(o.darcy_ids)
+        log("cpu baseline: %d Darcy bases, %.3f s each" % (len(o.darcy_ids), t_unit))
+        o.s3_table = table
+        w = float(o.grid.weights[l0])
+        acc1, acc2 = {}, {}
+        t2 = t_log = time.perf_counter()
+        nr = 0
+        while True:
+            fields, _, _, _ = o.realization_S3(l0, rtol=1e-8)
+            for key, v in fields.items():
+                acc1[key] = acc1.get(key, 0.0) + w * v
+                acc2[key] = acc2.get(key, 0.0) + w * v * v
+            nr += 1
+            now = time.perf_counter()
+            if now - t_log > 5.0:
+                log("cpu baseline: %d realizations of the sample done" % nr)
+                t_log = now
+            if now - t1 > budget_s:
+                break
+        t_real = (time.perf_counter() - t2) / nr
+    n_units = sum(o.grid.nlocal[L.subs[i]["region"]] for i in o.darcy_ids)
+    total = n_units * t_unit + o.grid.nreal * t_real
+    return {"value": o.grid.nreal / total, "unit": "realizations/s", "cores": 1, "kind": "oracle",
+            "sample": "%d Darcy flux bases of realization %d (%.3f s each) and that realization through CG "
+                      "rtol 1e-8 + recovery + moments %d times (%.3f s each), one thread, extrapolated to "
+                      "%d units + %d realizations; oracle set-up and Stokes basis (%.0f s) excluded"
+                      % (len(o.darcy_ids), l0, t_unit, nr, t_real, n_units, o.grid.nreal, t_setup),
+            "basis_builds_per_s": 1.0 / t_unit}
+
+
+def start_cpu_baseline(args):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--workload", args.workload,
+           "--cpu-budget", str(args.cpu_budget)]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, env=env, cwd=ROOT)
+
+
+# ---------------------------------------------------------------------------
+# GPU path
 
 
 def gpu_step(ctx, prec, g, lam, rtol, torch):
@@ -44,80 +137,119 @@ def gpu_step(ctx, prec, g, lam, rtol, torch):
     torch.cuda.synchronize()
 
 
+COUNTER_KEYS = ("cg_iterations", "realizations", "cg_launches", "cg_timed_launches", "cg_timed_active", "cg_timed_columns",
+                "ms_cg_apply", "ms_cg_update", "basis_solves_darcy", "units_built")
+
+
 def time_path(ctx, prec, g, lam, rtol, steps, warmup, torch):
     for _ in range(warmup):
         gpu_step(ctx, prec, g, lam, rtol, torch)
     ctx.reset_moments()
     torch.cuda.synchronize()
+    c0 = ctx.counters()
     basis_ms, solve_ms = [], []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for s in range(steps):
         gpu_step(ctx, prec, g, lam, rtol, torch)
         c = ctx.counters()
         basis_ms.append(c["ms_basis_darcy"])
         solve_ms.append(c["ms_solve"])
+        log("%s step %d: basis %.2f ms, CG %.1f ms" % (prec, s, basis_ms[-1], solve_ms[-1]))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return dt, sum(basis_ms) / steps, sum(solve_ms) / steps
+    c1 = ctx.counters()
+    d = {k: c1[k] - c0[k] for k in COUNTER_KEYS}
+    return dt, sum(basis_ms) / steps, sum(solve_ms) / steps, d
 
 
-def cpu_baseline(prob, budget_s):
-    """The oracle, untuned, on a bounded sample of the same workload."""
-    import numpy as np
-    from oracle.darcy import DarcyLocal
-    from oracle.methods import Oracle
-    t0 = time.perf_counter()
-    o = Oracle(prob)
-    o.stokes_basis()
-    t_setup = time.perf_counter() - t0
-    L = o.L
-    # basis units: one local realization per Darcy subdomain, until the budget
-    t1 = time.perf_counter()
-    nu = 0
-    for i in o.darcy_ids:
-        r = L.subs[i]["region"]
-        DarcyLocal(L, i, o.darcy_K(i, o.grid.local_points(r)[0])).basis()
-        nu += 1
-        if time.perf_counter() - t1 > 0.4 * budget_s:
-            break
-    t_unit = (time.perf_counter() - t1) / nu
-    # realizations: S3 main loop (table from the units built above, reused)
-    table = {}
-    for i in o.darcy_ids:
-        r = L.subs[i]["region"]
-        table[(i, 0)] = None
-    o.s3_table = {}
-    for i in o.darcy_ids:
-        r = L.subs[i]["region"]
-        dl = DarcyLocal(L, i, o.darcy_K(i, o.grid.local_points(r)[0]))
-        S = dl.basis()
-        for k in range(o.grid.nlocal[r]):
-            o.s3_table[(i, k)] = S
-    for i, S in o.stokes_basis().items():
-        o.s3_table[(i, 0)] = S
-    t2 = time.perf_counter()
-    nr = 0
-    rng = np.random.default_rng(0)
-    while True:
-        o.realization_S3(int(rng.integers(0, o.grid.nreal)), rtol=1e-8)
-        nr += 1
-        if time.perf_counter() - t2 > 0.5 * budget_s:
-            break
-    t_real = (time.perf_counter() - t2) / nr
-    n_units = sum(o.grid.nlocal[L.subs[i]["region"]] for i in o.darcy_ids)
-    total = n_units * t_unit + o.grid.nreal * t_real
-    return {"value": o.grid.nreal / total, "unit": "realizations/s", "cores": 1, "kind": "oracle",
-            "sample": "%d Darcy flux bases (%.3f s each) and %d global realizations through CG rtol 1e-8 + "
-                      "recovery (%.3f s each), extrapolated to %d units + %d realizations; Stokes basis "
-                      "and setup (%.1f s) excluded" % (nu, t_unit, nr, t_real, n_units, o.grid.nreal, t_setup),
-            "basis_builds_per_s": 1.0 / t_unit}
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1802_06263_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per realization-iteration from the committed counter summary,
+    or None when there is none or the kernel sources changed since it was
+    taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_unit"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_rooflines(sz, sum_R, sum_R2, d, basis_ms, prec, workload):
+    """Per-kernel roofline entries.  The algorithmic unit of the CG kernels is
+    one realization-iteration (one CG iteration of one realization still
+    iterating); the library times one (product, update) launch pair per
+    convergence-check group and counts the realizations active in it.  The
+    unit of the basis kernel is one full build (a single launch)."""
+    M = sz["M"]
+    out = {}
+    nl = d["cg_timed_launches"]
+    if nl:
+        act = d["cg_timed_active"] / nl
+        # CG update: reads the subdomain-local product Y (sum R_i), p (M), r
+        # and lambda; writes lambda, r and p in the local layout (sum R_i)
+        b_upd = 8.0 * (2 * sum_R + 5 * M)
+        avg = d["ms_cg_update"] * 1e-3 / nl
+        per_launch = b_upd * act
+        out["cg_update"] = {"kernel": "cg_update2_kernel", "bound": "hbm", "achieved": per_launch / avg / 1e9,
+                            "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": per_launch / avg / PEAK_HBM,
+                            "avg_launch_us": avg * 1e6, "timed_launches": nl, "active_per_launch": act,
+                            "bytes_per_unit": b_upd, "algorithmic_bytes_per_launch": per_launch,
+                            "sampled_ms": d["ms_cg_update"]}
+        t = read_traffic("cg_update2", workload)
+        out["cg_update"]["traffic"] = t * act if t is not None else None
+        # CG product: 2 sum R_i^2 flops; reads p and writes Y in the local layout
+        f_app = 2.0 * sum_R2
+        b_app = 8.0 * 2 * sum_R
+        avg = d["ms_cg_apply"] * 1e-3 / nl
+        out["cg_apply"] = {"kernel": "cg_apply_mfma_kernel", "bound": "hbm",
+                           "achieved": b_app * act / avg / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                           "frac": b_app * act / avg / PEAK_HBM, "tflops": f_app * act / avg / 1e12,
+                           "frac_fp64_mfma": f_app * act / avg / PEAK_FP64, "avg_launch_us": avg * 1e6,
+                           "timed_launches": nl, "active_per_launch": act,
+                           "columns_per_launch": d["cg_timed_columns"] / nl,
+                           "bytes_per_unit": b_app, "flops_per_unit": f_app,
+                           "algorithmic_bytes_per_launch": b_app * act,
+                           "sampled_ms": d["ms_cg_apply"]}
+        t = read_traffic("cg_apply_mfma", workload)
+        out["cg_apply"]["traffic"] = t * act if t is not None else None
+    # Darcy basis build: banded factor + forward/backward flops, one launch
+    peak = PEAK_FP32 if prec == "mixed" else PEAK_FP64
+    ach = sz["darcy_flops"] / (basis_ms * 1e-3)
+    out["darcy_basis"] = {"kernel": "darcy_basis_blocked_%s_kernel" % prec, "bound": "alu",
+                          "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
+                          "avg_launch_us": basis_ms * 1e3, "launches": 1,
+                          "algorithmic_flops_per_launch": sz["darcy_flops"], "traffic": None}
+    return out
 
 
 def main():
     args = parse()
+    if args.cpu_baseline_only:
+        from workloads import problem
+        print(json.dumps(cpu_baseline(problem(args.workload), args.cpu_budget)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    # the oracle child starts before this process touches the GPU
+    child = None if args.no_cpu_baseline else start_cpu_baseline(args)
     import numpy as np
     import torch
     from paper_1802_06263_amd import sdmm
@@ -128,28 +260,49 @@ def main():
     ctx.set_problem(prob)
     sz = ctx.sizes()
     n, M = sz["n_real"], sz["M"]
-    t0 = time.perf_counter()
+    R = np.diff(ctx.index_map("sub_ptr"))
+    sum_R, sum_R2 = int(R.sum()), int((R.astype(np.int64) ** 2).sum())
+    log("%s: %d realizations, M = %d, %d basis units" % (args.workload, n, M, sz["n_units"]))
+    if args.copy_probe:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)   # an elementwise kernel: 256 MiB read, 256 MiB written
+        torch.cuda.synchronize()
+        del src, dst
     ctx.build_flux_basis("fp64")
     torch.cuda.synchronize()
     stokes_ms = ctx.counters()["ms_basis_stokes"]
     g = torch.arange(n, dtype=torch.int64, device="cuda")
     lam = torch.zeros((n, M), dtype=torch.float64, device="cuda")
+    ctx.set_option("kernel_timing", 1)
     other = "fp64" if args.precision == "mixed" else "mixed"
-    res = {}
+    res, kern = {}, {}
     for prec in ((args.precision,) if args.single else (other, args.precision)):
-        dt, bms, sms = time_path(ctx, prec, g, lam, args.rtol, args.steps, args.warmup, torch)
-        c = ctx.counters()
+        dt, bms, sms, d = time_path(ctx, prec, g, lam, args.rtol, args.steps, args.warmup, torch)
+        kern[prec] = kernel_rooflines(sz, sum_R, sum_R2, d, bms, prec, args.workload)
         res[prec] = {"ms_per_step": dt * 1e3, "realizations_per_s": n / dt, "ms_basis": bms, "ms_cg": sms,
                      "basis_builds_per_s": sz["n_units"] / (bms * 1e-3),
-                     "cg_iterations_mean": c["cg_iterations"] / max(1, c["realizations"])}
+                     "local_solves_per_s": d["basis_solves_darcy"] / (args.steps * bms * 1e-3),
+                     "cg_iterations_mean": d["cg_iterations"] / max(1, d["realizations"]),
+                     "refinement_steps_per_unit": (ctx.counters()["refinement_steps"] / sz["n_units"]
+                                                   if prec == "mixed" else 0.0),
+                     "cg_launches_per_step": d["cg_launches"] / args.steps}
     main_r = res[args.precision]
-    flops = sz["darcy_flops"]
-    peak = PEAK_FP32 if args.precision == "mixed" else PEAK_FP64
-    achieved = flops / (main_r["ms_basis"] * 1e-3)
-    roof = {"kernel": "darcy_basis_%s" % args.precision, "bound": "mfma", "achieved": achieved / 1e12,
-            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
-    out = {"metric": "collocation realizations/sec to CG rtol 1e-8 + basis builds/sec, FP64 vs mixed",
-           "value": main_r["realizations_per_s"], "unit": "realizations/s", "n_gpus": 1,
+    kmain = kern[args.precision]
+    # dominant kernel: largest share of the step (sampled CG launches scaled
+    # to every iteration of the step)
+    share = {k: v["avg_launch_us"] * (v.get("launches") or 0) for k, v in kmain.items()}
+    for k in ("cg_update", "cg_apply"):
+        if k in kmain:
+            share[k] = kmain[k]["avg_launch_us"] * res[args.precision]["cg_launches_per_step"]
+    for k in share:
+        kmain[k]["est_ms_per_step"] = share[k] * 1e-3
+    dom = max(share, key=share.get)
+    r = kmain[dom]
+    roof = {"kernel": r["kernel"], "bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
+            "unit": r["unit"], "frac": r["frac"], "traffic": r["traffic"],
+            "avg_launch_us": r["avg_launch_us"]}
+    out = {"metric": METRIC, "value": main_r["realizations_per_s"], "unit": "realizations/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_r["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
@@ -157,11 +310,17 @@ def main():
                       "precision": args.precision, "rtol": args.rtol},
            "basis_builds_per_s": main_r["basis_builds_per_s"],
            "fp64": res.get("fp64"), "mixed": res.get("mixed"), "stokes_basis_ms": stokes_ms,
-           "roofline": roof}
+           "roofline": roof, "kernels": kmain}
     ctx.close()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_budget)
-    print(json.dumps(out))
+    if child is not None:
+        log("waiting for the CPU baseline")
+        so, _ = child.communicate()
+        if child.returncode == 0 and so.strip():
+            out["cpu_baseline"] = json.loads(so.decode().strip().splitlines()[-1])
+        else:
+            log("CPU baseline failed (exit %d)" % child.returncode)
+            out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -130,13 +130,22 @@ typedef struct {
     int64_t basis_solves_stokes;  /* sum over Stokes subdomains of R_i          */
     int64_t complementary_solves; /* solves for g_H (once, deterministic)       */
     int64_t units_built;          /* Darcy (i, k) bases built                   */
-    int64_t refinement_steps;     /* FP64 refinement sweeps (mixed precision)   */
+    int64_t refinement_steps;     /* FP64 refinement sweeps of the last mixed build */
     int64_t cg_iterations;        /* summed over realizations                   */
     int64_t realizations;         /* taken through CG                           */
     double ms_basis_darcy;        /* last build: Darcy units                    */
     double ms_basis_stokes;       /* last build: Stokes subdomains              */
     double ms_solve;              /* last solve_interface                       */
     double max_refine_residual;   /* largest relative residual after refinement */
+    /* per-kernel timing of the CG iterations while SDMM_OPT_KERNEL_TIMING is
+     * on: one iteration of every convergence-check group is bracketed by HIP
+     * events on the stream the kernels run on; sums over all solves */
+    int64_t cg_launches;          /* product launches (= update launches), all   */
+    int64_t cg_timed_launches;    /* sampled (product, update) launch pairs     */
+    int64_t cg_timed_active;      /* realizations still iterating in them        */
+    int64_t cg_timed_columns;     /* realization columns the products covered    */
+    double ms_cg_apply;           /* summed duration of the sampled products     */
+    double ms_cg_update;          /* summed duration of the sampled updates      */
 } sdmm_counters;
 
 /* Create a context on HIP device `device`.  Ownership of *out passes to the
@@ -208,10 +217,14 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
  *                      chunk's vectors fit a ~96 MB cache budget)
  *   SDMM_OPT_CG_CHECK  iterations between host convergence checks (1..1024)
  *   SDMM_OPT_CG_GRAPH  1 = replay the iteration group as a captured HIP graph
+ *   SDMM_OPT_KERNEL_TIMING 1 = time one iteration of every check group with
+ *                      HIP events and sum the durations into the counters
+ *                      (launches then run eagerly, without graph replay)
  * Results do not depend on any of them. */
 #define SDMM_OPT_CG_CHUNK 0
 #define SDMM_OPT_CG_CHECK 1
 #define SDMM_OPT_CG_GRAPH 2
+#define SDMM_OPT_KERNEL_TIMING 3
 int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value);
 int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out);
 

@@ -32,15 +32,34 @@ from .stokes import StokesLocal
 FIELDS = ("lambda", "darcy_p", "darcy_u", "stokes_u", "stokes_p")
 
 
+def _map(fn, items, threads, progress=None):
+    """fn over independent items, in order; threads > 1 only overlaps the
+    sparse factorizations (SuperLU releases the GIL), the arithmetic is the
+    same.  progress(item) is called as each item finishes."""
+    def run(x):
+        y = fn(x)
+        if progress is not None:
+            progress(x)
+        return y
+    if threads <= 1:
+        return [run(x) for x in items]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(run, items))
+
+
 class Oracle:
-    def __init__(self, prob):
+    def __init__(self, prob, threads=1, progress=None):
         self.prob = prob
+        self.threads = threads
+        self.progress = progress
         self.L = Layout(prob)
         self.grid = Grid(prob["regions"], prob["rule"])
         L = self.L
         self.stokes_ids = [i for i in range(L.nsub) if L.subs[i]["type"] == "stokes"]
         self.darcy_ids = [i for i in range(L.nsub) if L.subs[i]["type"] == "darcy"]
-        self.stokes = {i: StokesLocal(L, i) for i in self.stokes_ids}
+        self.stokes = dict(zip(self.stokes_ids, _map(lambda i: StokesLocal(L, i), self.stokes_ids, threads,
+                                                           progress)))
         self.phi = {}
         for i in self.darcy_ids:
             reg = L.regions[L.subs[i]["region"]]
@@ -90,7 +109,9 @@ class Oracle:
 
     def stokes_basis(self):
         if self._stokes_S is None:
-            self._stokes_S = {i: self.stokes[i].basis() for i in self.stokes_ids}
+            self._stokes_S = dict(zip(self.stokes_ids,
+                                      _map(lambda i: self.stokes[i].basis(), self.stokes_ids, self.threads,
+                                           self.progress)))
         return self._stokes_S
 
     def _count(self, i, n):

@@ -82,6 +82,8 @@ struct sdmm_ctx {
     int64_t opt_chunk = 0;   // realizations per CG chunk, 0 = from the cache budget
     int opt_check = 16;      // iterations between convergence checks
     int opt_graph = 1;       // capture the iteration group in a HIP graph
+    int opt_ktime = 0;       // events around every CG kernel launch
+    std::vector<hipEvent_t> kev;   // event pool of the kernel timing
     hipStream_t cap_stream = nullptr;
     sdmm_counters counters{};
     hipEvent_t ev[6] = {};
@@ -711,7 +713,9 @@ int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, hipSt
 int64_t chunk_size(sdmm_ctx* ctx, int64_t n) {
     if (ctx->opt_chunk > 0) return std::min<int64_t>(n, ctx->opt_chunk);
     const int64_t per = (3 * (int64_t)ctx->P.M + ctx->SR) * 8 + 64;
-    int64_t c = std::max<int64_t>(256, (int64_t)(96.0 * 1024 * 1024) / per);
+    // the chunk's CG vectors stay within ~200 MB, resident in the 256 MB
+    // last-level cache between the product and the update
+    int64_t c = std::max<int64_t>(256, (int64_t)(200.0 * 1024 * 1024) / per);
     const int64_t nch = (n + c - 1) / c;
     return (n + nch - 1) / nch;
 }
@@ -777,6 +781,8 @@ int sdmm_destroy(sdmm_ctx* ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->kev)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
     return SDMM_OK;
@@ -965,6 +971,9 @@ int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value) {
         case SDMM_OPT_CG_GRAPH:
             ctx->opt_graph = value ? 1 : 0;
             return SDMM_OK;
+        case SDMM_OPT_KERNEL_TIMING:
+            ctx->opt_ktime = value ? 1 : 0;
+            return SDMM_OK;
         default:
             return fail(ctx, SDMM_EINVAL, "unknown option");
     }
@@ -991,22 +1000,57 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
     const int group = ctx->opt_check;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    auto body = [&](hipStream_t s) -> hipError_t {
-        for (int q = 0; q < group; ++q) {
-            hipError_t e = launch_cg_apply_mfma(a, a.p, Y, ctx->SR, ctx->d_work.as<int4>(), ctx->nwork,
-                                                ctx->d_perm.as<int>(), ctx->max_R, s);
-            if (e != hipSuccess) return e;
-            e = launch_cg_update2(a, Y, ctx->SR, pos, s);
-            if (e != hipSuccess) return e;
+    // Kernel timing samples the second iteration of every check group: the
+    // active realizations are counted just before it (into the second int of
+    // any_active), then events bracket its product and its update.  Earlier
+    // iterations keep the queue ahead of the device, so the events time the
+    // kernels and not host launch latency.
+    const bool ktime = ctx->opt_ktime != 0;
+    const int tq = group > 1 ? 1 : 0;
+    int32_t* tcount = a.any_active + 1;
+    if (ktime) {
+        while ((int)ctx->kev.size() < 3) {
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreate(&e));
+            ctx->kev.push_back(e);
         }
-        return hipSuccess;
+    }
+    auto body = [&](hipStream_t s) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int q = 0; q < group && e == hipSuccess; ++q) {
+            const bool timed = ktime && q == tq;
+            if (timed) {
+                e = launch_count_active(a.active, n, tcount, s);
+                if (e == hipSuccess) e = hipEventRecord(ctx->kev[0], s);
+                if (e != hipSuccess) break;
+            }
+            e = launch_cg_apply_mfma(a, a.p, Y, ctx->SR, ctx->d_work.as<int4>(), ctx->nwork,
+                                     ctx->d_perm.as<int>(), ctx->max_R, s);
+            if (e == hipSuccess && timed) e = hipEventRecord(ctx->kev[1], s);
+            if (e == hipSuccess) e = launch_cg_update2(a, Y, ctx->SR, pos, s);
+            if (e == hipSuccess && timed) e = hipEventRecord(ctx->kev[2], s);
+        }
+        return e;
+    };
+    // after the group has synchronized: add the sampled launch durations
+    int32_t tactive = 0;
+    auto add_times = [&]() -> int {
+        float ma = 0.f, mu = 0.f;
+        HIPCHK(hipEventElapsedTime(&ma, ctx->kev[0], ctx->kev[1]));
+        HIPCHK(hipEventElapsedTime(&mu, ctx->kev[1], ctx->kev[2]));
+        ctx->counters.ms_cg_apply += ma;
+        ctx->counters.ms_cg_update += mu;
+        ctx->counters.cg_timed_launches += 1;
+        ctx->counters.cg_timed_active += tactive;
+        ctx->counters.cg_timed_columns += in_work;
+        return SDMM_OK;
     };
     auto capture = [&]() -> int {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
-        if (!ctx->opt_graph) return SDMM_OK;
+        if (!ctx->opt_graph || ktime) return SDMM_OK;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         hipError_t e = body(st);
         hipError_t e2 = hipStreamEndCapture(st, &graph);
@@ -1034,9 +1078,12 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
             HIPCHK(body(st));
         }
         it += group;
+        ctx->counters.cg_launches += group;
         HIPCHK(launch_count_active(a.active, n, a.any_active, st));
         HIPCHK(hipMemcpyAsync(&count, a.any_active, 4, hipMemcpyDeviceToHost, st));
+        if (ktime) HIPCHK(hipMemcpyAsync(&tactive, tcount, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        if (ktime && (rc = add_times())) return rc;
         if (count == 0) break;
         // drop converged realizations from the operator once they are a
         // quarter of its work (their results are final)

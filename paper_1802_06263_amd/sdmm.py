@@ -45,7 +45,9 @@ class CSizes(ctypes.Structure):
 class CCounters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("basis_solves_darcy", "basis_solves_stokes", "complementary_solves",
                                               "units_built", "refinement_steps", "cg_iterations", "realizations")] + \
-               [(n, ctypes.c_double) for n in ("ms_basis_darcy", "ms_basis_stokes", "ms_solve", "max_refine_residual")]
+               [(n, ctypes.c_double) for n in ("ms_basis_darcy", "ms_basis_stokes", "ms_solve", "max_refine_residual")] + \
+               [(n, ctypes.c_int64) for n in ("cg_launches", "cg_timed_launches", "cg_timed_active", "cg_timed_columns")] + \
+               [(n, ctypes.c_double) for n in ("ms_cg_apply", "ms_cg_update")]
 
 
 EXPORTS = {
@@ -69,7 +71,7 @@ EXPORTS = {
     "sdmm_get_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CCounters)]),
     "sdmm_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
 }
-OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2}
+OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2, "kernel_timing": 3}
 
 _LIB = None
 
