@@ -162,11 +162,21 @@ def time_path(ctx, prec, g, lam, rtol, steps, warmup, torch):
     return dt, sum(basis_ms) / steps, sum(solve_ms) / steps, d
 
 
-def kernel_source_hash():
+def kernel_source_hash(kernel):
+    """Hash of one CG kernel's source: its definition through its launcher,
+    and the argument struct it takes."""
+    csrc = os.path.join(ROOT, "paper_1802_06263_amd", "csrc")
+    with open(os.path.join(csrc, "kernels.hip")) as fh:
+        src = fh.read()
+    with open(os.path.join(csrc, "kernels.hpp")) as fh:
+        hdr = fh.read()
+    i0 = src.index("void %s(" % kernel)
+    i1 = src.index("return hipGetLastError();", i0)
+    j0 = hdr.index("struct CgArgs")
+    j1 = hdr.index("};", j0)
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_1802_06263_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    h.update(src[i0:i1].encode())
+    h.update(hdr[j0:j1].encode())
     return h.hexdigest()[:16]
 
 
@@ -183,7 +193,7 @@ def read_traffic(kernel, workload):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(kernel + "_kernel"):
         return None
     try:
         return float(vals["hbm_bytes_per_unit"])

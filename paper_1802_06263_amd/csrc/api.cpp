@@ -55,7 +55,6 @@ struct sdmm_ctx {
     std::vector<int64_t> cell_out_off, edge_out_off, u_out_off, p_out_off;
     std::vector<int> pair_sub, pair_k;
     // device buffers
-    DevBuf d_meint;
     DevBuf d_dar, d_units, d_be_cell, d_be_kind, d_be_len, d_be_hperp, d_be_medge, d_be_sgn, d_cell_be, d_Pi, d_phi,
         d_xi, d_supp_ptr, d_supp_e, d_supp_v, d_me_cell;
     DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_E, d_refine;
@@ -149,7 +148,7 @@ int setup_device(sdmm_ctx* ctx) {
     const int nsub = (int)P.subs.size();
     // ---- Darcy tables and units
     std::vector<DarcyDev> dar;
-    std::vector<int> be_cell, be_kind, be_medge, be_sgn, cell_be, supp_ptr, supp_e, me_cell, meint;
+    std::vector<int> be_cell, be_kind, be_medge, be_sgn, cell_be, supp_ptr, supp_e, me_cell;
     std::vector<double> be_len, be_hperp, Pi, phi, supp_v;
     std::vector<double> xi;
     std::vector<int64_t> region_xi_off(P.n_region);
@@ -223,18 +222,6 @@ int setup_device(sdmm_ctx* ctx) {
             }
         }
         cell_be.insert(cell_be.end(), cb.begin(), cb.end());
-        {
-            // mortar edges of every cell in the factor's internal order
-            std::vector<int> mi((size_t)2 * h.N, -1);
-            for (size_t e = 0; e < h.be_cell.size(); ++e) {
-                if (h.be_medge[e] < 0) continue;
-                const int c = h.be_cell[e];
-                const int ci = h.swap ? (c % h.nx) * h.ny + c / h.nx : c;
-                if (mi[2 * ci] < 0) mi[2 * ci] = h.be_medge[e];
-                else mi[2 * ci + 1] = h.be_medge[e];
-            }
-            meint.insert(meint.end(), mi.begin(), mi.end());
-        }
         // support lists: for every mortar DOF, the mortar edges where its average is non-zero
         int base = (int)supp_e.size();
         std::vector<std::vector<std::pair<int, double>>> sl(h.R);
@@ -407,7 +394,6 @@ int setup_device(sdmm_ctx* ctx) {
     UP(ctx->d_be_medge, be_medge);
     UP(ctx->d_be_sgn, be_sgn);
     UP(ctx->d_cell_be, cell_be);
-    UP(ctx->d_meint, meint);
     UP(ctx->d_Pi, Pi);
     UP(ctx->d_phi, phi);
     UP(ctx->d_xi, xi);

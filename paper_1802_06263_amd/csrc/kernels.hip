@@ -1,11 +1,12 @@
 // HIP kernels of the stochastic multiscale flux basis library (gfx950).
 //
-//   darcy_basis_fp64   Method S3 pre-computation loop for Darcy subdomains
+//   darcy_basis_*      Method S3 pre-computation loop for Darcy subdomains
 //                      (Section 5.4): per (subdomain, local realization) unit,
 //                      K = exp(Y) from the KL expansion (eq. KLapprox), the
-//                      RT0-Q0 cell-centred operator, its band Cholesky factor,
-//                      the solves for every mortar basis function (eqs.
-//                      starDproblem1-2) and the flux basis S_{H,i}^{(k)}.
+//                      RT0-Q0 cell-centred operator, its blocked band LDL^T
+//                      factor, the solves for every mortar basis function
+//                      (eqs. starDproblem1-2) and the flux basis S_{H,i}^{(k)}
+//                      (darcy_blocked.inc).
 //   stokes_*           the same for Stokes subdomains (eqs. starSproblem1-2,
 //                      barSproblem1-2) with a tiled band LDL^T of the
 //                      Taylor-Hood saddle matrix.
@@ -102,377 +103,7 @@ __device__ void darcy_transmissibilities(const DarcyTables& t, const DarcyDev& D
     __syncthreads();
 }
 
-__device__ inline double band_entry(const double* Tf, const double* Ts, const double* Tb, int col, int d, int b,
-                                    int N) {
-    if (col >= N) return 0.0;
-    double v = 0.0;
-    if (d == 0) {
-        v = Tf[col] + Ts[col] + Tb[col];
-        if (col % b) v += Tf[col - 1];
-        if (col >= b) v += Ts[col - b];
-    }
-    if (d == 1) v -= Tf[col];
-    if (d == b) v -= Ts[col];
-    return v;
-}
-
-// E[row, r]: mortar boundary loads of the cell at internal index row.
-__device__ inline double rhs_entry(const DarcyTables& t, const DarcyDev& D, const double* Tm, int row, int r) {
-    if (row >= D.N) return 0.0;
-    const int cell = cell_of_internal(row, D.nx, D.ny, D.swap);
-    double v = 0.0;
-    for (int q = 0; q < 2; ++q) {
-        const int e = t.cell_be[D.off_cellbe + 2 * cell + q];
-        if (e < 0 || t.be_kind[D.off_be + e] != 0) continue;
-        const int me = t.be_medge[D.off_be + e];
-        v += Tm[me] * t.Pi[D.off_Pi + (int64_t)me * D.R + r];
-    }
-    return v;
-}
-
 }  // namespace
-
-// ---------------------------------------------------------------------------
-// Darcy basis, FP64.  One workgroup per (subdomain, local realization).
-// The band (half width b = the shorter side) is factored column by column
-// in a sliding LDS window of b + 2 columns (right-looking, one barrier per
-// column); the R right-hand sides ride along in the same window (forward
-// solve fused with the factorisation), then a backward sweep gives the fine
-// pressure responses X = P^{-1} E, and S = Pi^T T Pi - E^T X.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void darcy_basis_fp64_kernel(DarcyTables t, double* __restrict__ S_cache,
-                                                                    double* __restrict__ X, double* __restrict__ Lscr,
-                                                                    double* __restrict__ Tscr) {
-    extern __shared__ double sm[];
-    const UnitDev U = t.units[blockIdx.x];
-    const DarcyDev D = t.dar[U.d];
-    const int N = D.N, b = D.b, R = D.R;
-    const int nslot = b + 2, bw = b + 1;
-    double* band = sm;                    // nslot x (b + 1)
-    double* rhs = band + nslot * bw;      // nslot x R
-    double* Ksc = Tscr + U.off_T;
-    double* Tf = Ksc + N;
-    double* Ts = Tf + N;
-    double* Tb = Ts + N;
-    double* Tm = Tb + N;
-    const double* xi = t.xi + U.off_xi;
-    darcy_transmissibilities(t, D, xi, Ksc, Tf, Ts, Tb, Tm);
-
-    double* L = Lscr + U.off_L;
-    double* Xu = X + U.off_X;
-    const int tid = threadIdx.x;
-    // initial window: columns / rows 0 .. b
-    for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
-        const int col = idx / bw, d = idx - col * bw;
-        band[col * bw + d] = band_entry(Tf, Ts, Tb, col, d, b, N);
-    }
-    for (int idx = tid; idx < (b + 1) * R; idx += blockDim.x) {
-        const int row = idx / R, r = idx - row * R;
-        rhs[row * R + r] = rhs_entry(t, D, Tm, row, r);
-    }
-    __syncthreads();
-    int sj = 0;  // slot of column j
-    for (int j = 0; j < N; ++j) {
-        const double* colj = band + sj * bw;
-        const double dj = colj[0];
-        const double dinv = 1.0 / dj;
-        const double rinv = rsqrt(dj);
-        // rank-1 update of the trailing window: A[j+i, j+m] -= a_i a_m / d
-        for (int idx = tid; idx < b * b; idx += blockDim.x) {
-            const int m = 1 + idx / b, i = 1 + idx - (m - 1) * b;
-            if (m > i) continue;
-            int sm_ = sj + m;
-            if (sm_ >= nslot) sm_ -= nslot;
-            band[sm_ * bw + (i - m)] -= colj[i] * colj[m] * dinv;
-        }
-        // forward substitution of the right-hand sides
-        const double* rj = rhs + sj * R;
-        for (int idx = tid; idx < b * R; idx += blockDim.x) {
-            const int i = 1 + idx / R, r = idx - (i - 1) * R;
-            int si = sj + i;
-            if (si >= nslot) si -= nslot;
-            rhs[si * R + r] -= colj[i] * rj[r] * dinv;
-        }
-        // outputs: column j of L and row j of W = L^{-1} E
-        for (int d = tid; d < bw; d += blockDim.x) L[(int64_t)j * bw + d] = (d == 0) ? dj * rinv : colj[d] * rinv;
-        for (int r = tid; r < R; r += blockDim.x) Xu[(int64_t)j * R + r] = rj[r] * rinv;
-        // load column / row j + b + 1 into the free slot
-        int sn = sj + b + 1;
-        if (sn >= nslot) sn -= nslot;
-        for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = band_entry(Tf, Ts, Tb, j + b + 1, d, b, N);
-        for (int r = tid; r < R; r += blockDim.x) rhs[sn * R + r] = rhs_entry(t, D, Tm, j + b + 1, r);
-        __syncthreads();
-        sj = (sj + 1 == nslot) ? 0 : sj + 1;
-    }
-    // backward sweep: X = L^{-T} W, columns of L from the scratch
-    {
-        // window holds columns / rows N-1-b .. N-1 at slot col mod nslot
-        for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
-            const int q = idx / bw, d = idx - q * bw;
-            const int col = N - 1 - q;
-            if (col >= 0) band[(col % nslot) * bw + d] = L[(int64_t)col * bw + d];
-        }
-        for (int idx = tid; idx < (b + 1) * R; idx += blockDim.x) {
-            const int q = idx / R, r = idx - q * R;
-            const int row = N - 1 - q;
-            if (row >= 0) rhs[(row % nslot) * R + r] = Xu[(int64_t)row * R + r];
-        }
-        __syncthreads();
-        for (int j = N - 1; j >= 0; --j) {
-            const int s = j % nslot;
-            const double linv = 1.0 / band[s * bw];
-            for (int idx = tid; idx < b * R; idx += blockDim.x) {
-                const int i = 1 + idx / R, r = idx - (i - 1) * R;
-                const int row = j - i;
-                if (row < 0) continue;
-                const int sr = row % nslot;
-                rhs[sr * R + r] -= band[sr * bw + i] * rhs[s * R + r] * linv;
-            }
-            for (int r = tid; r < R; r += blockDim.x) Xu[(int64_t)j * R + r] = rhs[s * R + r] * linv;
-            const int col = j - b - 1;
-            if (col >= 0) {
-                const int sn = col % nslot;
-                for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = L[(int64_t)col * bw + d];
-                for (int r = tid; r < R; r += blockDim.x) rhs[sn * R + r] = Xu[(int64_t)col * R + r];
-            }
-            __syncthreads();
-        }
-    }
-    // flux basis: S[m, jj] = sum_{e in supp(m)} Pi[e, m] T_e (Pi[e, jj] - X[cell(e), jj])
-    double* S = S_cache + U.off_S;
-    const int* sp = t.supp_ptr + D.off_supp;
-    const double* Pi = t.Pi + D.off_Pi;
-    const int* mec = t.me_cell + D.off_me;
-    for (int o = tid; o < R * R; o += blockDim.x) {
-        const int m = o % R, jj = o / R;
-        double s = 0.0;
-        for (int q = sp[m]; q < sp[m + 1]; ++q) {
-            const int e = t.supp_e[q];
-            s += t.supp_v[q] * Tm[e] * (Pi[(int64_t)e * R + jj] - Xu[(int64_t)mec[e] * R + jj]);
-        }
-        S[(int64_t)jj * R + m] = s;
-    }
-}
-
-hipError_t launch_darcy_basis_fp64(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
-                                   double* X, double* Lscr, double* Tscr, hipStream_t stream) {
-    if (n_units <= 0) return hipSuccess;
-    const size_t lds = (size_t)(max_b + 2) * (max_b + 1 + max_R) * sizeof(double);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(darcy_basis_fp64_kernel, dim3(n_units), dim3(kThreads), lds, stream, t, S_cache, X, Lscr, Tscr);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Darcy basis, mixed precision: FP32 band factor and FP32 triangular sweeps,
-// FP64 residuals r = E - P X on the 5-point operator, corrections solved with
-// the FP32 factor until max|r| <= tol max|E| (or max_refine sweeps); S and X
-// in FP64.
-// ---------------------------------------------------------------------------
-__device__ void sweep_solve_fp32(const DarcyDev& D, const float* __restrict__ L, float* __restrict__ W,
-                                 float* band, float* rhs) {
-    // in-place solve L L^T y = W (W: N x R, internal order) with L in FP32 scratch
-    const int N = D.N, b = D.b, R = D.R, nslot = b + 2, bw = b + 1;
-    const int tid = threadIdx.x;
-    // forward: y = L^{-1} W, window of L columns j .. j + b
-    for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
-        const int col = idx / bw, d = idx - col * bw;
-        band[col * bw + d] = col < N ? L[(int64_t)col * bw + d] : 0.0f;
-    }
-    for (int idx = tid; idx < (b + 1) * R; idx += blockDim.x) {
-        const int row = idx / R, r = idx - row * R;
-        rhs[row * R + r] = row < N ? W[(int64_t)row * R + r] : 0.0f;
-    }
-    __syncthreads();
-    int sj = 0;
-    for (int j = 0; j < N; ++j) {
-        const float* colj = band + sj * bw;
-        const float linv = 1.0f / colj[0];
-        const float* rj = rhs + sj * R;
-        for (int idx = tid; idx < b * R; idx += blockDim.x) {
-            const int i = 1 + idx / R, r = idx - (i - 1) * R;
-            int si = sj + i;
-            if (si >= nslot) si -= nslot;
-            rhs[si * R + r] -= colj[i] * rj[r] * linv;
-        }
-        for (int r = tid; r < R; r += blockDim.x) W[(int64_t)j * R + r] = rj[r] * linv;
-        int sn = sj + b + 1;
-        if (sn >= nslot) sn -= nslot;
-        const int col = j + b + 1;
-        for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = col < N ? L[(int64_t)col * bw + d] : 0.0f;
-        for (int r = tid; r < R; r += blockDim.x) rhs[sn * R + r] = col < N ? W[(int64_t)col * R + r] : 0.0f;
-        __syncthreads();
-        sj = (sj + 1 == nslot) ? 0 : sj + 1;
-    }
-    // backward
-    for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
-        const int q = idx / bw, d = idx - q * bw;
-        const int col = N - 1 - q;
-        if (col >= 0) band[(col % nslot) * bw + d] = L[(int64_t)col * bw + d];
-    }
-    for (int idx = tid; idx < (b + 1) * R; idx += blockDim.x) {
-        const int q = idx / R, r = idx - q * R;
-        const int row = N - 1 - q;
-        if (row >= 0) rhs[(row % nslot) * R + r] = W[(int64_t)row * R + r];
-    }
-    __syncthreads();
-    for (int j = N - 1; j >= 0; --j) {
-        const int s = j % nslot;
-        const float linv = 1.0f / band[s * bw];
-        for (int idx = tid; idx < b * R; idx += blockDim.x) {
-            const int i = 1 + idx / R, r = idx - (i - 1) * R;
-            const int row = j - i;
-            if (row < 0) continue;
-            const int sr = row % nslot;
-            rhs[sr * R + r] -= band[sr * bw + i] * rhs[s * R + r] * linv;
-        }
-        for (int r = tid; r < R; r += blockDim.x) W[(int64_t)j * R + r] = rhs[s * R + r] * linv;
-        const int col = j - b - 1;
-        if (col >= 0) {
-            const int sn = col % nslot;
-            for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = L[(int64_t)col * bw + d];
-            for (int r = tid; r < R; r += blockDim.x) rhs[sn * R + r] = W[(int64_t)col * R + r];
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void darcy_basis_mixed_kernel(DarcyTables t, double* __restrict__ S_cache,
-                                                                     double* __restrict__ X, float* __restrict__ L32,
-                                                                     double* __restrict__ Tscr, float* __restrict__ W32,
-                                                                     int max_refine, double tol, double* max_res,
-                                                                     int* steps) {
-    extern __shared__ double smd[];
-    float* sm = reinterpret_cast<float*>(smd);
-    __shared__ double red[kThreads / 64];
-    const UnitDev U = t.units[blockIdx.x];
-    const DarcyDev D = t.dar[U.d];
-    const int N = D.N, b = D.b, R = D.R;
-    const int nslot = b + 2, bw = b + 1;
-    float* band = sm;
-    float* rhs = band + nslot * bw;
-    double* Ksc = Tscr + U.off_T;
-    double* Tf = Ksc + N;
-    double* Ts = Tf + N;
-    double* Tb = Ts + N;
-    double* Tm = Tb + N;
-    const double* xi = t.xi + U.off_xi;
-    darcy_transmissibilities(t, D, xi, Ksc, Tf, Ts, Tb, Tm);
-    float* L = L32 + U.off_L;
-    float* W = W32 + U.off_X;
-    double* Xu = X + U.off_X;
-    const int tid = threadIdx.x;
-    // FP32 factorisation (no right-hand sides in the window)
-    for (int idx = tid; idx < (b + 1) * bw; idx += blockDim.x) {
-        const int col = idx / bw, d = idx - col * bw;
-        band[col * bw + d] = (float)band_entry(Tf, Ts, Tb, col, d, b, N);
-    }
-    __syncthreads();
-    int sj = 0;
-    for (int j = 0; j < N; ++j) {
-        const float* colj = band + sj * bw;
-        const float dj = colj[0];
-        const float dinv = 1.0f / dj;
-        const float rinv = rsqrtf(dj);
-        for (int idx = tid; idx < b * b; idx += blockDim.x) {
-            const int m = 1 + idx / b, i = 1 + idx - (m - 1) * b;
-            if (m > i) continue;
-            int sm_ = sj + m;
-            if (sm_ >= nslot) sm_ -= nslot;
-            band[sm_ * bw + (i - m)] -= colj[i] * colj[m] * dinv;
-        }
-        for (int d = tid; d < bw; d += blockDim.x) L[(int64_t)j * bw + d] = (d == 0) ? dj * rinv : colj[d] * rinv;
-        int sn = sj + b + 1;
-        if (sn >= nslot) sn -= nslot;
-        for (int d = tid; d < bw; d += blockDim.x) band[sn * bw + d] = (float)band_entry(Tf, Ts, Tb, j + b + 1, d, b, N);
-        __syncthreads();
-        sj = (sj + 1 == nslot) ? 0 : sj + 1;
-    }
-    // X = 0; residual r = E - P X in FP64; W = (float) r; solve; X += W
-    double emax = 0.0;
-    for (int idx = tid; idx < N * R; idx += blockDim.x) {
-        const int row = idx / R, r = idx - row * R;
-        const double e = rhs_entry(t, D, Tm, row, r);
-        Xu[idx] = 0.0;
-        W[idx] = (float)e;
-        emax = fmax(emax, fabs(e));
-    }
-    // block max through the sum helper on a one-hot scheme: use a max reduction
-    {
-        double v = emax;
-        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-        __syncthreads();
-        if ((tid & 63) == 0) red[tid >> 6] = v;
-        __syncthreads();
-        emax = 0.0;
-        for (int k = 0; k < kThreads / 64; ++k) emax = fmax(emax, red[k]);
-        __syncthreads();
-    }
-    int it = 0;
-    double rmax = emax;
-    while (true) {
-        sweep_solve_fp32(D, L, W, band, rhs);
-        // X += W; residual in FP64
-        for (int idx = tid; idx < N * R; idx += blockDim.x) Xu[idx] += (double)W[idx];
-        __syncthreads();
-        ++it;
-        double lmax = 0.0;
-        for (int idx = tid; idx < N * R; idx += blockDim.x) {
-            const int c = idx / R, r = idx - c * R;
-            double v = rhs_entry(t, D, Tm, c, r);
-            double diag = Tf[c] + Ts[c] + Tb[c];
-            if (c % b) diag += Tf[c - 1];
-            if (c >= b) diag += Ts[c - b];
-            v -= diag * Xu[idx];
-            if ((c % b) != b - 1) v += Tf[c] * Xu[idx + R];
-            if (c % b) v += Tf[c - 1] * Xu[idx - R];
-            if (c + b < N) v += Ts[c] * Xu[idx + (int64_t)b * R];
-            if (c >= b) v += Ts[c - b] * Xu[idx - (int64_t)b * R];
-            W[idx] = (float)v;
-            lmax = fmax(lmax, fabs(v));
-        }
-        double v = lmax;
-        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-        __syncthreads();
-        if ((tid & 63) == 0) red[tid >> 6] = v;
-        __syncthreads();
-        rmax = 0.0;
-        for (int k = 0; k < kThreads / 64; ++k) rmax = fmax(rmax, red[k]);
-        __syncthreads();
-        if (rmax <= tol * emax || it > max_refine) break;
-    }
-    if (tid == 0) {
-        atomicAdd(steps, it - 1);
-        const double rel = emax > 0 ? rmax / emax : 0.0;
-        // non-negative doubles order like their bit patterns
-        atomicMax(reinterpret_cast<unsigned long long*>(max_res), (unsigned long long)__double_as_longlong(rel));
-    }
-    double* S = S_cache + U.off_S;
-    const int* sp = t.supp_ptr + D.off_supp;
-    const double* Pi = t.Pi + D.off_Pi;
-    const int* mec = t.me_cell + D.off_me;
-    for (int o = tid; o < R * R; o += blockDim.x) {
-        const int m = o % R, jj = o / R;
-        double s = 0.0;
-        for (int q = sp[m]; q < sp[m + 1]; ++q) {
-            const int e = t.supp_e[q];
-            s += t.supp_v[q] * Tm[e] * (Pi[(int64_t)e * R + jj] - Xu[(int64_t)mec[e] * R + jj]);
-        }
-        S[(int64_t)jj * R + m] = s;
-    }
-}
-
-hipError_t launch_darcy_basis_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
-                                    double* X, float* Lscr32, double* Tscr, float* W32, double* /*Rres*/,
-                                    int max_refine, double refine_tol, double* max_res, int* steps,
-                                    hipStream_t stream) {
-    if (n_units <= 0) return hipSuccess;
-    const size_t lds = (size_t)(max_b + 2) * (max_b + 1 + max_R) * sizeof(float);
-    if (lds > 150 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(darcy_basis_mixed_kernel, dim3(n_units), dim3(kThreads), lds, stream, t, S_cache, X, Lscr32,
-                       Tscr, W32, max_refine, refine_tol, max_res, steps);
-    return hipGetLastError();
-}
 
 #include "darcy_blocked.inc"
 

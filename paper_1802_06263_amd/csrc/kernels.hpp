@@ -48,12 +48,6 @@ struct DarcyTables {
 };
 
 // Launchers (all enqueue on `stream`).
-hipError_t launch_darcy_basis_fp64(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
-                                   double* X, double* Lscr, double* Tscr, hipStream_t stream);
-hipError_t launch_darcy_basis_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
-                                    double* X, float* Lscr32, double* Tscr, float* W32, double* Rres,
-                                    int max_refine, double refine_tol, double* max_res, int* steps,
-                                    hipStream_t stream);
 
 size_t darcy_blocked_lds(int max_b, int max_R, size_t elem);
 hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
