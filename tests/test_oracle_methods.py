@@ -143,3 +143,17 @@ def test_moments_are_weighted_sums(cfg0_oracle):
     lam = np.stack([d["lambda"] for d in info])
     assert np.allclose(mom["lambda"][0], w @ lam, rtol=1e-14, atol=1e-15)
     assert np.allclose(mom["lambda"][1], w @ lam ** 2 - (w @ lam) ** 2, rtol=1e-12, atol=1e-14)
+
+
+def test_closed_form_stokes_pressure_on_the_cfg1_meshes():
+    """sigma^2 = 0 on the cfg1 layout (Stokes 32x32 Q2-Q1): p_s = 1 and
+    u = (0, -1) exactly in the discrete spaces.  The saddle solves must reach
+    the discrete solution to near machine precision: with one refinement
+    step after the sparse LU the pressure error is about 1e-11 (from the CG
+    tolerance); without it, about 1e-9."""
+    o = Oracle(problem("cfg1", sigma2=0.0))
+    f, it, rel, ok = o.realization_S2(0, rtol=1e-13)
+    assert ok
+    assert np.abs(f["stokes_p"] - 1.0).max() < 1e-10
+    su = f["stokes_u"]
+    assert np.abs(su[0::2]).max() < 1e-11 and np.abs(su[1::2] + 1).max() < 1e-11
