@@ -191,6 +191,13 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream);
  * The signs of Stokes-Stokes mortar DOFs are included. */
 int sdmm_get_basis(sdmm_ctx* ctx, int sub, int k, double* S, int64_t ld);
 
+/* The interface right-hand side g_H (host, M values; Section 5.1, the
+ * complementary Stokes solutions of eqs. barSproblem1-2 tested with the
+ * mortar functions) and the FETI matrix G (host, n_kernel x M, one row per
+ * rigid-motion mode of a floating Stokes subdomain: its velocity trace on
+ * the mortar functions).  Either pointer may be NULL.  Needs a built basis. */
+int sdmm_get_interface_data(sdmm_ctx* ctx, double* g, double* G);
+
 /* Solve S_H lambda = g_H (Section 5.1) for n global collocation points
  * with indices gidx (device int64, n), by CG with S_H applied from the
  * basis cache (Section 5.3, linear combinations of phi) and, with floating
@@ -226,6 +233,13 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
 #define SDMM_OPT_CG_GRAPH 2
 #define SDMM_OPT_KERNEL_TIMING 3
 int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value);
+/* Autotuner of the batched CG: times the steady-state cost per
+ * realization-iteration of candidate chunk sizes (512 .. 8192 and
+ * min(n, 16384)) on the first realizations of gidx (device int64, n) and
+ * keeps the fastest as SDMM_OPT_CG_CHUNK; *chunk_out (host, may be NULL)
+ * receives it.  Needs a built basis; results of later solves do not depend
+ * on the choice.  Counters are left as they were.  Runs on `stream`. */
+int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, void* stream, int64_t* chunk_out);
 int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out);
 
 #ifdef __cplusplus

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -45,6 +46,16 @@ struct sdmm_ctx {
     int max_b = 0, max_R = 0, max_Rd = 0, max_ext = 0;
     int64_t n_units = 0;
     std::vector<UnitDev> units;
+    // Darcy units grouped by shape class (padded band bp, padded R): each
+    // class is one launch with LDS sized for it, on its own stream
+    struct UnitClass {
+        int base, count, bp, Rs;
+    };
+    std::vector<UnitClass> classes;
+    std::vector<int> h_order;
+    DevBuf d_order;
+    std::vector<hipStream_t> class_streams;
+    std::vector<hipEvent_t> class_events;
     std::vector<int64_t> sub_Sbase, sub_Abase;
     std::vector<int> sub_R, sub_region, sub_ker, sub_Gcol, sub_nlocal;
     std::vector<StokesDev> sdev;
@@ -59,7 +70,7 @@ struct sdmm_ctx {
         d_xi, d_supp_ptr, d_supp_e, d_supp_v, d_me_cell;
     DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_E, d_refine;
     DevBuf d_sdev, d_tiles, d_rhs, d_U, d_P, d_bmap, d_Z, d_q_ptr, d_q_col, d_q_val, d_uD, d_uD_off, d_tr_sub, d_tr_r,
-        d_tr_c, d_tr_v;
+        d_tr_c, d_tr_v, d_cptr, d_ccol, d_cval, d_rhs0, d_res;
     DevBuf d_g, d_G, d_GtGinv, d_Grow, d_Gval;
     int nGrow = 0;
     DevBuf d_sub_R, d_sub_dof_ptr, d_sub_dofs, d_sub_region, d_sub_Sbase, d_g2l, d_weights;
@@ -140,6 +151,8 @@ DarcyTables darcy_tables(sdmm_ctx* c) {
     t.supp_e = c->d_supp_e.as<int>();
     t.supp_v = c->d_supp_v.as<double>();
     t.me_cell = c->d_me_cell.as<int>();
+    t.order = c->d_order.as<int>();
+    t.unit_base = 0;
     return t;
 }
 
@@ -284,10 +297,33 @@ int setup_device(sdmm_ctx* ctx) {
     ctx->n_units = (int64_t)ctx->units.size();
     if (darcy_blocked_lds(ctx->max_b, ctx->max_Rd, 8) > 160 * 1024)
         return fail(ctx, SDMM_EINVAL, "a Darcy subdomain's band window does not fit in LDS (shorter side too long)");
+    {
+        // shape classes, most expensive unit shape first
+        std::map<std::pair<int, int>, std::vector<int>> cls;
+        for (size_t u = 0; u < ctx->units.size(); ++u) {
+            const DarcyHost& h = P.darcy[ctx->units[u].d];
+            cls[{(h.b + 15) / 16 * 16, (h.R + 3) & ~3}].push_back((int)u);
+        }
+        std::vector<std::pair<double, std::pair<int, int>>> rank;
+        for (auto& kv : cls) {
+            const DarcyHost& h = P.darcy[ctx->units[kv.second[0]].d];
+            const double cost = (double)h.N * kv.first.first * (kv.first.first + kv.first.second);
+            rank.push_back({-cost, kv.first});
+        }
+        std::sort(rank.begin(), rank.end());
+        ctx->classes.clear();
+        ctx->h_order.clear();
+        for (auto& rk : rank) {
+            const auto& ids = cls[rk.second];
+            ctx->classes.push_back({(int)ctx->h_order.size(), (int)ids.size(), rk.second.first, rk.second.second});
+            ctx->h_order.insert(ctx->h_order.end(), ids.begin(), ids.end());
+        }
+    }
     // ---- Stokes
     ctx->sdev.clear();
-    std::vector<int> tr_sub, tr_r, tr_c, bmap, q_ptr, q_col;
-    std::vector<double> tr_v, Zc, q_val, uD;
+    std::vector<int> tr_sub, tr_r, tr_c, bmap, q_ptr, q_col, ccol;
+    std::vector<double> tr_v, Zc, q_val, uD, cval;
+    std::vector<int64_t> cptr;
     std::vector<int64_t> uD_off;
     int64_t tiles_off = 0, rhs_off = 0, U_off = 0, P_off = 0;
     int gcol = 0;
@@ -335,6 +371,24 @@ int setup_device(sdmm_ctx* ctx) {
             tr_r.push_back(h.ar[q]);
             tr_c.push_back(h.ac[q]);
             tr_v.push_back(h.av[q]);
+        }
+        {
+            // the full symmetric band matrix as CSR, columns ascending per row
+            s.off_cptr = (int64_t)cptr.size();
+            std::vector<std::vector<std::pair<int, double>>> rows(h.nband);
+            for (size_t q = 0; q < h.ar.size(); ++q) {
+                rows[h.ar[q]].push_back({h.ac[q], h.av[q]});
+                if (h.ar[q] != h.ac[q]) rows[h.ac[q]].push_back({h.ar[q], h.av[q]});
+            }
+            for (int r = 0; r < h.nband; ++r) {
+                std::sort(rows[r].begin(), rows[r].end());
+                cptr.push_back((int64_t)ccol.size());
+                for (auto& e : rows[r]) {
+                    ccol.push_back(e.first);
+                    cval.push_back(e.second);
+                }
+            }
+            cptr.push_back((int64_t)ccol.size());
         }
         const int i = h.sub;
         ctx->sub_R[i] = h.R;
@@ -387,6 +441,7 @@ int setup_device(sdmm_ctx* ctx) {
     if ((rc = upload(ctx, buf, vec))) return rc;
     UP(ctx->d_dar, dar);
     UP(ctx->d_units, ctx->units);
+    UP(ctx->d_order, ctx->h_order);
     UP(ctx->d_be_cell, be_cell);
     UP(ctx->d_be_kind, be_kind);
     UP(ctx->d_be_len, be_len);
@@ -413,6 +468,9 @@ int setup_device(sdmm_ctx* ctx) {
     UP(ctx->d_tr_r, tr_r);
     UP(ctx->d_tr_c, tr_c);
     UP(ctx->d_tr_v, tr_v);
+    UP(ctx->d_cptr, cptr);
+    UP(ctx->d_ccol, ccol);
+    UP(ctx->d_cval, cval);
     std::vector<int64_t> dofs(P.sub_dofs.begin(), P.sub_dofs.end());
     UP(ctx->d_sub_dofs, dofs);
     UP(ctx->d_sub_dof_ptr, P.sub_ptr);
@@ -480,6 +538,9 @@ int setup_device(sdmm_ctx* ctx) {
     }
     ctx->d_rhs.release();
     if ((rc = upload(ctx, ctx->d_rhs, rhs))) return rc;
+    ctx->d_rhs0.release();
+    if ((rc = upload(ctx, ctx->d_rhs0, rhs))) return rc;
+    if ((rc = alloc(ctx, ctx->d_res, std::max<size_t>(rhs.size(), 1) * 8))) return rc;
     HIPCHK(hipMemset(ctx->d_acc.p, 0, ctx->d_acc.bytes));
     HIPCHK(hipMemset(ctx->d_lam1.p, 0, ctx->d_lam1.bytes));
     HIPCHK(hipMemset(ctx->d_lam2.p, 0, ctx->d_lam2.bytes));
@@ -501,6 +562,17 @@ int build_stokes(sdmm_ctx* ctx, hipStream_t st) {
     HIPCHK(launch_stokes_pad_identity(sd, ns, ctx->max_nblk, tiles, st));
     for (int J = 0; J < ctx->max_nblk; ++J) HIPCHK(launch_stokes_ldl_step(sd, ns, J, ctx->max_w, tiles, st));
     HIPCHK(launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, ctx->d_rhs.as<double>(), st));
+    // two steps of FP64 iterative refinement: the LDL^T without pivoting of
+    // the saddle matrix loses digits that the refined solution recovers
+    for (int step = 0; step < 2; ++step) {
+        HIPCHK(launch_stokes_residual(sd, ns, ctx->max_nblk, ctx->max_ncol, ctx->d_cptr.as<int64_t>(),
+                                      ctx->d_ccol.as<int>(), ctx->d_cval.as<double>(), ctx->d_rhs0.as<double>(),
+                                      ctx->d_rhs.as<double>(), ctx->d_res.as<double>(), st));
+        HIPCHK(launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, ctx->d_res.as<double>(),
+                                   st));
+        HIPCHK(launch_add_inplace(ctx->d_rhs.as<double>(), ctx->d_res.as<double>(),
+                                  (int64_t)(ctx->d_rhs.bytes / 8), st));
+    }
     HIPCHK(launch_stokes_finish(sd, ns, ctx->max_ncol, ctx->max_R, ctx->d_rhs.as<double>(), ctx->d_bmap.as<int>(),
                                 ctx->d_uD.as<double>(), ctx->d_uD_off.as<int64_t>(), ctx->d_Z.as<double>(),
                                 ctx->d_q_ptr.as<int>(), ctx->d_q_col.as<int>(), ctx->d_q_val.as<double>(),
@@ -729,6 +801,48 @@ int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
 
 }  // namespace
 
+namespace {
+
+// One launch per shape class, each on its own stream (forked from and joined
+// back into `st`), largest class first; a single class runs on `st` itself.
+template <class F>
+hipError_t launch_classes(sdmm_ctx* ctx, hipStream_t st, F&& launch) {
+    DarcyTables t = darcy_tables(ctx);
+    const int nc = (int)ctx->classes.size();
+    if (nc == 1) {
+        const auto& c = ctx->classes[0];
+        t.unit_base = c.base;
+        return launch(t, c.count, c.bp, c.Rs, st);
+    }
+    const int ns = std::min(nc, 4);
+    hipError_t e;
+    while ((int)ctx->class_streams.size() < ns) {
+        hipStream_t q = nullptr;
+        if ((e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking)) != hipSuccess) return e;
+        ctx->class_streams.push_back(q);
+    }
+    while ((int)ctx->class_events.size() < ns + 1) {
+        hipEvent_t ev = nullptr;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+        ctx->class_events.push_back(ev);
+    }
+    if ((e = hipEventRecord(ctx->class_events[ns], st)) != hipSuccess) return e;
+    for (int q = 0; q < ns; ++q)
+        if ((e = hipStreamWaitEvent(ctx->class_streams[q], ctx->class_events[ns], 0)) != hipSuccess) return e;
+    for (int c = 0; c < nc; ++c) {
+        const auto& cl = ctx->classes[c];
+        t.unit_base = cl.base;
+        if ((e = launch(t, cl.count, cl.bp, cl.Rs, ctx->class_streams[c % ns])) != hipSuccess) return e;
+    }
+    for (int q = 0; q < ns; ++q) {
+        if ((e = hipEventRecord(ctx->class_events[q], ctx->class_streams[q])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st, ctx->class_events[q], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 int sdmm_create(int device, sdmm_ctx** out) {
@@ -770,6 +884,10 @@ int sdmm_destroy(sdmm_ctx* ctx) {
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->kev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->class_events)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& q : ctx->class_streams)
+        if (q) (void)hipStreamDestroy(q);
     delete ctx;
     return SDMM_OK;
 }
@@ -890,11 +1008,12 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
     if (precision != SDMM_PREC_FP64 && precision != SDMM_PREC_MIXED) return fail(ctx, SDMM_EINVAL, "bad precision");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    DarcyTables t = darcy_tables(ctx);
     HIPCHK(hipEventRecord(ctx->ev[0], st));
     if (precision == SDMM_PREC_FP64) {
-        HIPCHK(launch_darcy_basis_blocked(t, (int)ctx->n_units, ctx->max_b, ctx->max_Rd, ctx->d_S.as<double>(),
-                                          ctx->d_X.as<double>(), ctx->d_L.as<double>(), ctx->d_T.as<double>(), st));
+        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, hipStream_t q) {
+            return launch_darcy_basis_blocked(tc, count, bp, Rs, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
+                                              ctx->d_L.as<double>(), ctx->d_T.as<double>(), q);
+        }));
     } else {
         int rc;
         if (!ctx->d_L32.p && (rc = alloc(ctx, ctx->d_L32, ctx->L_total * 4))) return rc;
@@ -903,10 +1022,12 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
         HIPCHK(hipMemsetAsync(ctx->d_refine.p, 0, 16, st));
         double* max_res = ctx->d_refine.as<double>();
         int* steps = reinterpret_cast<int*>(ctx->d_refine.as<char>() + 8);
-        HIPCHK(launch_darcy_basis_blocked_mixed(t, (int)ctx->n_units, ctx->max_b, ctx->max_Rd, ctx->d_S.as<double>(),
-                                                ctx->d_X.as<double>(), ctx->d_E.as<double>(), ctx->d_L32.as<float>(),
-                                                ctx->d_T.as<double>(), ctx->d_W32.as<float>(), 4, 1e-13, max_res, steps,
-                                                st));
+        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, hipStream_t q) {
+            return launch_darcy_basis_blocked_mixed(tc, count, bp, Rs, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
+                                                    ctx->d_E.as<double>(), ctx->d_L32.as<float>(),
+                                                    ctx->d_T.as<double>(), ctx->d_W32.as<float>(), 4, 1e-13, max_res,
+                                                    steps, q);
+        }));
     }
     HIPCHK(hipEventRecord(ctx->ev[1], st));
     if (!ctx->stokes_built) {
@@ -940,6 +1061,18 @@ int sdmm_get_basis(sdmm_ctx* ctx, int sub, int k, double* S, int64_t ld) {
                      hipMemcpyDeviceToHost));
     for (int j = 0; j < R; ++j)
         for (int m = 0; m < R; ++m) S[(int64_t)j * ld + m] = tmp[(size_t)j * R + m];
+    return SDMM_OK;
+}
+
+int sdmm_get_interface_data(sdmm_ctx* ctx, double* g, double* G) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    const size_t M = ctx->P.M;
+    if (g) HIPCHK(hipMemcpy(g, ctx->d_g.p, M * 8, hipMemcpyDeviceToHost));
+    if (G && ctx->P.n_kernel > 0) HIPCHK(hipMemcpy(G, ctx->d_G.p, (size_t)ctx->P.n_kernel * M * 8, hipMemcpyDeviceToHost));
     return SDMM_OK;
 }
 
@@ -1147,6 +1280,65 @@ int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double r
     if (hipEventElapsedTime(&ms, ctx->ev[3], ctx->ev[4]) == hipSuccess) ctx->counters.ms_solve = ms;
     if (brk) return fail(ctx, SDMM_EBREAKDOWN, "CG breakdown in some realization");
     if (bad) return fail(ctx, SDMM_ENOTCONV, "some realization reached max_iter");
+    return SDMM_OK;
+}
+
+int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, void* stream, int64_t* chunk_out) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    if (n < 1 || !gidx) return fail(ctx, SDMM_EINVAL, "invalid arguments");
+    if (n > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t user = (hipStream_t)stream;
+    hipStream_t st = work_stream(ctx, user);
+    HIPCHK(hipEventRecord(ctx->ev[5], user));
+    HIPCHK(hipStreamWaitEvent(st, ctx->ev[5], 0));
+    int rc;
+    if ((rc = check_indices(ctx, gidx, n, st))) return rc;
+    std::vector<int64_t> cand;
+    for (int64_t c : {512, 1024, 2048, 3072, 4096, 6144, 8192})
+        if (c < n) cand.push_back(c);
+    cand.push_back(std::min<int64_t>(n, 16384));
+    const int64_t cmax = cand.back();
+    if ((rc = ensure_workspace(ctx, cmax))) return rc;
+    DevBuf lam;
+    if ((rc = alloc(ctx, lam, (size_t)cmax * ctx->P.M * 8))) return rc;
+    const int64_t saved = ctx->opt_chunk;
+    const sdmm_counters saved_counters = ctx->counters;
+    const int short_it = ctx->opt_check, long_it = ctx->opt_check * 5;
+    double best = 1e300;
+    int64_t best_c = cand.back();
+    for (int64_t c : cand) {
+        // steady-state time per realization-iteration: the difference of a
+        // short and a long run removes the per-chunk set-up
+        double t[2];
+        for (int pass = 0; pass < 2; ++pass) {
+            int64_t tot = 0;
+            bool bad = false, brk = false;
+            HIPCHK(hipStreamSynchronize(st));
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = solve_chunk(ctx, c, gidx, 1e-300, pass ? long_it : short_it, lam.as<double>(), nullptr, nullptr,
+                             nullptr, st, tot, bad, brk);
+            if (rc) {
+                ctx->opt_chunk = saved;
+                ctx->counters = saved_counters;
+                return rc;
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            t[pass] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        const double per = (t[1] - t[0]) / ((double)c * (long_it - short_it));
+        if (per < best) {
+            best = per;
+            best_c = c;
+        }
+    }
+    ctx->counters = saved_counters;
+    ctx->opt_chunk = best_c;
+    if (chunk_out) *chunk_out = best_c;
+    HIPCHK(hipEventRecord(ctx->ev[4], st));
+    HIPCHK(hipStreamWaitEvent(user, ctx->ev[4], 0));
     return SDMM_OK;
 }
 

@@ -421,6 +421,48 @@ hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int ma
     return hipGetLastError();
 }
 
+// res = b - A x for every right-hand side column (one thread per band row;
+// padding rows get 0).
+__global__ void stokes_residual_kernel(const StokesDev* sd, const int64_t* __restrict__ cptr,
+                                       const int* __restrict__ ccol, const double* __restrict__ cval,
+                                       const double* __restrict__ b, const double* __restrict__ x,
+                                       double* __restrict__ res) {
+    const StokesDev s = sd[blockIdx.z];
+    const int col = blockIdx.y;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ld = (int64_t)s.nblk * kTile;
+    if (col >= s.ncol || row >= ld) return;
+    const int64_t base = s.off_rhs + (int64_t)col * ld;
+    double r = 0.0;
+    if (row < s.nband) {
+        r = b[base + row];
+        const int64_t q0 = cptr[s.off_cptr + row], q1 = cptr[s.off_cptr + row + 1];
+        for (int64_t q = q0; q < q1; ++q) r -= cval[q] * x[base + ccol[q]];
+    }
+    res[base + row] = r;
+}
+
+hipError_t launch_stokes_residual(const StokesDev* sd, int ns, int max_nblk, int max_ncol, const int64_t* cptr,
+                                  const int* ccol, const double* cval, const double* b, const double* x, double* res,
+                                  hipStream_t stream) {
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stokes_residual_kernel, dim3((max_nblk * kTile + 255) / 256, max_ncol, ns), dim3(256), 0,
+                       stream, sd, cptr, ccol, cval, b, x, res);
+    return hipGetLastError();
+}
+
+__global__ void add_inplace_kernel(double* __restrict__ x, const double* __restrict__ d, int64_t n) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        x[q] += d[q];
+}
+
+hipError_t launch_add_inplace(double* x, const double* d, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(add_inplace_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, d, n);
+    return hipGetLastError();
+}
+
 // Scatter the band solutions to raw velocity / pressure layouts, project the
 // floating subdomains' responses onto the complement of the rigid motions,
 // then S = -Q U (basis columns), g += Q u_bar and the FETI traces G = Q Z.

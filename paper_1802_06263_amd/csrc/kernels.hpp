@@ -45,6 +45,8 @@ struct DarcyTables {
     const int* supp_e;
     const double* supp_v;
     const int* me_cell;
+    const int* order;   // unit ids grouped by shape class
+    int unit_base;      // first entry of `order` this launch covers
 };
 
 // Launchers (all enqueue on `stream`).
@@ -70,6 +72,7 @@ struct StokesDev {
     int64_t off_S;      // basis cache offset
     int64_t off_dofs;   // local->global mortar DOFs
     int64_t off_G;      // first column of this subdomain's kernel traces in G
+    int64_t off_cptr;   // CSR row pointer base of the full band matrix (nband + 1)
 };
 
 hipError_t launch_stokes_scatter(const StokesDev* sd, int ns, const int* tr_sub, const int* tr_r, const int* tr_c,
@@ -78,6 +81,12 @@ hipError_t launch_stokes_pad_identity(const StokesDev* sd, int ns, int max_nblk,
 hipError_t launch_stokes_ldl_step(const StokesDev* sd, int ns, int J, int max_w, double* tiles, hipStream_t stream);
 hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol, const double* tiles,
                                double* rhs, hipStream_t stream);
+// FP64 iterative refinement of the band solves: res = b - A x with the full
+// band matrix in CSR (fixed summation order), then x += d after d = A^{-1} res.
+hipError_t launch_stokes_residual(const StokesDev* sd, int ns, int max_nblk, int max_ncol, const int64_t* cptr,
+                                  const int* ccol, const double* cval, const double* b, const double* x, double* res,
+                                  hipStream_t stream);
+hipError_t launch_add_inplace(double* x, const double* d, int64_t n, hipStream_t stream);
 hipError_t launch_stokes_finish(const StokesDev* sd, int ns, int max_ncol, int max_R, const double* rhs, const int* bmap,
                                 const double* uD, const int64_t* uD_off, const double* Z, const int* q_ptr,
                                 const int* q_col, const double* q_val, const int64_t* dofs, double* U, double* P,

@@ -64,6 +64,8 @@ EXPORTS = {
     "sdmm_solve_interface": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double,
                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "sdmm_get_interface_data": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
+    "sdmm_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, _i64p]),
     "sdmm_accumulate_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p]),
     "sdmm_get_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _f64p, _f64p]),
@@ -240,6 +242,20 @@ class Context:
         rc = self.lib.sdmm_solve_interface(self.h, n, _dptr(gidx), float(rtol), int(max_iter), _dptr(lam),
                                            _dptr(iters), _dptr(relres), _dptr(status), _stream(stream))
         return self._check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+
+    def interface_data(self):
+        """(g_H [M], G [n_kernel x M]) as host arrays."""
+        M, nk = self._sizes["M"], self._sizes["n_kernel"]
+        g = np.zeros(M)
+        G = np.zeros((max(nk, 1), M))
+        self._check(self.lib.sdmm_get_interface_data(self.h, _ptr(g, ctypes.c_double), _ptr(G, ctypes.c_double)))
+        return g, G[:nk]
+
+    def autotune(self, gidx, stream=None):
+        """Pick the CG chunk size on gidx (int64 device tensor); returns it."""
+        out = ctypes.c_int64()
+        self._check(self.lib.sdmm_autotune(self.h, gidx.numel(), _dptr(gidx), _stream(stream), ctypes.byref(out)))
+        return out.value
 
     def accumulate_moments(self, gidx, lam, weights=None, stream=None):
         self._check(self.lib.sdmm_accumulate_moments(self.h, gidx.numel(), _dptr(gidx), _dptr(lam),

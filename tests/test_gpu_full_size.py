@@ -1,0 +1,174 @@
+"""Full-size parity of the HIP path (needs an MI355X).
+
+cfg1 is small enough for the oracle to run whole: every realization through
+Method S3 at rtol 1e-13, compared field by field with the GPU moments.  On
+cfg2 and cfg3 the oracle computes sampled flux bases one by one (one unit
+per Darcy mesh shape on cfg3, i.e. every shape class of the launch), and the
+CG and moment results are checked through properties that hold at any size:
+
+  * the true FETI-projected residual P (g - S lambda) of every sampled
+    realization, recomputed on the host in FP64 from the library's own
+    S blocks (pinned by the sampled bases), g and G, is at most 2e-8 ||P g||
+    (the CG stops on its recursive residual, which differs from the true one
+    by rounding), and G^T lambda = 0;
+  * the mean and variance of lambda equal the weighted sums of the returned
+    realizations (Section 2 with the collocation weights of Section 4).
+
+Tolerances for S and the moments are those of test_gpu_parity.
+"""
+import numpy as np
+import pytest
+
+from oracle import interface as itf
+from oracle.collocation import Grid
+from oracle.darcy import DarcyLocal
+from oracle.geometry import Layout
+from oracle.kl import cell_centres, region_field
+from oracle.methods import FIELDS, Oracle
+from workloads import problem
+
+from gpu_helpers import gpu_ctx, gpu_solve, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_unit_basis(L, grid, i, k):
+    """S_{H,i}^{(k)} of one Darcy unit by the oracle (Section 5.4)."""
+    sub = L.subs[i]
+    reg = L.regions[sub["region"]]
+    phi = region_field(reg, cell_centres(sub))
+    y = grid.local_points(sub["region"])[k]
+    K = np.exp(float(reg["mean_logk"]) + np.asarray(y) @ phi)
+    return DarcyLocal(L, i, K).basis()
+
+
+def sampled_units(L, grid, name, rng):
+    darcy = [i for i in range(L.nsub) if L.subs[i]["type"] == "darcy"]
+    if name == "cfg3":
+        # one unit per Darcy mesh shape: every shape class of the launch
+        seen = {}
+        for i in darcy:
+            seen.setdefault(tuple(L.subs[i]["n"]), i)
+        subs = list(seen.values())
+    else:
+        subs = [darcy[0], darcy[len(darcy) // 2], darcy[-1]]
+    return [(i, int(rng.integers(grid.nlocal[L.subs[i]["region"]]))) for i in subs]
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 1e-10)])
+def test_sampled_basis_parity_full_size(name, precision, tol):
+    print("case: sampled basis", name, precision, flush=True)
+    prob = problem(name)
+    L = Layout(prob)
+    grid = Grid(prob["regions"], prob["rule"])
+    ctx = gpu_ctx(prob, precision)
+    if precision == "mixed":
+        assert ctx.counters()["max_refine_residual"] <= 1e-12
+    rng = np.random.default_rng(11)
+    for i, k in sampled_units(L, grid, name, rng):
+        S = oracle_unit_basis(L, grid, i, k)
+        Sg = ctx.get_basis(i, k, S.shape[0])
+        assert rel(Sg, S) < tol, (name, i, k, rel(Sg, S))
+    ctx.close()
+
+
+def test_cfg1_all_realizations_match_oracle():
+    print("case: cfg1 full collocation loop vs oracle", flush=True)
+    o = Oracle(problem("cfg1"))
+    # rtol 1e-13 on both sides: at 1e-12 the two CGs stop at points whose
+    # difference, amplified by the Stokes pressure recovery, reaches 1e-9
+    mom, info = o.run("S3", rtol=1e-13)
+    ctx = gpu_ctx(o.prob, "fp64")
+    g_h, _ = ctx.interface_data()
+    assert rel(g_h, o.g_stokes) < 1e-11
+    n = o.grid.nreal
+    g, lam, it, rr, st, rc = gpu_solve(ctx, np.arange(n), rtol=1e-13)
+    assert (st == 0).all()
+    lam_o = np.stack([d["lambda"] for d in info])
+    assert rel(lam.cpu().numpy(), lam_o) < 1e-9
+    ctx.accumulate_moments(g, lam)
+    for f in FIELDS:
+        mg, vg = ctx.get_moments(f)
+        mo, vo = mom[f]
+        assert rel(mg, mo) < 1e-9, f
+        assert np.abs(vg - vo).max() < 1e-9 * max(np.abs(vo).max(), 1e-12 * np.abs(mo).max() ** 2), f
+    ctx.close()
+
+
+def _assembled_S(ctx, L, g2l, l):
+    S_loc = []
+    for i in range(L.nsub):
+        R = L.sub_dofs[i].size
+        k = 0 if L.subs[i]["type"] == "stokes" else int(g2l[l, L.subs[i]["region"]])
+        S_loc.append(ctx.get_basis(i, k, R))
+    return itf.assemble(L, S_loc)
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+def test_interface_residual_full_size(name):
+    print("case: CG residual property", name, flush=True)
+    prob = problem(name)
+    L = Layout(prob)
+    ctx = gpu_ctx(prob, "fp64")
+    sz = ctx.sizes()
+    n, nr = sz["n_real"], sz["n_region"]
+    g2l = ctx.index_map("g2l").reshape(n, nr)
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(n, 24, replace=False))
+    g, lam, it, rr, st, rc = gpu_solve(ctx, idx, rtol=1e-8)
+    assert (st == 0).all() and (rr <= 1e-8).all()
+    gH, G = ctx.interface_data()
+    assert G.shape[0] == sz["n_kernel"]
+    if G.shape[0]:
+        Q = np.linalg.solve(G @ G.T, G)
+
+        def proj(v):
+            return v - G.T @ (Q @ v)
+    else:
+        def proj(v):
+            return v
+    lam = lam.cpu().numpy()
+    for q, l in enumerate(idx):
+        S = _assembled_S(ctx, L, g2l, l)
+        r = proj(gH - S @ lam[q])
+        assert np.linalg.norm(r) <= 2e-8 * np.linalg.norm(proj(gH)), (name, l)
+        if G.shape[0]:
+            assert np.abs(G @ lam[q]).max() <= 1e-10 * np.abs(G).max() * np.abs(lam[q]).max()
+    ctx.close()
+
+
+def test_lambda_moments_are_weighted_sums_cfg2():
+    print("case: cfg2 lambda moments vs weighted sums", flush=True)
+    import torch
+    ctx = gpu_ctx(problem("cfg2"), "fp64")
+    n = ctx.sizes()["n_real"]
+    g, lam, it, rr, st, rc = gpu_solve(ctx, np.arange(n), rtol=1e-8)
+    assert (st == 0).all()
+    ctx.accumulate_moments(g, lam)
+    torch.cuda.synchronize()
+    _, w = ctx.collocation()
+    lam = lam.cpu().numpy()
+    mean = w @ lam
+    m2 = w @ (lam * lam)
+    mg, vg = ctx.get_moments("lambda")
+    assert rel(mg, mean) < 1e-12
+    assert np.abs(vg - (m2 - mean ** 2)).max() < 1e-12 * np.abs(m2).max()
+    ctx.close()
+
+
+def test_autotune_keeps_results():
+    print("case: autotune on the small FETI case", flush=True)
+    prob = problem("cfg2", stokes_mesh=(8, 8), darcy_mesh=(4, 4), mortar={"degree": 1, "elements": 2})
+    ctx = gpu_ctx(prob, "fp64")
+    n = ctx.sizes()["n_real"]
+    g, lam0, it0, _, st0, _ = gpu_solve(ctx, np.arange(n), rtol=1e-10)
+    c0 = ctx.counters()
+    chunk = ctx.autotune(g)
+    assert chunk in (512, 1024, 2048, 3072, 4096, 6144, 8192, min(n, 16384))
+    c1 = ctx.counters()
+    assert c1["cg_iterations"] == c0["cg_iterations"]
+    _, lam1, it1, _, st1, _ = gpu_solve(ctx, np.arange(n), rtol=1e-10)
+    assert np.array_equal(lam0.cpu().numpy(), lam1.cpu().numpy())
+    assert np.array_equal(it0, it1) and np.array_equal(st0, st1)
+    ctx.close()
