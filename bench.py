@@ -284,6 +284,8 @@ def main():
     stokes_ms = ctx.counters()["ms_basis_stokes"]
     g = torch.arange(n, dtype=torch.int64, device="cuda")
     lam = torch.zeros((n, M), dtype=torch.float64, device="cuda")
+    chunk = ctx.autotune(g, rtol=args.rtol)
+    log("autotuned CG chunk: %d realizations" % chunk)
     ctx.set_option("kernel_timing", 1)
     other = "fp64" if args.precision == "mixed" else "mixed"
     res, kern = {}, {}
@@ -317,7 +319,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
            "config": {"workload": args.workload, "n_real": n, "M": M, "basis_units": sz["n_units"],
-                      "precision": args.precision, "rtol": args.rtol},
+                      "precision": args.precision, "rtol": args.rtol, "cg_chunk": chunk},
            "basis_builds_per_s": main_r["basis_builds_per_s"],
            "fp64": res.get("fp64"), "mixed": res.get("mixed"), "stokes_basis_ms": stokes_ms,
            "roofline": roof, "kernels": kmain}

@@ -233,13 +233,15 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
 #define SDMM_OPT_CG_GRAPH 2
 #define SDMM_OPT_KERNEL_TIMING 3
 int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value);
-/* Autotuner of the batched CG: times the steady-state cost per
- * realization-iteration of candidate chunk sizes (512 .. 8192 and
- * min(n, 16384)) on the first realizations of gidx (device int64, n) and
+/* Autotuner of the batched CG: runs the first min(n, 16384) realizations of
+ * gidx (device int64, n) through the whole CG (rtol, max_iter as in
+ * sdmm_solve_interface) once per candidate chunk size (the sample split into
+ * 1..4 equal chunks, and the default sized for a ~200 MB cache budget) and
  * keeps the fastest as SDMM_OPT_CG_CHUNK; *chunk_out (host, may be NULL)
  * receives it.  Needs a built basis; results of later solves do not depend
  * on the choice.  Counters are left as they were.  Runs on `stream`. */
-int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, void* stream, int64_t* chunk_out);
+int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,
+                  int64_t* chunk_out);
 int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out);
 
 #ifdef __cplusplus

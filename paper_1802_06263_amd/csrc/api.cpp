@@ -1283,11 +1283,12 @@ int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double r
     return SDMM_OK;
 }
 
-int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, void* stream, int64_t* chunk_out) {
+int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,
+                  int64_t* chunk_out) {
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
-    if (n < 1 || !gidx) return fail(ctx, SDMM_EINVAL, "invalid arguments");
+    if (n < 1 || !gidx || !(rtol > 0) || max_iter < 1) return fail(ctx, SDMM_EINVAL, "invalid arguments");
     if (n > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t user = (hipStream_t)stream;
@@ -1296,41 +1297,50 @@ int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, void* stream, i
     HIPCHK(hipStreamWaitEvent(st, ctx->ev[5], 0));
     int rc;
     if ((rc = check_indices(ctx, gidx, n, st))) return rc;
-    std::vector<int64_t> cand;
-    for (int64_t c : {512, 1024, 2048, 3072, 4096, 6144, 8192})
-        if (c < n) cand.push_back(c);
-    cand.push_back(std::min<int64_t>(n, 16384));
-    const int64_t cmax = cand.back();
-    if ((rc = ensure_workspace(ctx, cmax))) return rc;
-    DevBuf lam;
-    if ((rc = alloc(ctx, lam, (size_t)cmax * ctx->P.M * 8))) return rc;
+    // the sample: the first realizations of the batch; candidates split it
+    // into 1..4 equal chunks, plus the cache-budget default
+    const int64_t ns = std::min<int64_t>(n, 16384);
     const int64_t saved = ctx->opt_chunk;
+    ctx->opt_chunk = 0;
+    std::vector<int64_t> cand;
+    for (int k = 1; k <= 4; ++k) {
+        const int64_t c = (ns + k - 1) / k;
+        if (c >= 256 || k == 1) cand.push_back(c);
+    }
+    cand.push_back(chunk_size(ctx, ns));
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    if ((rc = ensure_workspace(ctx, cand.back()))) {
+        ctx->opt_chunk = saved;
+        return rc;
+    }
+    DevBuf lam;
+    if ((rc = alloc(ctx, lam, (size_t)ns * ctx->P.M * 8))) {
+        ctx->opt_chunk = saved;
+        return rc;
+    }
     const sdmm_counters saved_counters = ctx->counters;
-    const int short_it = ctx->opt_check, long_it = ctx->opt_check * 5;
     double best = 1e300;
     int64_t best_c = cand.back();
     for (int64_t c : cand) {
-        // steady-state time per realization-iteration: the difference of a
-        // short and a long run removes the per-chunk set-up
-        double t[2];
-        for (int pass = 0; pass < 2; ++pass) {
-            int64_t tot = 0;
-            bool bad = false, brk = false;
-            HIPCHK(hipStreamSynchronize(st));
-            const auto t0 = std::chrono::steady_clock::now();
-            rc = solve_chunk(ctx, c, gidx, 1e-300, pass ? long_it : short_it, lam.as<double>(), nullptr, nullptr,
-                             nullptr, st, tot, bad, brk);
-            if (rc) {
-                ctx->opt_chunk = saved;
-                ctx->counters = saved_counters;
-                return rc;
-            }
-            HIPCHK(hipStreamSynchronize(st));
-            t[pass] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        // the whole sample through CG with chunks of c: per-chunk tails and
+        // cache residency are both in the measurement
+        int64_t tot = 0;
+        bool bad = false, brk = false;
+        HIPCHK(hipStreamSynchronize(st));
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int64_t c0 = 0; c0 < ns && !rc; c0 += c)
+            rc = solve_chunk(ctx, std::min(c, ns - c0), gidx + c0, rtol, max_iter, lam.as<double>() + c0 * ctx->P.M,
+                             nullptr, nullptr, nullptr, st, tot, bad, brk);
+        if (rc) {
+            ctx->opt_chunk = saved;
+            ctx->counters = saved_counters;
+            return rc;
         }
-        const double per = (t[1] - t[0]) / ((double)c * (long_it - short_it));
-        if (per < best) {
-            best = per;
+        HIPCHK(hipStreamSynchronize(st));
+        const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (t < best) {
+            best = t;
             best_c = c;
         }
     }

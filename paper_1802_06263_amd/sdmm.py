@@ -65,7 +65,8 @@ EXPORTS = {
                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
     "sdmm_get_interface_data": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
-    "sdmm_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, _i64p]),
+    "sdmm_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_void_p, _i64p]),
     "sdmm_accumulate_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p]),
     "sdmm_get_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _f64p, _f64p]),
@@ -251,10 +252,13 @@ class Context:
         self._check(self.lib.sdmm_get_interface_data(self.h, _ptr(g, ctypes.c_double), _ptr(G, ctypes.c_double)))
         return g, G[:nk]
 
-    def autotune(self, gidx, stream=None):
+    def autotune(self, gidx, rtol=1e-8, max_iter=None, stream=None):
         """Pick the CG chunk size on gidx (int64 device tensor); returns it."""
         out = ctypes.c_int64()
-        self._check(self.lib.sdmm_autotune(self.h, gidx.numel(), _dptr(gidx), _stream(stream), ctypes.byref(out)))
+        if max_iter is None:
+            max_iter = 10 * self._sizes["M"]
+        self._check(self.lib.sdmm_autotune(self.h, gidx.numel(), _dptr(gidx), float(rtol), int(max_iter),
+                                           _stream(stream), ctypes.byref(out)))
         return out.value
 
     def accumulate_moments(self, gidx, lam, weights=None, stream=None):
