@@ -295,7 +295,8 @@ int setup_device(sdmm_ctx* ctx) {
         edge_tot += (int64_t)(h.nx + 1) * h.ny + (int64_t)h.nx * (h.ny + 1);
     }
     ctx->n_units = (int64_t)ctx->units.size();
-    if (darcy_blocked_lds(ctx->max_b, ctx->max_Rd, 8) > 160 * 1024)
+    if (darcy_factor_lds((ctx->max_b + 15) / 16 * 16, 8) > 150 * 1024 ||
+        darcy_solve_lds((ctx->max_b + 15) / 16 * 16, ctx->max_Rd, 8) > 150 * 1024)
         return fail(ctx, SDMM_EINVAL, "a Darcy subdomain's band window does not fit in LDS (shorter side too long)");
     {
         // shape classes, most expensive unit shape first

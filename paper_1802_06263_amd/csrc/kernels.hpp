@@ -51,7 +51,8 @@ struct DarcyTables {
 
 // Launchers (all enqueue on `stream`).
 
-size_t darcy_blocked_lds(int max_b, int max_R, size_t elem);
+size_t darcy_factor_lds(int bp, size_t elem);
+size_t darcy_solve_lds(int bp, int R, size_t elem);
 hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
                                       double* X, double* Lscr, double* Tscr, hipStream_t stream);
 hipError_t launch_darcy_basis_blocked_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
