@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--single", action="store_true", help="time only --precision (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (scale reference for HBM counters)")
+    ap.add_argument("--cg-chunk", type=int, default=0, help="CG chunk size (0: autotune)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -284,8 +285,12 @@ def main():
     stokes_ms = ctx.counters()["ms_basis_stokes"]
     g = torch.arange(n, dtype=torch.int64, device="cuda")
     lam = torch.zeros((n, M), dtype=torch.float64, device="cuda")
-    chunk = ctx.autotune(g, rtol=args.rtol)
-    log("autotuned CG chunk: %d realizations" % chunk)
+    if args.cg_chunk > 0:
+        chunk = args.cg_chunk
+        ctx.set_option("cg_chunk", chunk)
+    else:
+        chunk = ctx.autotune(g, rtol=args.rtol)
+        log("autotuned CG chunk: %d realizations" % chunk)
     ctx.set_option("kernel_timing", 1)
     other = "fp64" if args.precision == "mixed" else "mixed"
     res, kern = {}, {}
@@ -296,7 +301,7 @@ def main():
                      "basis_builds_per_s": sz["n_units"] / (bms * 1e-3),
                      "local_solves_per_s": d["basis_solves_darcy"] / (args.steps * bms * 1e-3),
                      "cg_iterations_mean": d["cg_iterations"] / max(1, d["realizations"]),
-                     "refinement_steps_per_unit": (ctx.counters()["refinement_steps"] / sz["n_units"]
+                     "refinement_group_steps_per_unit": (ctx.counters()["refinement_steps"] / sz["n_units"]
                                                    if prec == "mixed" else 0.0),
                      "cg_launches_per_step": d["cg_launches"] / args.steps}
     main_r = res[args.precision]

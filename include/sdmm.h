@@ -130,7 +130,8 @@ typedef struct {
     int64_t basis_solves_stokes;  /* sum over Stokes subdomains of R_i          */
     int64_t complementary_solves; /* solves for g_H (once, deterministic)       */
     int64_t units_built;          /* Darcy (i, k) bases built                   */
-    int64_t refinement_steps;     /* FP64 refinement sweeps of the last mixed build */
+    int64_t refinement_steps;     /* FP64 refinement steps of the last mixed build,
+                                     summed over the right-hand-side groups   */
     int64_t cg_iterations;        /* summed over realizations                   */
     int64_t realizations;         /* taken through CG                           */
     double ms_basis_darcy;        /* last build: Darcy units                    */

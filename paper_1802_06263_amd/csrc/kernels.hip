@@ -601,18 +601,19 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
 
 // Grouped operator: one workgroup per (subdomain i, local realization k,
 // 64-row block of S_{i,k}, chunk of <= 64 realizations whose local index in
-// i's KL region is k).  The row block of S and the gathered coefficients sit
-// in LDS; four waves compute the 64 x 64 product with FP64 MFMA (16x16x4,
-// 2 x 2 tiles per wave), so each S entry is read once per chunk.  Results go
+// i's KL region is k).  16-wide k-chunks of the S row block and of the
+// gathered coefficients are staged in LDS (16.5 KB, so LDS does not limit
+// occupancy); four waves compute the 64 x 64 product with FP64 MFMA
+// (16x16x4, 2 x 2 tiles per wave), so each S entry is read once per chunk.  Results go
 // to Y (n x sum_i R_i, subdomain-local layout) with plain stores; the CG
 // update adds the two contributions of every mortar DOF in a fixed order.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kThreads) void cg_apply_mfma_kernel(CgArgs a, const double* __restrict__ xloc,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void cg_apply_mfma_kernel(CgArgs a, const double* __restrict__ xloc,
                                                                  double* __restrict__ Y, int64_t SR,
                                                                  const int4* __restrict__ work,
                                                                  const int* __restrict__ perm) {
-    constexpr int KC = 32;                       // k-chunk of S columns staged in LDS
+    constexpr int KC = 16;                       // k-chunk of S columns staged in LDS
     __shared__ double St[KC * 64];               // St[j][r] = S[row0 + r][k0 + j]
     __shared__ double Xs[KC * 65];               // Xs[j][c] = x_{l_c}[local DOF k0 + j], stride 65
     __shared__ int64_t rowoff[64];
@@ -631,26 +632,27 @@ __global__ __launch_bounds__(kThreads) void cg_apply_mfma_kernel(CgArgs a, const
     dbl4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
     for (int k0 = 0; k0 < R; k0 += KC) {
         __syncthreads();
-        // 8 independent loads per thread for each operand
-        double sv[8], xv[8];
+        // KC / 4 independent loads per thread for each operand
+        constexpr int NL = KC * 64 / kThreads;
+        double sv[NL], xv[NL];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < NL; ++q) {
             const int idx = tid + q * kThreads;
             const int j = idx >> 6, r = idx & 63;
             sv[q] = (k0 + j < R && r < nrow) ? S[(int64_t)(k0 + j) * R + row0 + r] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < NL; ++q) {
             const int idx = tid + q * kThreads;
-            const int c = idx >> 5, j = idx & 31;
+            const int c = idx / KC, j = idx % KC;
             const int64_t ro = rowoff[c];
             xv[q] = (ro >= 0 && k0 + j < R) ? xloc[ro + k0 + j] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < NL; ++q) {
             const int idx = tid + q * kThreads;
             St[idx] = sv[q];
-            Xs[(idx & 31) * 65 + (idx >> 5)] = xv[q];
+            Xs[(idx % KC) * 65 + idx / KC] = xv[q];
         }
         __syncthreads();
         // transposed product Y^T = X^T S^T: tile rows are realizations, columns
@@ -737,15 +739,16 @@ hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int
 // is assembled in LDS (both subdomain contributions of every mortar DOF, in a
 // fixed order); the FETI projection touches only the rows of G that belong to
 // floating subdomains.
-constexpr int kMaxQ = 8;
-constexpr int kMaxM = kThreads * kMaxQ;
-
-__global__ __launch_bounds__(kThreads) void cg_update2_kernel(CgArgs a, const double* __restrict__ Y, int64_t SR,
+// kMaxQ: vector entries per thread (M <= kThreads kMaxQ), so registers and
+// LDS match the problem; W: waves per SIMD the register budget is held to
+// (the most without spills: 8 up to M = 1280)
+template <int kMaxQ, int W>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))) void cg_update2_kernel(CgArgs a, const double* __restrict__ Y, int64_t SR,
                                                               const int* __restrict__ pos) {
     __shared__ double red[kThreads / 64];
     __shared__ double redk[16][kThreads / 64];
     __shared__ double coef[32];
-    __shared__ double aps[kMaxM];
+    __shared__ double aps[kThreads * kMaxQ];
     const int64_t l = blockIdx.x;
     if (!a.active[l]) return;
     const int M = a.M, tid = threadIdx.x;
@@ -854,9 +857,27 @@ __global__ __launch_bounds__(kThreads) void cg_update2_kernel(CgArgs a, const do
     if (tid == 0) a.rr[l] = rrn;
 }
 
-hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream) {
-    hipLaunchKernelGGL(cg_update2_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, Y, SR, pos);
+template <int Q>
+static hipError_t launch_update2_q(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream) {
+    auto kern = cg_update2_kernel<Q, (Q <= 5 ? 8 : Q == 6 ? 6 : 5)>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, Y, SR, pos);
     return hipGetLastError();
+}
+
+hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream) {
+    if (a.n <= 0) return hipSuccess;
+    switch ((a.M + kThreads - 1) / kThreads) {
+        case 0:
+        case 1: return launch_update2_q<1>(a, Y, SR, pos, stream);
+        case 2: return launch_update2_q<2>(a, Y, SR, pos, stream);
+        case 3: return launch_update2_q<3>(a, Y, SR, pos, stream);
+        case 4: return launch_update2_q<4>(a, Y, SR, pos, stream);
+        case 5: return launch_update2_q<5>(a, Y, SR, pos, stream);
+        case 6: return launch_update2_q<6>(a, Y, SR, pos, stream);
+        case 7:
+        case 8: return launch_update2_q<8>(a, Y, SR, pos, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // Number of realizations of the chunk still iterating (deterministic sum).
