@@ -738,75 +738,71 @@ hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int
 // launch is identical every iteration (graph capture).  The operator result
 // is assembled in LDS (both subdomain contributions of every mortar DOF, in a
 // fixed order); the FETI projection touches only the rows of G that belong to
-// floating subdomains.
+// floating subdomains.  Two barriers per iteration without floating
+// subdomains, five with; every sum has a fixed order.
 // kMaxQ: vector entries per thread (M <= kThreads kMaxQ), so registers and
 // LDS match the problem; W: waves per SIMD the register budget is held to
 // (the most without spills: 8 up to M = 1280)
 template <int kMaxQ, int W>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))) void cg_update2_kernel(CgArgs a, const double* __restrict__ Y, int64_t SR,
                                                               const int* __restrict__ pos) {
-    __shared__ double red[kThreads / 64];
-    __shared__ double redk[16][kThreads / 64];
+    __shared__ double red[kThreads / 64], red2[kThreads / 64];
     __shared__ double coef[32];
     __shared__ double aps[kThreads * kMaxQ];
     const int64_t l = blockIdx.x;
     if (!a.active[l]) return;
-    const int M = a.M, tid = threadIdx.x;
+    const int M = a.M, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double* r = a.r + l * M;
     double* pl = a.p + l * SR;   // search direction in the subdomain-local layout
     double* lam = a.lam + l * M;
     const double* Yl = Y + l * SR;
+    // A p, both subdomain contributions in a fixed order; p^T A p from the
+    // unprojected product (p stays in the range of the FETI projection P,
+    // so p^T P A p = p^T A p)
     double pv[kMaxQ], rv[kMaxQ];
+    double part = 0.0;
 #pragma unroll
     for (int q = 0; q < kMaxQ; ++q) {
         const int m = tid + q * kThreads;
         pv[q] = rv[q] = 0.0;
         if (m < M) {
             const int p0 = pos[2 * m], p1 = pos[2 * m + 1];
-            aps[m] = Yl[p0] + Yl[p1];
+            const double v = Yl[p0] + Yl[p1];
+            aps[m] = v;
             pv[q] = pl[p0];
             rv[q] = r[m];
+            part += pv[q] * v;
         }
     }
+    part = wave_sum(part);
+    if (lane == 0) red[wid] = part;
+    __syncthreads();
     const int nk = a.nker;
     if (nk > 0) {
-        __syncthreads();
-        // c = G^T ap over the rows of floating subdomains, all nk sums at once
-        for (int kk = 0; kk < nk; ++kk) {
-            double part = 0.0;
-            for (int q = tid; q < a.nGrow; q += kThreads) part += a.Gval[q * nk + kk] * aps[a.Grow[q]];
-            part = wave_sum(part);
-            if ((tid & 63) == 0) redk[kk][tid >> 6] = part;
-        }
-        __syncthreads();
-        if (tid < nk) {
-            double sum = 0.0;
-            for (int w = 0; w < kThreads / 64; ++w) sum += redk[tid][w];
-            coef[tid] = sum;
+        // c = G^T A p over the rows of floating subdomains (wave w: modes w, w + 4, ...)
+        for (int kk = wid; kk < nk; kk += kThreads / 64) {
+            double c = 0.0;
+            for (int q = lane; q < a.nGrow; q += 64) c += a.Gval[q * nk + kk] * aps[a.Grow[q]];
+            c = wave_sum(c);
+            if (lane == 0) coef[kk] = c;
         }
         __syncthreads();
         if (tid < nk) {
             double d = 0.0;
             for (int q = 0; q < nk; ++q) d += a.GtGinv[tid * nk + q] * coef[q];
-            coef[nk + tid] = d;
+            coef[16 + tid] = d;
         }
         __syncthreads();
+        // P A p = A p - G d on those rows
         for (int q = tid; q < a.nGrow; q += kThreads) {
             double c = 0.0;
-            for (int kk = 0; kk < nk; ++kk) c += a.Gval[q * nk + kk] * coef[nk + kk];
+            for (int kk = 0; kk < nk; ++kk) c += a.Gval[q * nk + kk] * coef[16 + kk];
             aps[a.Grow[q]] -= c;
         }
+        __syncthreads();
     }
-    __syncthreads();
-    double ap[kMaxQ];
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < kMaxQ; ++q) {
-        const int m = tid + q * kThreads;
-        ap[q] = m < M ? aps[m] : 0.0;
-        part += pv[q] * ap[q];
-    }
-    const double pAp = block_sum(part, red);
+    double pAp = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) pAp += red[w];
     const double rr = a.rr[l];
     const int iter = a.iters[l];
     if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -822,14 +818,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
 #pragma unroll
     for (int q = 0; q < kMaxQ; ++q) {
         const int m = tid + q * kThreads;
-        rv[q] -= alpha * ap[q];
-        part += rv[q] * rv[q];
         if (m < M) {
+            rv[q] -= alpha * aps[m];
             lam[m] += alpha * pv[q];
             r[m] = rv[q];
         }
+        part += rv[q] * rv[q];
     }
-    const double rrn = block_sum(part, red);
+    part = wave_sum(part);
+    if (lane == 0) red2[wid] = part;
+    __syncthreads();
+    double rrn = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) rrn += red2[w];
     const double rel = sqrt(rrn) / a.r0[l];
     const bool conv = rel <= a.rtol;
     const bool last = iter + 1 >= a.max_iter;
@@ -859,7 +859,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
 
 template <int Q>
 static hipError_t launch_update2_q(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream) {
-    auto kern = cg_update2_kernel<Q, (Q <= 5 ? 8 : Q == 6 ? 6 : 5)>;
+    auto kern = cg_update2_kernel<Q, (Q <= 3 ? 8 : Q == 4 ? 7 : Q == 5 ? 6 : Q == 6 ? 5 : 4)>;
     hipLaunchKernelGGL(kern, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, Y, SR, pos);
     return hipGetLastError();
 }
