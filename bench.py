@@ -240,12 +240,13 @@ def kernel_rooflines(sz, sum_R, sum_R2, d, basis_ms, prec, workload):
                            "sampled_ms": d["ms_cg_apply"]}
         t = read_traffic("cg_apply_mfma", workload)
         out["cg_apply"]["traffic"] = t * act if t is not None else None
-    # Darcy basis build: banded factor + forward/backward flops, one launch
+    # Darcy basis build: banded factor + forward/backward flops; one factor and
+    # one solve launch per shape class, timed together with HIP events
     peak = PEAK_FP32 if prec == "mixed" else PEAK_FP64
     ach = sz["darcy_flops"] / (basis_ms * 1e-3)
-    out["darcy_basis"] = {"kernel": "darcy_basis_blocked_%s_kernel" % prec, "bound": "alu",
+    out["darcy_basis"] = {"kernel": "darcy_factor_kernel + darcy_solve_%s_kernel" % prec, "bound": "alu",
                           "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
-                          "avg_launch_us": basis_ms * 1e3, "launches": 1,
+                          "avg_launch_us": basis_ms * 1e3, "launches": 2,
                           "algorithmic_flops_per_launch": sz["darcy_flops"], "traffic": None}
     return out
 
