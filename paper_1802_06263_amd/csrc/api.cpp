@@ -61,14 +61,14 @@ struct sdmm_ctx {
     std::vector<StokesDev> sdev;
     int max_nblk = 0, max_w = 0, max_ncol = 0, max_nout_d = 0, max_nout_s = 0, max_units_per_d = 0;
     int64_t n_trip = 0;
-    int64_t S_total = 0, X_total = 0, L_total = 0, T_total = 0, A_total = 0;
+    int64_t S_total = 0, X_total = 0, L_total = 0, T_total = 0, A_total = 0, I_total = 0;
     int64_t field_size[5] = {0, 0, 0, 0, 0};
     std::vector<int64_t> cell_out_off, edge_out_off, u_out_off, p_out_off;
     std::vector<int> pair_sub, pair_k;
     // device buffers
     DevBuf d_dar, d_units, d_be_cell, d_be_kind, d_be_len, d_be_hperp, d_be_medge, d_be_sgn, d_cell_be, d_Pi, d_phi,
         d_xi, d_supp_ptr, d_supp_e, d_supp_v, d_me_cell;
-    DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_E, d_refine;
+    DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_E, d_refine, d_I, d_I32;
     DevBuf d_sdev, d_tiles, d_rhs, d_U, d_P, d_bmap, d_Z, d_q_ptr, d_q_col, d_q_val, d_uD, d_uD_off, d_tr_sub, d_tr_r,
         d_tr_c, d_tr_v, d_cptr, d_ccol, d_cval, d_rhs0, d_res;
     DevBuf d_g, d_G, d_GtGinv, d_Grow, d_Gval;
@@ -180,7 +180,7 @@ int setup_device(sdmm_ctx* ctx) {
     ctx->sub_Gcol.assign(nsub, 0);
     ctx->sub_nlocal.assign(nsub, 1);
     ctx->sub_Abase.assign(nsub, 0);
-    int64_t S_off = 0, X_off = 0, L_off = 0, T_off = 0, A_off = 0;
+    int64_t S_off = 0, X_off = 0, L_off = 0, T_off = 0, A_off = 0, I_off = 0;
     ctx->max_b = 0;
     ctx->max_R = 0;
     ctx->max_Rd = 0;
@@ -273,11 +273,13 @@ int setup_device(sdmm_ctx* ctx) {
             u.off_X = X_off;
             u.off_L = L_off;
             u.off_T = T_off;
+            u.off_I = I_off;
             // the blocked factor pads rows to a multiple of 16 and the band to bp
             const int64_t Np = (h.N + 15) / 16 * 16, bp = (h.b + 15) / 16 * 16;
             S_off += (int64_t)h.R * h.R;
             X_off += Np * h.R;
             L_off += Np * (bp + 1);
+            I_off += Np * 16;
             T_off += (int64_t)4 * h.N + h.n_medge;
             A_off += (int64_t)h.R + (int64_t)h.R * h.R;
             ctx->units.push_back(u);
@@ -428,6 +430,7 @@ int setup_device(sdmm_ctx* ctx) {
     ctx->S_total = S_off;
     ctx->X_total = X_off;
     ctx->L_total = L_off;
+    ctx->I_total = I_off;
     ctx->T_total = T_off;
     ctx->A_total = A_off;
     ctx->field_size[0] = P.M;
@@ -512,6 +515,7 @@ int setup_device(sdmm_ctx* ctx) {
     if ((rc = alloc(ctx, ctx->d_S, ctx->S_total * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_X, ctx->X_total * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_L, ctx->L_total * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_I, std::max<int64_t>(ctx->I_total, 1) * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_T, ctx->T_total * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_tiles, tiles_off * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_rhs, rhs_off * 8))) return rc;
@@ -1013,11 +1017,12 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
     if (precision == SDMM_PREC_FP64) {
         HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, hipStream_t q) {
             return launch_darcy_basis_blocked(tc, count, bp, Rs, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
-                                              ctx->d_L.as<double>(), ctx->d_T.as<double>(), q);
+                                              ctx->d_L.as<double>(), ctx->d_I.as<double>(), ctx->d_T.as<double>(), q);
         }));
     } else {
         int rc;
         if (!ctx->d_L32.p && (rc = alloc(ctx, ctx->d_L32, ctx->L_total * 4))) return rc;
+        if (!ctx->d_I32.p && (rc = alloc(ctx, ctx->d_I32, std::max<int64_t>(ctx->I_total, 1) * 4))) return rc;
         if (!ctx->d_W32.p && (rc = alloc(ctx, ctx->d_W32, ctx->X_total * 4))) return rc;
         if (!ctx->d_E.p && (rc = alloc(ctx, ctx->d_E, ctx->X_total * 8))) return rc;
         HIPCHK(hipMemsetAsync(ctx->d_refine.p, 0, 16, st));
@@ -1026,6 +1031,7 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
         HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, hipStream_t q) {
             return launch_darcy_basis_blocked_mixed(tc, count, bp, Rs, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
                                                     ctx->d_E.as<double>(), ctx->d_L32.as<float>(),
+                                                    ctx->d_I32.as<float>(),
                                                     ctx->d_T.as<double>(), ctx->d_W32.as<float>(), 4, 1e-13, max_res,
                                                     steps, q);
         }));

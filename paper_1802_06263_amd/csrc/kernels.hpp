@@ -26,6 +26,7 @@ struct UnitDev {
     int64_t off_X;      // fine responses X (N x R, internal cell order)
     int64_t off_L;      // band factor scratch (N x (b + 1))
     int64_t off_T;      // K / transmissibility scratch (4 N + n_medge)
+    int64_t off_I;      // inverses of the 16 x 16 diagonal blocks of L (Np x 16)
 };
 
 struct DarcyTables {
@@ -54,10 +55,11 @@ struct DarcyTables {
 size_t darcy_factor_lds(int bp, size_t elem);
 size_t darcy_solve_lds(int bp, int R, size_t elem);
 hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
-                                      double* X, double* Lscr, double* Tscr, hipStream_t stream);
+                                      double* X, double* Lscr, double* Iscr, double* Tscr, hipStream_t stream);
 hipError_t launch_darcy_basis_blocked_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
-                                            double* X, double* E, float* L32, double* Tscr, float* W32, int max_refine,
-                                            double refine_tol, double* max_res, int* steps, hipStream_t stream);
+                                            double* X, double* E, float* L32, float* I32, double* Tscr, float* W32,
+                                            int max_refine, double refine_tol, double* max_res, int* steps,
+                                            hipStream_t stream);
 
 // Stokes: tiled band LDL^T (tile 64) of several subdomains at once.
 struct StokesDev {
