@@ -49,7 +49,7 @@ struct sdmm_ctx {
     // Darcy units grouped by shape class (padded band bp, padded R): each
     // class is one launch with LDS sized for it, on its own stream
     struct UnitClass {
-        int base, count, bp, Rs;
+        int base, count, bp, Rs, np;   // np: largest padded cell count of the class
     };
     std::vector<UnitClass> classes;
     std::vector<int> h_order;
@@ -318,7 +318,9 @@ int setup_device(sdmm_ctx* ctx) {
         ctx->h_order.clear();
         for (auto& rk : rank) {
             const auto& ids = cls[rk.second];
-            ctx->classes.push_back({(int)ctx->h_order.size(), (int)ids.size(), rk.second.first, rk.second.second});
+            int np = 0;
+            for (int u : ids) np = std::max(np, (P.darcy[ctx->units[u].d].N + 15) / 16 * 16);
+            ctx->classes.push_back({(int)ctx->h_order.size(), (int)ids.size(), rk.second.first, rk.second.second, np});
             ctx->h_order.insert(ctx->h_order.end(), ids.begin(), ids.end());
         }
     }
@@ -817,7 +819,7 @@ hipError_t launch_classes(sdmm_ctx* ctx, hipStream_t st, F&& launch) {
     if (nc == 1) {
         const auto& c = ctx->classes[0];
         t.unit_base = c.base;
-        return launch(t, c.count, c.bp, c.Rs, st);
+        return launch(t, c.count, c.bp, c.Rs, c.np, st);
     }
     const int ns = std::min(nc, 4);
     hipError_t e;
@@ -837,7 +839,7 @@ hipError_t launch_classes(sdmm_ctx* ctx, hipStream_t st, F&& launch) {
     for (int c = 0; c < nc; ++c) {
         const auto& cl = ctx->classes[c];
         t.unit_base = cl.base;
-        if ((e = launch(t, cl.count, cl.bp, cl.Rs, ctx->class_streams[c % ns])) != hipSuccess) return e;
+        if ((e = launch(t, cl.count, cl.bp, cl.Rs, cl.np, ctx->class_streams[c % ns])) != hipSuccess) return e;
     }
     for (int q = 0; q < ns; ++q) {
         if ((e = hipEventRecord(ctx->class_events[q], ctx->class_streams[q])) != hipSuccess) return e;
@@ -1015,8 +1017,8 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
     if (precision == SDMM_PREC_FP64) {
-        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, hipStream_t q) {
-            return launch_darcy_basis_blocked(tc, count, bp, Rs, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
+        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, int np, hipStream_t q) {
+            return launch_darcy_basis_blocked(tc, count, bp, Rs, np, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
                                               ctx->d_L.as<double>(), ctx->d_I.as<double>(), ctx->d_T.as<double>(), q);
         }));
     } else {
@@ -1028,8 +1030,8 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
         HIPCHK(hipMemsetAsync(ctx->d_refine.p, 0, 16, st));
         double* max_res = ctx->d_refine.as<double>();
         int* steps = reinterpret_cast<int*>(ctx->d_refine.as<char>() + 8);
-        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, hipStream_t q) {
-            return launch_darcy_basis_blocked_mixed(tc, count, bp, Rs, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
+        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, int np, hipStream_t q) {
+            return launch_darcy_basis_blocked_mixed(tc, count, bp, Rs, np, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
                                                     ctx->d_E.as<double>(), ctx->d_L32.as<float>(),
                                                     ctx->d_I32.as<float>(),
                                                     ctx->d_T.as<double>(), ctx->d_W32.as<float>(), 4, 1e-13, max_res,

@@ -54,12 +54,14 @@ struct DarcyTables {
 
 size_t darcy_factor_lds(int bp, size_t elem);
 size_t darcy_solve_lds(int bp, int R, size_t elem);
-hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
-                                      double* X, double* Lscr, double* Iscr, double* Tscr, hipStream_t stream);
-hipError_t launch_darcy_basis_blocked_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, double* S_cache,
-                                            double* X, double* E, float* L32, float* I32, double* Tscr, float* W32,
-                                            int max_refine, double refine_tol, double* max_res, int* steps,
-                                            hipStream_t stream);
+// max_np: largest padded cell count of the launch's units
+hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np,
+                                      double* S_cache, double* X, double* Lscr, double* Iscr, double* Tscr,
+                                      hipStream_t stream);
+hipError_t launch_darcy_basis_blocked_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np,
+                                            double* S_cache, double* X, double* E, float* L32, float* I32,
+                                            double* Tscr, float* W32, int max_refine, double refine_tol,
+                                            double* max_res, int* steps, hipStream_t stream);
 
 // Stokes: tiled band LDL^T (tile 64) of several subdomains at once.
 struct StokesDev {
