@@ -139,8 +139,8 @@ typedef struct {
     double ms_solve;              /* last solve_interface                       */
     double max_refine_residual;   /* largest relative residual after refinement */
     /* per-kernel timing of the CG iterations while SDMM_OPT_KERNEL_TIMING is
-     * on: one iteration of every convergence-check group is bracketed by HIP
-     * events on the stream the kernels run on; sums over all solves */
+     * on: one iteration of every fourth convergence-check group is bracketed
+     * by HIP events on the stream the kernels run on; sums over all solves */
     int64_t cg_launches;          /* product launches (= update launches), all   */
     int64_t cg_timed_launches;    /* sampled (product, update) launch pairs     */
     int64_t cg_timed_active;      /* realizations still iterating in them        */
@@ -225,9 +225,10 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
  *                      chunk's vectors fit a ~96 MB cache budget)
  *   SDMM_OPT_CG_CHECK  iterations between host convergence checks (1..1024)
  *   SDMM_OPT_CG_GRAPH  1 = replay the iteration group as a captured HIP graph
- *   SDMM_OPT_KERNEL_TIMING 1 = time one iteration of every check group with
- *                      HIP events and sum the durations into the counters
- *                      (launches then run eagerly, without graph replay)
+ *   SDMM_OPT_KERNEL_TIMING 1 = time one iteration of every fourth check group
+ *                      with HIP events and sum the durations into the
+ *                      counters (those groups run eagerly, the others replay
+ *                      the captured graph)
  * Results do not depend on any of them. */
 #define SDMM_OPT_CG_CHUNK 0
 #define SDMM_OPT_CG_CHECK 1

@@ -1128,12 +1128,15 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
     const int group = ctx->opt_check;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    // Kernel timing samples the second iteration of every check group: the
+    // Kernel timing samples the second iteration of one check group in
+    // kTimeEvery (the other groups replay the captured graph): the
     // active realizations are counted just before it (into the second int of
     // any_active), then events bracket its product and its update.  Earlier
     // iterations keep the queue ahead of the device, so the events time the
     // kernels and not host launch latency.
     const bool ktime = ctx->opt_ktime != 0;
+    constexpr int kTimeEvery = 4;
+    int ngroup = 0;
     const int tq = group > 1 ? 1 : 0;
     int32_t* tcount = a.any_active + 1;
     if (ktime) {
@@ -1143,10 +1146,10 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
             ctx->kev.push_back(e);
         }
     }
-    auto body = [&](hipStream_t s) -> hipError_t {
+    auto body = [&](hipStream_t s, bool timed_group) -> hipError_t {
         hipError_t e = hipSuccess;
         for (int q = 0; q < group && e == hipSuccess; ++q) {
-            const bool timed = ktime && q == tq;
+            const bool timed = timed_group && q == tq;
             if (timed) {
                 e = launch_count_active(a.active, n, tcount, s);
                 if (e == hipSuccess) e = hipEventRecord(ctx->kev[0], s);
@@ -1178,9 +1181,9 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
-        if (!ctx->opt_graph || ktime) return SDMM_OK;
+        if (!ctx->opt_graph) return SDMM_OK;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        hipError_t e = body(st);
+        hipError_t e = body(st, false);
         hipError_t e2 = hipStreamEndCapture(st, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -1200,18 +1203,21 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
     int32_t count = (int32_t)n;
     std::vector<int32_t> act;
     while (it < max_iter) {
-        if (exec) {
+        // one check group in kTimeEvery is timed (eager, with events); the
+        // others replay the captured graph when there is one
+        const bool timed_group = ktime && (ngroup++ % kTimeEvery == 0);
+        if (exec && !timed_group) {
             HIPCHK(hipGraphLaunch(exec, st));
         } else {
-            HIPCHK(body(st));
+            HIPCHK(body(st, timed_group));
         }
         it += group;
         ctx->counters.cg_launches += group;
         HIPCHK(launch_count_active(a.active, n, a.any_active, st));
         HIPCHK(hipMemcpyAsync(&count, a.any_active, 4, hipMemcpyDeviceToHost, st));
-        if (ktime) HIPCHK(hipMemcpyAsync(&tactive, tcount, 4, hipMemcpyDeviceToHost, st));
+        if (timed_group) HIPCHK(hipMemcpyAsync(&tactive, tcount, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (ktime && (rc = add_times())) return rc;
+        if (timed_group && (rc = add_times())) return rc;
         if (count == 0) break;
         // drop converged realizations from the operator once they are a
         // quarter of its work (their results are final)
