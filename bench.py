@@ -213,9 +213,9 @@ def kernel_rooflines(sz, sum_R, sum_R2, d, basis_ms, prec, workload):
     nl = d["cg_timed_launches"]
     if nl:
         act = d["cg_timed_active"] / nl
-        # CG update: reads the subdomain-local product Y (sum R_i), p (M), r
-        # and lambda; writes lambda, r and p in the local layout (sum R_i)
-        b_upd = 8.0 * (2 * sum_R + 5 * M)
+        # CG update: reads the subdomain-local product Y (sum R_i), p, r and
+        # lambda (M each); writes lambda, r and p (M each)
+        b_upd = 8.0 * (sum_R + 6 * M)
         avg = d["ms_cg_update"] * 1e-3 / nl
         per_launch = b_upd * act
         out["cg_update"] = {"kernel": "cg_update2_kernel", "bound": "hbm", "achieved": per_launch / avg / 1e9,
@@ -225,9 +225,10 @@ def kernel_rooflines(sz, sum_R, sum_R2, d, basis_ms, prec, workload):
                             "sampled_ms": d["ms_cg_update"]}
         t = read_traffic("cg_update2", workload)
         out["cg_update"]["traffic"] = t * act if t is not None else None
-        # CG product: 2 sum R_i^2 flops; reads p and writes Y in the local layout
+        # CG product: 2 sum R_i^2 flops; reads p (global layout, M) and writes
+        # Y in the subdomain-local layout (sum R_i)
         f_app = 2.0 * sum_R2
-        b_app = 8.0 * 2 * sum_R
+        b_app = 8.0 * (M + sum_R)
         avg = d["ms_cg_apply"] * 1e-3 / nl
         out["cg_apply"] = {"kernel": "cg_apply_mfma_kernel", "bound": "hbm",
                            "achieved": b_app * act / avg / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",

@@ -79,7 +79,7 @@ struct sdmm_ctx {
     DevBuf d_mom;  // p1 p2 u1 u2 for moments output
     DevBuf d_flag; // index validation flag
     // CG workspace
-    DevBuf w_r, w_p, w_Ap, w_rr, w_r0, w_iters, w_relres, w_status, w_active, w_any, w_alpha, w_Slam;
+    DevBuf w_r, w_p, w_rr, w_r0, w_iters, w_relres, w_status, w_active, w_any, w_alpha, w_Slam;
     int64_t w_cap = 0;
     // realization groups of the current chunk (grouped operator)
     DevBuf d_work, d_perm, d_awork, d_slot, d_part, d_item0, d_pos, w_Y;
@@ -662,7 +662,6 @@ CgArgs cg_args(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double* lam) {
     a.lam = lam;
     a.r = ctx->w_r.as<double>();
     a.p = ctx->w_p.as<double>();
-    a.Ap = ctx->w_Ap.as<double>();
     a.rr = ctx->w_rr.as<double>();
     a.r0 = ctx->w_r0.as<double>();
     a.iters = ctx->w_iters.as<int32_t>();
@@ -790,8 +789,7 @@ int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
     const size_t M = ctx->P.M;
     int rc;
     if ((rc = alloc(ctx, ctx->w_r, n * M * 8))) return rc;
-    if ((rc = alloc(ctx, ctx->w_p, n * (size_t)std::max<int64_t>(M, ctx->SR) * 8))) return rc;
-    if ((rc = alloc(ctx, ctx->w_Ap, n * M * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_p, n * M * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_Slam, n * M * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_rr, n * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_r0, n * 8))) return rc;
@@ -1122,9 +1120,7 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
     a.max_iter = max_iter;
     double* Y = ctx->w_Y.as<double>();
     const int* pos = ctx->d_pos.as<int>();
-    HIPCHK(launch_cg_init(a, st));
-    // search direction p_0 = r_0 in the subdomain-local layout
-    HIPCHK(launch_scatter_local(a.r, ctx->SR, pos, ctx->P.M, n, a.p, st));
+    HIPCHK(launch_cg_init(a, st));   // r_0, lambda_0 = 0 and p_0 = r_0
     const int group = ctx->opt_check;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -1140,7 +1136,7 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
     const int tq = group > 1 ? 1 : 0;
     int32_t* tcount = a.any_active + 1;
     if (ktime) {
-        while ((int)ctx->kev.size() < 3) {
+        while ((int)ctx->kev.size() < 4) {
             hipEvent_t e = nullptr;
             HIPCHK(hipEventCreate(&e));
             ctx->kev.push_back(e);
@@ -1150,16 +1146,14 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
         hipError_t e = hipSuccess;
         for (int q = 0; q < group && e == hipSuccess; ++q) {
             const bool timed = timed_group && q == tq;
-            if (timed) {
-                e = launch_count_active(a.active, n, tcount, s);
-                if (e == hipSuccess) e = hipEventRecord(ctx->kev[0], s);
-                if (e != hipSuccess) break;
-            }
+            if (timed && (e = launch_count_active(a.active, n, tcount, s)) != hipSuccess) break;
+            // timed launches stamp the events from their own dispatch packets
             e = launch_cg_apply_mfma(a, a.p, Y, ctx->SR, ctx->d_work.as<int4>(), ctx->nwork,
-                                     ctx->d_perm.as<int>(), ctx->max_R, s);
-            if (e == hipSuccess && timed) e = hipEventRecord(ctx->kev[1], s);
-            if (e == hipSuccess) e = launch_cg_update2(a, Y, ctx->SR, pos, s);
-            if (e == hipSuccess && timed) e = hipEventRecord(ctx->kev[2], s);
+                                     ctx->d_perm.as<int>(), ctx->max_R, s, timed ? ctx->kev[0] : nullptr,
+                                     timed ? ctx->kev[1] : nullptr);
+            if (e == hipSuccess)
+                e = launch_cg_update2(a, Y, ctx->SR, pos, s, timed ? ctx->kev[2] : nullptr,
+                                      timed ? ctx->kev[3] : nullptr);
         }
         return e;
     };
@@ -1168,7 +1162,7 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
     auto add_times = [&]() -> int {
         float ma = 0.f, mu = 0.f;
         HIPCHK(hipEventElapsedTime(&ma, ctx->kev[0], ctx->kev[1]));
-        HIPCHK(hipEventElapsedTime(&mu, ctx->kev[1], ctx->kev[2]));
+        HIPCHK(hipEventElapsedTime(&mu, ctx->kev[2], ctx->kev[3]));
         ctx->counters.ms_cg_apply += ma;
         ctx->counters.ms_cg_update += mu;
         ctx->counters.cg_timed_launches += 1;
@@ -1389,8 +1383,7 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const
         if ((rc = build_groups(ctx, cn, nullptr, st))) return rc;
         CgArgs a = cg_args(ctx, cn, g, const_cast<double*>(lam));
         if (ctx->P.n_kernel > 0) {
-            HIPCHK(launch_scatter_local(lam, ctx->SR, ctx->d_pos.as<int>(), M, cn, ctx->w_p.as<double>(), st));
-            HIPCHK(launch_cg_apply_mfma(a, ctx->w_p.as<double>(), ctx->w_Y.as<double>(), ctx->SR,
+            HIPCHK(launch_cg_apply_mfma(a, lam, ctx->w_Y.as<double>(), ctx->SR,
                                         ctx->d_work.as<int4>(), ctx->nwork, ctx->d_perm.as<int>(), ctx->max_R, st));
             HIPCHK(launch_gather_global(ctx->w_Y.as<double>(), ctx->SR, ctx->d_pos.as<int>(), M, cn,
                                         ctx->w_Slam.as<double>(), st));

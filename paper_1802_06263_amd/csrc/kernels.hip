@@ -15,6 +15,7 @@
 //                      of the basis (Section 5.3).
 //   accumulate / *_moments   weighted moments (Section 2, Step 6 of S3).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 
@@ -586,8 +587,12 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
     }
     __syncthreads();
     if (a.nker > 0) feti_project_row(a, r, red, coef);
+    double* p = a.p + l * a.M;
     double part = 0.0;
-    for (int m = threadIdx.x; m < a.M; m += blockDim.x) part += r[m] * r[m];
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
+        p[m] = r[m];   // p_0 = r_0
+        part += r[m] * r[m];
+    }
     const double rr = block_sum(part, red);
     if (threadIdx.x == 0) {
         a.rr[l] = rr;
@@ -602,21 +607,23 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
 // Grouped operator: one workgroup per (subdomain i, local realization k,
 // 64-row block of S_{i,k}, chunk of <= 64 realizations whose local index in
 // i's KL region is k).  16-wide k-chunks of the S row block and of the
-// gathered coefficients are staged in LDS (16.5 KB, so LDS does not limit
+// coefficients, gathered from the global mortar layout (x: n x M) through
+// i's DOF list, are staged in LDS (16.5 KB, so LDS does not limit
 // occupancy); four waves compute the 64 x 64 product with FP64 MFMA
 // (16x16x4, 2 x 2 tiles per wave), so each S entry is read once per chunk.  Results go
 // to Y (n x sum_i R_i, subdomain-local layout) with plain stores; the CG
 // update adds the two contributions of every mortar DOF in a fixed order.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void cg_apply_mfma_kernel(CgArgs a, const double* __restrict__ xloc,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void cg_apply_mfma_kernel(CgArgs a, const double* __restrict__ x,
                                                                  double* __restrict__ Y, int64_t SR,
                                                                  const int4* __restrict__ work,
                                                                  const int* __restrict__ perm) {
     constexpr int KC = 16;                       // k-chunk of S columns staged in LDS
     __shared__ double St[KC * 64];               // St[j][r] = S[row0 + r][k0 + j]
     __shared__ double Xs[KC * 65];               // Xs[j][c] = x_{l_c}[local DOF k0 + j], stride 65
-    __shared__ int64_t rowoff[64];
+    __shared__ int64_t rowoff[64];              // Y offset of each realization's block of i
+    __shared__ int64_t xoff[64];                // x offset of each realization
     const int4 wk = work[blockIdx.x];   // (i, k, row0 | count << 16, perm offset)
     const int i = wk.x, k = wk.y;
     const int row0 = wk.z & 0xffff, count = wk.z >> 16;
@@ -625,12 +632,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
     const double* S = a.S_cache + a.sub_Sbase[i] + (int64_t)k * R * R;
     const int64_t dptr = a.sub_dof_ptr[i];
     const int tid = threadIdx.x;
-    if (tid < 64) rowoff[tid] = tid < count ? (int64_t)perm[wk.w + tid] * SR + dptr : -1;
+    if (tid < 64) {
+        const int64_t l = tid < count ? (int64_t)perm[wk.w + tid] : -1;
+        rowoff[tid] = l >= 0 ? l * SR + dptr : -1;
+        xoff[tid] = l >= 0 ? l * a.M : -1;
+    }
+    const int64_t* dofs = a.sub_dofs + dptr;   // global mortar index of each local DOF of i
     const int lane = tid & 63, wave = tid >> 6;
     const int cb = (wave >> 1) * 32, rb = (wave & 1) * 32;   // realizations x S-rows quadrant
     const int li = lane & 15, lk = lane >> 4;
     dbl4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
+    // every coefficient load of a thread is for local DOF k0 + (tid % KC); its
+    // global index is fetched one chunk ahead
+    const int jt = tid % KC;
+    int64_t gnext = jt < R ? dofs[jt] : 0;
     for (int k0 = 0; k0 < R; k0 += KC) {
+        const int64_t gj = gnext;
+        if (k0 + KC + jt < R) gnext = dofs[k0 + KC + jt];
         __syncthreads();
         // KC / 4 independent loads per thread for each operand
         constexpr int NL = KC * 64 / kThreads;
@@ -643,16 +661,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
         }
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
-            const int idx = tid + q * kThreads;
-            const int c = idx / KC, j = idx % KC;
-            const int64_t ro = rowoff[c];
-            xv[q] = (ro >= 0 && k0 + j < R) ? xloc[ro + k0 + j] : 0.0;
+            const int c = (tid + q * kThreads) / KC;
+            const int64_t xo = xoff[c];
+            xv[q] = (xo >= 0 && k0 + jt < R) ? x[xo + gj] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             const int idx = tid + q * kThreads;
             St[idx] = sv[q];
-            Xs[(idx % KC) * 65 + idx / KC] = xv[q];
+            Xs[jt * 65 + idx / KC] = xv[q];
         }
         __syncthreads();
         // transposed product Y^T = X^T S^T: tile rows are realizations, columns
@@ -685,34 +702,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
 }
 
 hipError_t launch_cg_apply_mfma(const CgArgs& a, const double* x, double* Y, int64_t SR, const int4* work, int nwork,
-                                const int* perm, int max_R, hipStream_t stream) {
+                                const int* perm, int max_R, hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
     if (nwork <= 0) return hipSuccess;
     (void)max_R;
-    hipLaunchKernelGGL(cg_apply_mfma_kernel, dim3(nwork), dim3(kThreads), 0, stream, a, x, Y, SR, work, perm);
+    if (t0 != nullptr)
+        hipExtLaunchKernelGGL(cg_apply_mfma_kernel, dim3(nwork), dim3(kThreads), 0, stream, t0, t1, 0, a, x, Y, SR,
+                              work, perm);
+    else
+        hipLaunchKernelGGL(cg_apply_mfma_kernel, dim3(nwork), dim3(kThreads), 0, stream, a, x, Y, SR, work, perm);
     return hipGetLastError();
 }
-
-// Scatter a global-layout vector to the subdomain-local layout (both copies
-// of every mortar DOF).
-__global__ void scatter_local_kernel(const double* __restrict__ x, int64_t SR, const int* __restrict__ pos, int M,
-                                     int64_t n, double* __restrict__ xloc) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n * M) return;
-    const int64_t l = q / M;
-    const int m = (int)(q - l * M);
-    const double v = x[q];
-    xloc[l * SR + pos[2 * m]] = v;
-    xloc[l * SR + pos[2 * m + 1]] = v;
-}
-
-hipError_t launch_scatter_local(const double* x, int64_t SR, const int* pos, int M, int64_t n, double* xloc,
-                                hipStream_t stream) {
-    const int64_t tot = n * M;
-    hipLaunchKernelGGL(scatter_local_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream, x, SR, pos, M,
-                       n, xloc);
-    return hipGetLastError();
-}
-
 
 // S x for the realizations of the batch into the global layout (used by the
 // moments for the FETI coefficients): y_m = Y[pos1(m)] + Y[pos2(m)].
@@ -753,7 +752,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
     if (!a.active[l]) return;
     const int M = a.M, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double* r = a.r + l * M;
-    double* pl = a.p + l * SR;   // search direction in the subdomain-local layout
+    double* pg = a.p + l * M;   // search direction (global layout)
     double* lam = a.lam + l * M;
     const double* Yl = Y + l * SR;
     // A p, both subdomain contributions in a fixed order; p^T A p from the
@@ -769,7 +768,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
             const int p0 = pos[2 * m], p1 = pos[2 * m + 1];
             const double v = Yl[p0] + Yl[p1];
             aps[m] = v;
-            pv[q] = pl[p0];
+            pv[q] = pg[m];
             rv[q] = r[m];
             part += pv[q] * v;
         }
@@ -849,33 +848,36 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
     for (int q = 0; q < kMaxQ; ++q) {
         const int m = tid + q * kThreads;
         if (m < M) {
-            const double v = rv[q] + beta * pv[q];
-            pl[pos[2 * m]] = v;
-            pl[pos[2 * m + 1]] = v;
+            pg[m] = rv[q] + beta * pv[q];
         }
     }
     if (tid == 0) a.rr[l] = rrn;
 }
 
 template <int Q>
-static hipError_t launch_update2_q(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream) {
+static hipError_t launch_update2_q(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream,
+                                   hipEvent_t t0, hipEvent_t t1) {
     auto kern = cg_update2_kernel<Q, (Q <= 3 ? 8 : Q == 4 ? 7 : Q == 5 ? 6 : Q == 6 ? 5 : 4)>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, Y, SR, pos);
+    if (t0 != nullptr)
+        hipExtLaunchKernelGGL(kern, dim3((unsigned)a.n), dim3(kThreads), 0, stream, t0, t1, 0, a, Y, SR, pos);
+    else
+        hipLaunchKernelGGL(kern, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a, Y, SR, pos);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream) {
+hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream,
+                             hipEvent_t t0, hipEvent_t t1) {
     if (a.n <= 0) return hipSuccess;
     switch ((a.M + kThreads - 1) / kThreads) {
         case 0:
-        case 1: return launch_update2_q<1>(a, Y, SR, pos, stream);
-        case 2: return launch_update2_q<2>(a, Y, SR, pos, stream);
-        case 3: return launch_update2_q<3>(a, Y, SR, pos, stream);
-        case 4: return launch_update2_q<4>(a, Y, SR, pos, stream);
-        case 5: return launch_update2_q<5>(a, Y, SR, pos, stream);
-        case 6: return launch_update2_q<6>(a, Y, SR, pos, stream);
+        case 1: return launch_update2_q<1>(a, Y, SR, pos, stream, t0, t1);
+        case 2: return launch_update2_q<2>(a, Y, SR, pos, stream, t0, t1);
+        case 3: return launch_update2_q<3>(a, Y, SR, pos, stream, t0, t1);
+        case 4: return launch_update2_q<4>(a, Y, SR, pos, stream, t0, t1);
+        case 5: return launch_update2_q<5>(a, Y, SR, pos, stream, t0, t1);
+        case 6: return launch_update2_q<6>(a, Y, SR, pos, stream, t0, t1);
         case 7:
-        case 8: return launch_update2_q<8>(a, Y, SR, pos, stream);
+        case 8: return launch_update2_q<8>(a, Y, SR, pos, stream, t0, t1);
         default: return hipErrorInvalidValue;
     }
 }

@@ -115,7 +115,6 @@ struct CgArgs {
     double* lam;
     double* r;
     double* p;
-    double* Ap;
     double* rr;
     double* r0;
     int32_t* iters;
@@ -133,12 +132,14 @@ struct CgArgs {
 hipError_t launch_validate_index(const int64_t* gidx, int64_t n, int64_t nreal, int32_t* bad, hipStream_t stream);
 hipError_t launch_cg_init(const CgArgs& a, hipStream_t stream);
 hipError_t launch_cg_apply_mfma(const CgArgs& a, const double* x, double* Y, int64_t SR, const int4* work, int nwork,
-                                const int* perm, int max_R, hipStream_t stream);
-hipError_t launch_scatter_local(const double* x, int64_t SR, const int* pos, int M, int64_t n, double* xloc,
-                                hipStream_t stream);
+                                const int* perm, int max_R, hipStream_t stream, hipEvent_t t0 = nullptr,
+                                hipEvent_t t1 = nullptr);
 hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int M, int64_t n, double* y,
                                 hipStream_t stream);
-hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream);
+// t0/t1, when given, receive the start and end time stamps of the kernel's own
+// dispatch (hipExtLaunchKernel), so their interval excludes launch gaps.
+hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream,
+                             hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_count_active(const int32_t* active, int64_t n, int32_t* count, hipStream_t stream);
 hipError_t launch_cg_finish(const CgArgs& a, double* lam_out, int32_t* iters_out, double* relres_out,
                             int32_t* status_out, hipStream_t stream);

@@ -52,7 +52,8 @@ class Request:
 
 def footprint_bytes(sizes, batch):
     """Resident device bytes of one engine: basis cache, fine responses and the
-    CG state of one batch (r, lambda, p and the product in the local layout)."""
+    CG state of one batch (r, p, S lambda and lambda itself, M each, and the
+    product in the subdomain-local layout, 2 M)."""
     M = sizes["M"]
     per_real = 8 * (6 * M + 64)
     return sizes["basis_bytes"] + sizes["response_bytes"] + batch * per_real
