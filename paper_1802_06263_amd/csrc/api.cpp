@@ -772,13 +772,12 @@ int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, hipSt
 }
 
 // Realizations per CG chunk: the chunk's vectors (lambda, r, p and the
-// subdomain-local operator results) are kept within ~96 MB so that they stay
-// resident in the 256 MB Infinity Cache across iterations.
+// subdomain-local operator results) are kept within ~200 MB so that they stay
+// resident in the 256 MB last-level cache between the product and the
+// update; the chunks are then made equal.
 int64_t chunk_size(sdmm_ctx* ctx, int64_t n) {
     if (ctx->opt_chunk > 0) return std::min<int64_t>(n, ctx->opt_chunk);
     const int64_t per = (3 * (int64_t)ctx->P.M + ctx->SR) * 8 + 64;
-    // the chunk's CG vectors stay within ~200 MB, resident in the 256 MB
-    // last-level cache between the product and the update
     int64_t c = std::max<int64_t>(256, (int64_t)(200.0 * 1024 * 1024) / per);
     const int64_t nch = (n + c - 1) / c;
     return (n + nch - 1) / nch;
