@@ -221,8 +221,10 @@ int sdmm_get_moments(sdmm_ctx* ctx, int field, double* mean, double* var);
 int sdmm_reset_moments(sdmm_ctx* ctx);
 
 /* Tuning knobs of the batched CG (used by the autotuner):
- *   SDMM_OPT_CG_CHUNK  realizations per internal CG chunk (0 = sized so the
- *                      chunk's vectors fit a ~96 MB cache budget)
+ *   SDMM_OPT_CG_CHUNK  realizations in flight in the CG (slots; a finished
+ *                      realization's slot is refilled from the batch) and
+ *                      per moment pass (0 = sized so their vectors fit a
+ *                      ~200 MB cache budget)
  *   SDMM_OPT_CG_CHECK  iterations between host convergence checks (1..1024)
  *   SDMM_OPT_CG_GRAPH  1 = replay the iteration group as a captured HIP graph
  *   SDMM_OPT_KERNEL_TIMING 1 = time one iteration of every fourth check group
@@ -237,9 +239,9 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
 int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value);
 /* Autotuner of the batched CG: runs the first min(n, 16384) realizations of
  * gidx (device int64, n) through the whole CG (rtol, max_iter as in
- * sdmm_solve_interface) once per candidate chunk size (the sample split into
- * 1..4 equal chunks, and the default sized for a ~200 MB cache budget) and
- * keeps the fastest as SDMM_OPT_CG_CHUNK; *chunk_out (host, may be NULL)
+ * sdmm_solve_interface) once per candidate slot count (all of the sample,
+ * 1024 .. 8192 in steps of 512 below the sample size, and the default sized
+ * for a ~200 MB cache budget) and keeps the fastest as SDMM_OPT_CG_CHUNK; *chunk_out (host, may be NULL)
  * receives it.  Needs a built basis; results of later solves do not depend
  * on the choice.  Counters are left as they were.  Runs on `stream`. */
 int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,

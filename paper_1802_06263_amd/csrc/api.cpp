@@ -79,6 +79,7 @@ struct sdmm_ctx {
     DevBuf d_mom;  // p1 p2 u1 u2 for moments output
     DevBuf d_flag; // index validation flag
     // CG workspace
+    DevBuf w_slot_q, w_init;   // CG slot -> batch position; slots to start
     DevBuf w_r, w_p, w_rr, w_r0, w_iters, w_relres, w_status, w_active, w_any, w_alpha, w_Slam;
     int64_t w_cap = 0;
     // realization groups of the current chunk (grouped operator)
@@ -697,9 +698,9 @@ int fetch_gidx(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
     return SDMM_OK;
 }
 
-// subset: positions (into the fetched batch) of the realizations to include;
-// null means all n.
-int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, hipStream_t st) {
+// subset: positions of the realizations to include (null means all n);
+// hg: host global index of every position.
+int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, const int64_t* hg, hipStream_t st) {
     const Problem& P = ctx->P;
     std::vector<int> all;
     if (!subset) {
@@ -721,12 +722,12 @@ int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, hipSt
         rbase[r] = (int64_t)ctx->h_perm.size();
         const int L = P.nlocal[r];
         goff[r].assign(L + 1, 0);
-        for (int64_t q = 0; q < n; ++q) goff[r][P.g2l[(size_t)ctx->h_gidx[sel[q]] * nr + r] + 1]++;
+        for (int64_t q = 0; q < n; ++q) goff[r][P.g2l[(size_t)hg[sel[q]] * nr + r] + 1]++;
         for (int k = 0; k < L; ++k) goff[r][k + 1] += goff[r][k];
         std::vector<int64_t> fill(goff[r].begin(), goff[r].end() - 1);
         ctx->h_perm.resize(ctx->h_perm.size() + n);
         for (int64_t q = 0; q < n; ++q) {
-            const int k = P.g2l[(size_t)ctx->h_gidx[sel[q]] * nr + r];
+            const int k = P.g2l[(size_t)hg[sel[q]] * nr + r];
             ctx->h_perm[rbase[r] + fill[k]++] = sel[q];
         }
     }
@@ -771,16 +772,15 @@ int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, hipSt
     return SDMM_OK;
 }
 
-// Realizations per CG chunk: the chunk's vectors (lambda, r, p and the
-// subdomain-local operator results) are kept within ~200 MB so that they stay
-// resident in the 256 MB last-level cache between the product and the
-// update; the chunks are then made equal.
+// Realizations in flight (CG slots, and the chunk of the moment passes): their
+// vectors (lambda, r, p and the subdomain-local operator results) are kept
+// within ~200 MB so that they stay resident in the 256 MB last-level cache
+// between the product and the update.
 int64_t chunk_size(sdmm_ctx* ctx, int64_t n) {
     if (ctx->opt_chunk > 0) return std::min<int64_t>(n, ctx->opt_chunk);
     const int64_t per = (3 * (int64_t)ctx->P.M + ctx->SR) * 8 + 64;
-    int64_t c = std::max<int64_t>(256, (int64_t)(200.0 * 1024 * 1024) / per);
-    const int64_t nch = (n + c - 1) / c;
-    return (n + nch - 1) / nch;
+    const int64_t c = std::max<int64_t>(256, (int64_t)(200.0 * 1024 * 1024) / per);
+    return std::min(n, c);
 }
 
 int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
@@ -799,6 +799,8 @@ int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
     if ((rc = alloc(ctx, ctx->w_any, 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_alpha, n * std::max(1, ctx->P.n_kernel) * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_Y, (size_t)n * ctx->SR * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_slot_q, n * 4))) return rc;
+    if ((rc = alloc(ctx, ctx->w_init, n * 4))) return rc;
     ctx->w_cap = n;
     return SDMM_OK;
 }
@@ -1106,29 +1108,44 @@ int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value) {
 
 namespace {
 
-// One chunk of realizations through CG (all on stream st).
-int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, double* lambda,
-                int32_t* iters, double* relres, int32_t* status, hipStream_t st, int64_t& tot_it, bool& bad,
-                bool& brk) {
+// The batch through CG with S slots (all on stream st).  Slots are filled in
+// batch order; when at least a sixteenth of them hold finished realizations and
+// some are still pending, the finished ones are retired (their iterations and
+// status counted, their outputs already written by the kernels) and pending
+// ones start in their place, so the operator keeps about S realizations in
+// flight instead of draining once per chunk.  Once nothing is pending, the
+// operator drops finished realizations when they are a quarter of its work.
+// A realization's arithmetic does not depend on its slot or its neighbours,
+// so results do not depend on S.
+int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double rtol, int32_t max_iter,
+                double* lambda, int32_t* iters, double* relres, int32_t* status, hipStream_t st, int64_t& tot_it,
+                bool& bad, bool& brk) {
     int rc;
+    S = std::max<int64_t>(1, std::min(S, n));
     if ((rc = fetch_gidx(ctx, gidx, n, st))) return rc;
-    if ((rc = build_groups(ctx, n, nullptr, st))) return rc;
-    int64_t in_work = n;   // realizations covered by the operator work list
-    CgArgs a = cg_args(ctx, n, gidx, lambda);
+    CgArgs a = cg_args(ctx, S, gidx, lambda);
     a.rtol = rtol;
     a.max_iter = max_iter;
+    a.slot_q = ctx->w_slot_q.as<int>();
+    a.init_slots = ctx->w_init.as<int>();
+    a.iters_out = iters;
+    a.relres_out = relres;
+    a.status_out = status;
     double* Y = ctx->w_Y.as<double>();
     const int* pos = ctx->d_pos.as<int>();
-    HIPCHK(launch_cg_init(a, st));   // r_0, lambda_0 = 0 and p_0 = r_0
+    std::vector<int> slot_q(S, -1), init, sel;
+    std::vector<int64_t> slot_g(S, 0);   // global index of each slot's realization
+    std::vector<int32_t> act(S), itv(S), stv(S);
+    int64_t next = 0;                    // next batch position to start
+    int64_t in_work = 0;                 // slots covered by the operator work list
     const int group = ctx->opt_check;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     // Kernel timing samples the second iteration of one check group in
     // kTimeEvery (the other groups replay the captured graph): the
     // active realizations are counted just before it (into the second int of
-    // any_active), then events bracket its product and its update.  Earlier
-    // iterations keep the queue ahead of the device, so the events time the
-    // kernels and not host launch latency.
+    // any_active), then the product and the update are launched with events
+    // that take the time stamps of their own dispatch packets.
     const bool ktime = ctx->opt_ktime != 0;
     constexpr int kTimeEvery = 4;
     int ngroup = 0;
@@ -1145,8 +1162,7 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
         hipError_t e = hipSuccess;
         for (int q = 0; q < group && e == hipSuccess; ++q) {
             const bool timed = timed_group && q == tq;
-            if (timed && (e = launch_count_active(a.active, n, tcount, s)) != hipSuccess) break;
-            // timed launches stamp the events from their own dispatch packets
+            if (timed && (e = launch_count_active(a.active, S, tcount, s)) != hipSuccess) break;
             e = launch_cg_apply_mfma(a, a.p, Y, ctx->SR, ctx->d_work.as<int4>(), ctx->nwork,
                                      ctx->d_perm.as<int>(), ctx->max_R, s, timed ? ctx->kev[0] : nullptr,
                                      timed ? ctx->kev[1] : nullptr);
@@ -1169,11 +1185,14 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
         ctx->counters.cg_timed_columns += in_work;
         return SDMM_OK;
     };
-    auto capture = [&]() -> int {
+    auto release_graph = [&]() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
+    };
+    auto capture = [&]() -> int {
+        release_graph();
         if (!ctx->opt_graph) return SDMM_OK;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         hipError_t e = body(st, false);
@@ -1191,54 +1210,85 @@ int solve_chunk(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int3
         }
         return SDMM_OK;
     };
-    if ((rc = capture())) return rc;
-    int it = 0;
-    int32_t count = (int32_t)n;
-    std::vector<int32_t> act;
-    while (it < max_iter) {
+    // pending realizations into the free slots, and their CG started
+    auto admit = [&]() -> int {
+        init.clear();
+        for (int64_t l = 0; l < S && next < n; ++l) {
+            if (slot_q[l] >= 0) continue;
+            slot_q[l] = (int)next;
+            slot_g[l] = ctx->h_gidx[next];
+            ++next;
+            init.push_back((int)l);
+        }
+        if (init.empty()) return SDMM_OK;
+        HIPCHK(hipMemcpyAsync(ctx->w_slot_q.p, slot_q.data(), S * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ctx->w_init.p, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_cg_init(a, (int64_t)init.size(), st));
+        HIPCHK(hipStreamSynchronize(st));   // the host vectors change before the next admission
+        return SDMM_OK;
+    };
+    // finished realizations leave their slots (all occupied slots when `all`)
+    auto retire = [&](bool all) -> int {
+        HIPCHK(hipMemcpyAsync(act.data(), a.active, S * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(itv.data(), a.iters, S * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(stv.data(), a.status, S * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int64_t l = 0; l < S; ++l) {
+            if (slot_q[l] < 0 || (act[l] && !all)) continue;
+            tot_it += itv[l];
+            bad |= stv[l] != SDMM_CG_CONVERGED;
+            brk |= stv[l] == SDMM_CG_BREAKDOWN;
+            slot_q[l] = -1;
+        }
+        return SDMM_OK;
+    };
+    // operator work over the occupied slots, and a new graph for it
+    auto regroup = [&]() -> int {
+        sel.clear();
+        for (int64_t l = 0; l < S; ++l)
+            if (slot_q[l] >= 0) sel.push_back((int)l);
+        int r2;
+        if ((r2 = build_groups(ctx, S, &sel, slot_g.data(), st))) return r2;
+        in_work = (int64_t)sel.size();
+        return capture();
+    };
+    if ((rc = admit()) || (rc = regroup())) {
+        release_graph();
+        return rc;
+    }
+    const int64_t refill = std::max<int64_t>(1, S / 16);
+    // every realization stops within max_iter iterations of its start
+    const int64_t max_groups = (n / refill + 2) * ((int64_t)max_iter / group + 2);
+    int32_t count = (int32_t)S;
+    for (int64_t g = 0;; ++g) {
+        if (g > max_groups) {
+            release_graph();
+            return fail(ctx, SDMM_EDEVICE, "the CG driver did not finish");
+        }
         // one check group in kTimeEvery is timed (eager, with events); the
         // others replay the captured graph when there is one
         const bool timed_group = ktime && (ngroup++ % kTimeEvery == 0);
-        if (exec && !timed_group) {
-            HIPCHK(hipGraphLaunch(exec, st));
-        } else {
-            HIPCHK(body(st, timed_group));
+        hipError_t e = (exec && !timed_group) ? hipGraphLaunch(exec, st) : body(st, timed_group);
+        if (e == hipSuccess) e = launch_count_active(a.active, S, a.any_active, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&count, a.any_active, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && timed_group) e = hipMemcpyAsync(&tactive, tcount, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            release_graph();
+            return fail(ctx, SDMM_EDEVICE, hipGetErrorString(e));
         }
-        it += group;
         ctx->counters.cg_launches += group;
-        HIPCHK(launch_count_active(a.active, n, a.any_active, st));
-        HIPCHK(hipMemcpyAsync(&count, a.any_active, 4, hipMemcpyDeviceToHost, st));
-        if (timed_group) HIPCHK(hipMemcpyAsync(&tactive, tcount, 4, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (timed_group && (rc = add_times())) return rc;
-        if (count == 0) break;
-        // drop converged realizations from the operator once they are a
-        // quarter of its work (their results are final)
-        if (count < 0.75 * in_work) {
-            act.resize(n);
-            HIPCHK(hipMemcpyAsync(act.data(), a.active, n * 4, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            std::vector<int> sel;
-            for (int64_t l = 0; l < n; ++l)
-                if (act[l]) sel.push_back((int)l);
-            if ((rc = build_groups(ctx, n, &sel, st))) return rc;
-            in_work = (int64_t)sel.size();
-            if ((rc = capture())) return rc;
+        if (timed_group && (rc = add_times())) break;
+        if (count == 0 && next >= n) break;
+        if (next < n && S - count >= refill) {
+            if ((rc = retire(false)) || (rc = admit()) || (rc = regroup())) break;
+        } else if (next >= n && count < 0.75 * in_work) {
+            if ((rc = retire(false)) || (rc = regroup())) break;
         }
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    HIPCHK(launch_cg_finish(a, lambda, iters, relres, status, st));
-    std::vector<int32_t> stv(n), itv(n);
-    HIPCHK(hipMemcpyAsync(stv.data(), a.status, n * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(itv.data(), a.iters, n * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int64_t l = 0; l < n; ++l) {
-        tot_it += itv[l];
-        bad |= stv[l] != SDMM_CG_CONVERGED;
-        brk |= stv[l] == SDMM_CG_BREAKDOWN;
-    }
-    return SDMM_OK;
+    release_graph();
+    if (rc) return rc;
+    return retire(true);
 }
 
 hipStream_t work_stream(sdmm_ctx* ctx, hipStream_t user) {
@@ -1272,13 +1322,8 @@ int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double r
     HIPCHK(hipEventRecord(ctx->ev[3], st));
     int64_t tot = 0;
     bool bad = false, brk = false;
-    const int M = ctx->P.M;
-    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
-        const int64_t cn = std::min(chunk, n - c0);
-        rc = solve_chunk(ctx, cn, gidx + c0, rtol, max_iter, lambda + c0 * M, iters ? iters + c0 : nullptr,
-                         relres ? relres + c0 : nullptr, status ? status + c0 : nullptr, st, tot, bad, brk);
-        if (rc) return rc;
-    }
+    if ((rc = solve_batch(ctx, n, chunk, gidx, rtol, max_iter, lambda, iters, relres, status, st, tot, bad, brk)))
+        return rc;
     HIPCHK(hipEventRecord(ctx->ev[4], st));
     HIPCHK(hipStreamWaitEvent(user, ctx->ev[4], 0));
     HIPCHK(hipStreamSynchronize(st));
@@ -1305,16 +1350,15 @@ int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, in
     HIPCHK(hipStreamWaitEvent(st, ctx->ev[5], 0));
     int rc;
     if ((rc = check_indices(ctx, gidx, n, st))) return rc;
-    // the sample: the first realizations of the batch; candidates split it
-    // into 1..4 equal chunks, plus the cache-budget default
+    // the sample: the first realizations of the batch; candidate slot counts:
+    // all of it, 1024 .. 8192 in steps of 512 below its size, and the
+    // cache-budget default
     const int64_t ns = std::min<int64_t>(n, 16384);
     const int64_t saved = ctx->opt_chunk;
     ctx->opt_chunk = 0;
-    std::vector<int64_t> cand;
-    for (int k = 1; k <= 4; ++k) {
-        const int64_t c = (ns + k - 1) / k;
-        if (c >= 256 || k == 1) cand.push_back(c);
-    }
+    std::vector<int64_t> cand{ns};
+    for (int64_t c = 1024; c <= 8192; c += 512)
+        if (c < ns) cand.push_back(c);
     cand.push_back(chunk_size(ctx, ns));
     std::sort(cand.begin(), cand.end());
     cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
@@ -1331,15 +1375,14 @@ int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, in
     double best = 1e300;
     int64_t best_c = cand.back();
     for (int64_t c : cand) {
-        // the whole sample through CG with chunks of c: per-chunk tails and
+        // the whole sample through CG with c slots: the final drain and
         // cache residency are both in the measurement
         int64_t tot = 0;
         bool bad = false, brk = false;
         HIPCHK(hipStreamSynchronize(st));
         const auto t0 = std::chrono::steady_clock::now();
-        for (int64_t c0 = 0; c0 < ns && !rc; c0 += c)
-            rc = solve_chunk(ctx, std::min(c, ns - c0), gidx + c0, rtol, max_iter, lam.as<double>() + c0 * ctx->P.M,
-                             nullptr, nullptr, nullptr, st, tot, bad, brk);
+        rc = solve_batch(ctx, ns, c, gidx, rtol, max_iter, lam.as<double>(), nullptr, nullptr, nullptr, st, tot, bad,
+                         brk);
         if (rc) {
             ctx->opt_chunk = saved;
             ctx->counters = saved_counters;
@@ -1379,7 +1422,7 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const
         const int64_t* g = gidx + c0;
         const double* lam = lambda + c0 * M;
         if ((rc = fetch_gidx(ctx, g, cn, st))) return rc;
-        if ((rc = build_groups(ctx, cn, nullptr, st))) return rc;
+        if ((rc = build_groups(ctx, cn, nullptr, ctx->h_gidx.data(), st))) return rc;
         CgArgs a = cg_args(ctx, cn, g, const_cast<double*>(lam));
         if (ctx->P.n_kernel > 0) {
             HIPCHK(launch_cg_apply_mfma(a, lam, ctx->w_Y.as<double>(), ctx->SR,

@@ -575,12 +575,15 @@ __device__ void feti_project_row(const CgArgs& a, double* v, double* red, double
     __syncthreads();
 }
 
+// Starts the CG of one slot: r_0 = P g (the same for every realization,
+// R14), lambda_0 = 0, p_0 = r_0.  A realization with r_0 = 0 is final at once.
 __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
     __shared__ double red[kThreads / 64];
     __shared__ double coef[32];
-    const int64_t l = blockIdx.x;
+    const int64_t l = a.init_slots[blockIdx.x];
+    const int64_t q = a.slot_q[l];
     double* r = a.r + l * a.M;
-    double* lam = a.lam + l * a.M;
+    double* lam = a.lam + q * a.M;
     for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
         r[m] = a.g[m];
         lam[m] = 0.0;
@@ -601,6 +604,11 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
         a.relres[l] = rr > 0 ? 1.0 : 0.0;
         a.status[l] = rr > 0 ? SDMM_CG_MAXITER : SDMM_CG_CONVERGED;
         a.active[l] = rr > 0 ? 1 : 0;
+        if (!(rr > 0)) {
+            if (a.iters_out) a.iters_out[q] = 0;
+            if (a.relres_out) a.relres_out[q] = 0.0;
+            if (a.status_out) a.status_out[q] = SDMM_CG_CONVERGED;
+        }
     }
 }
 
@@ -753,7 +761,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
     const int M = a.M, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double* r = a.r + l * M;
     double* pg = a.p + l * M;   // search direction (global layout)
-    double* lam = a.lam + l * M;
+    const int64_t qb = a.slot_q[l];   // the slot's realization in the batch
+    double* lam = a.lam + qb * M;
     const double* Yl = Y + l * SR;
     // A p, both subdomain contributions in a fixed order; p^T A p from the
     // unprojected product (p stays in the range of the FETI projection P,
@@ -806,9 +815,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
     const int iter = a.iters[l];
     if (!(pAp > 0.0) || !isfinite(pAp)) {
         if (tid == 0) {
+            const double rel = a.r0[l] > 0 ? sqrt(rr) / a.r0[l] : 0.0;
             a.status[l] = SDMM_CG_BREAKDOWN;
             a.active[l] = 0;
-            a.relres[l] = a.r0[l] > 0 ? sqrt(rr) / a.r0[l] : 0.0;
+            a.relres[l] = rel;
+            if (a.iters_out) a.iters_out[qb] = iter;
+            if (a.relres_out) a.relres_out[qb] = rel;
+            if (a.status_out) a.status_out[qb] = SDMM_CG_BREAKDOWN;
         }
         return;
     }
@@ -838,8 +851,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
     }
     if (conv || last) {
         if (tid == 0) {
-            a.status[l] = conv ? SDMM_CG_CONVERGED : SDMM_CG_MAXITER;
+            const int st = conv ? SDMM_CG_CONVERGED : SDMM_CG_MAXITER;
+            a.status[l] = st;
             a.active[l] = 0;
+            if (a.iters_out) a.iters_out[qb] = iter + 1;
+            if (a.relres_out) a.relres_out[qb] = rel;
+            if (a.status_out) a.status_out[qb] = st;
         }
         return;
     }
@@ -901,14 +918,6 @@ hipError_t launch_count_active(const int32_t* active, int64_t n, int32_t* count,
     return hipGetLastError();
 }
 
-__global__ void cg_finish_kernel(CgArgs a, int32_t* iters_out, double* relres_out, int32_t* status_out) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= a.n) return;
-    if (iters_out) iters_out[l] = a.iters[l];
-    if (relres_out) relres_out[l] = a.relres[l];
-    if (status_out) status_out[l] = a.status[l];
-}
-
 __global__ void validate_index_kernel(const int64_t* gidx, int64_t n, int64_t nreal, int32_t* bad) {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l < n && (gidx[l] < 0 || gidx[l] >= nreal)) *bad = 1;
@@ -920,17 +929,12 @@ hipError_t launch_validate_index(const int64_t* gidx, int64_t n, int64_t nreal, 
     return hipGetLastError();
 }
 
-hipError_t launch_cg_init(const CgArgs& a, hipStream_t stream) {
-    hipLaunchKernelGGL(cg_init_kernel, dim3((unsigned)a.n), dim3(kThreads), 0, stream, a);
+hipError_t launch_cg_init(const CgArgs& a, int64_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cg_init_kernel, dim3((unsigned)count), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_finish(const CgArgs& a, double* /*lam_out*/, int32_t* iters_out, double* relres_out,
-                            int32_t* status_out, hipStream_t stream) {
-    hipLaunchKernelGGL(cg_finish_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, stream, a, iters_out,
-                       relres_out, status_out);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // Moments.  Per realization the fine fields are linear in the local mortar

@@ -127,10 +127,19 @@ struct CgArgs {
     int nGrow;
     double rtol;
     int max_iter;
+    // slots: the CG state arrays (r, p, rr, r0, iters, relres, status, active)
+    // have one row per slot; slot l holds batch realization slot_q[l], whose
+    // lambda row and outputs are at that batch position
+    const int* slot_q;
+    const int* init_slots;   // slots cg_init starts
+    int32_t* iters_out;      // batch outputs, written when a realization stops (may be null)
+    double* relres_out;
+    int32_t* status_out;
 };
 
 hipError_t launch_validate_index(const int64_t* gidx, int64_t n, int64_t nreal, int32_t* bad, hipStream_t stream);
-hipError_t launch_cg_init(const CgArgs& a, hipStream_t stream);
+// starts the CG of the `count` slots listed in a.init_slots
+hipError_t launch_cg_init(const CgArgs& a, int64_t count, hipStream_t stream);
 hipError_t launch_cg_apply_mfma(const CgArgs& a, const double* x, double* Y, int64_t SR, const int4* work, int nwork,
                                 const int* perm, int max_R, hipStream_t stream, hipEvent_t t0 = nullptr,
                                 hipEvent_t t1 = nullptr);
@@ -141,8 +150,6 @@ hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int
 hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream,
                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_count_active(const int32_t* active, int64_t n, int32_t* count, hipStream_t stream);
-hipError_t launch_cg_finish(const CgArgs& a, double* lam_out, int32_t* iters_out, double* relres_out,
-                            int32_t* status_out, hipStream_t stream);
 
 // Moments
 struct MomArgs {

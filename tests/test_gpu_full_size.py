@@ -166,10 +166,47 @@ def test_autotune_keeps_results():
     c0 = ctx.counters()
     chunk = ctx.autotune(g, rtol=1e-10)
     ns = min(n, 16384)
-    assert chunk >= 1 and (chunk in [(ns + k - 1) // k for k in range(1, 5)] or chunk <= ns)
+    assert 1 <= chunk <= ns
     c1 = ctx.counters()
     assert c1["cg_iterations"] == c0["cg_iterations"]
     _, lam1, it1, _, st1, _ = gpu_solve(ctx, np.arange(n), rtol=1e-10)
     assert np.array_equal(lam0.cpu().numpy(), lam1.cpu().numpy())
     assert np.array_equal(it0, it1) and np.array_equal(st0, st1)
+    ctx.close()
+
+
+CG_CONVERGED, CG_MAXITER = 0, 1   # status values of sdmm_solve_interface
+
+
+def test_cg_slot_refill_keeps_results():
+    """The CG keeps a fixed number of realizations in flight and starts a
+    pending realization in each finished one's slot.  Every output must be
+    bit-identical whatever the slot count, also for realizations that stop at
+    max_iter, and the iteration counter must add up the same."""
+    print("case: CG slot refill on cfg1", flush=True)
+    ctx = gpu_ctx(problem("cfg1"), "fp64")
+    n = ctx.sizes()["n_real"]
+    idx = np.arange(n)[::-1].copy()   # slots then hold non-consecutive global indices
+    ctx.set_option("cg_chunk", n)
+    c0 = ctx.counters()["cg_iterations"]
+    _, lam_r, it_r, rr_r, st_r, _ = gpu_solve(ctx, idx, rtol=1e-10)
+    tot_r = ctx.counters()["cg_iterations"] - c0
+    assert (st_r == CG_CONVERGED).all() and tot_r == int(it_r.sum())
+    for slots in (50, 3):
+        print("case: cfg1 with %d CG slots" % slots, flush=True)
+        ctx.set_option("cg_chunk", slots)
+        c0 = ctx.counters()["cg_iterations"]
+        _, lam, it, rr, st, _ = gpu_solve(ctx, idx, rtol=1e-10)
+        assert ctx.counters()["cg_iterations"] - c0 == tot_r
+        assert np.array_equal(lam.cpu().numpy(), lam_r.cpu().numpy())
+        assert np.array_equal(it, it_r) and np.array_equal(rr, rr_r) and np.array_equal(st, st_r)
+    print("case: cfg1 stopped at max_iter with 7 and 361 slots", flush=True)
+    out = []
+    for slots in (7, n):
+        ctx.set_option("cg_chunk", slots)
+        _, lam, it, rr, st, _ = gpu_solve(ctx, idx, rtol=1e-10, max_iter=40, allow_notconv=True)
+        out.append((lam.cpu().numpy(), it, rr, st))
+    assert (out[0][3] == CG_MAXITER).all() and (out[0][1] == 40).all()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
     ctx.close()
