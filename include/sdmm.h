@@ -225,7 +225,8 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
  *                      realization's slot is refilled from the batch) and
  *                      per moment pass (0 = sized so their vectors fit a
  *                      ~200 MB cache budget)
- *   SDMM_OPT_CG_CHECK  iterations between host convergence checks (1..1024)
+ *   SDMM_OPT_CG_CHECK  iterations between host convergence checks (1..1024,
+ *                      default 64)
  *   SDMM_OPT_CG_GRAPH  1 = replay the iteration group as a captured HIP graph
  *   SDMM_OPT_KERNEL_TIMING 1 = time one iteration of every fourth check group
  *                      with HIP events and sum the durations into the

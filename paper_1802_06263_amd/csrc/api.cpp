@@ -91,7 +91,7 @@ struct sdmm_ctx {
     int64_t SR = 0, part_total = 0;
     // tuning options (sdmm_set_option)
     int64_t opt_chunk = 0;   // realizations per CG chunk, 0 = from the cache budget
-    int opt_check = 16;      // iterations between convergence checks
+    int opt_check = 64;      // iterations between convergence checks
     int opt_graph = 1;       // capture the iteration group in a HIP graph
     int opt_ktime = 0;       // events around every CG kernel launch
     std::vector<hipEvent_t> kev;   // event pool of the kernel timing
