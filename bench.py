@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--single", action="store_true", help="time only --precision (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (scale reference for HBM counters)")
-    ap.add_argument("--cg-chunk", type=int, default=0, help="CG chunk size (0: autotune)")
+    ap.add_argument("--cg-chunk", type=int, default=0, help="realizations in flight in the CG (0: autotune)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
