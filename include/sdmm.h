@@ -228,6 +228,9 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
  *   SDMM_OPT_CG_CHECK  iterations between host convergence checks (1..1024,
  *                      default 64)
  *   SDMM_OPT_CG_GRAPH  1 = replay the iteration group as a captured HIP graph
+ *   SDMM_OPT_CG_LANES  2 (default) = split the slots into two lanes with their
+ *                      own streams, so that one lane's operator product
+ *                      overlaps the other's update on the device; 1 = one
  *   SDMM_OPT_KERNEL_TIMING 1 = time one iteration of every fourth check group
  *                      with HIP events and sum the durations into the
  *                      counters (those groups run eagerly, the others replay
@@ -237,6 +240,7 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
 #define SDMM_OPT_CG_CHECK 1
 #define SDMM_OPT_CG_GRAPH 2
 #define SDMM_OPT_KERNEL_TIMING 3
+#define SDMM_OPT_CG_LANES 4
 int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value);
 /* Autotuner of the batched CG: runs the first min(n, 16384) realizations of
  * gidx (device int64, n) through the whole CG (rtol, max_iter as in

@@ -33,6 +33,21 @@ struct DevBuf {
 
 }  // namespace
 
+// Realization groups of the grouped operator: the batch positions sorted by
+// local index per region (perm), the operator work items (work) and the
+// moment work items (awork, with their scratch offsets and first item per
+// (subdomain, local realization) pair).
+struct Groups {
+    DevBuf d_work, d_perm, d_awork, d_slot, d_item0;
+    std::vector<int4> h_work, h_awork;
+    std::vector<int> h_perm, h_item0;
+    std::vector<int64_t> h_slot;
+    int nwork = 0, nawork = 0;
+    int64_t part_total = 0;
+};
+
+constexpr int kMaxLanes = 2;   // CG lanes: halves of the slots on their own streams
+
 struct sdmm_ctx {
     int device = 0;
     bool host_only = false;  // device -1: problem setup and maps only
@@ -82,13 +97,12 @@ struct sdmm_ctx {
     DevBuf w_slot_q, w_init;   // CG slot -> batch position; slots to start
     DevBuf w_r, w_p, w_rr, w_r0, w_iters, w_relres, w_status, w_active, w_any, w_alpha, w_Slam;
     int64_t w_cap = 0;
-    // realization groups of the current chunk (grouped operator)
-    DevBuf d_work, d_perm, d_awork, d_slot, d_part, d_item0, d_pos, w_Y;
-    std::vector<int4> h_work, h_awork;
-    std::vector<int> h_perm, h_item0;
-    std::vector<int64_t> h_gidx, h_slot;
-    int nwork = 0, nawork = 0;
-    int64_t SR = 0, part_total = 0;
+    // realization groups (grouped operator), one set per CG lane; the moment
+    // passes use the first
+    Groups grp[kMaxLanes];
+    DevBuf d_part, d_pos, w_Y;
+    std::vector<int64_t> h_gidx;
+    int64_t SR = 0;
     // tuning options (sdmm_set_option)
     int64_t opt_chunk = 0;   // realizations per CG chunk, 0 = from the cache budget
     int opt_check = 64;      // iterations between convergence checks
@@ -96,6 +110,10 @@ struct sdmm_ctx {
     int opt_ktime = 0;       // events around every CG kernel launch
     std::vector<hipEvent_t> kev;   // event pool of the kernel timing
     hipStream_t cap_stream = nullptr;
+    hipStream_t lane_stream = nullptr;   // the second CG lane
+    hipEvent_t lane_ev[2] = {};          // fork / join of the second lane
+    int opt_lanes = 2;                   // CG lanes (1 or 2)
+    int32_t* h_count = nullptr;          // pinned: per lane the active count and the timed count
     sdmm_counters counters{};
     hipEvent_t ev[6] = {};
 };
@@ -700,7 +718,8 @@ int fetch_gidx(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
 
 // subset: positions of the realizations to include (null means all n);
 // hg: host global index of every position.
-int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, const int64_t* hg, hipStream_t st) {
+int build_groups(sdmm_ctx* ctx, Groups& G, int64_t n, const std::vector<int>* subset, const int64_t* hg,
+                 hipStream_t st) {
     const Problem& P = ctx->P;
     std::vector<int> all;
     if (!subset) {
@@ -710,30 +729,30 @@ int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, const
     }
     const std::vector<int>& sel = *subset;
     n = (int64_t)sel.size();
-    ctx->h_perm.clear();
-    ctx->h_work.clear();
-    ctx->h_awork.clear();
-    ctx->h_slot.clear();
-    ctx->h_item0.clear();
+    G.h_perm.clear();
+    G.h_work.clear();
+    G.h_awork.clear();
+    G.h_slot.clear();
+    G.h_item0.clear();
     const int nr = P.n_region;
     std::vector<int64_t> rbase(nr + 1);
     std::vector<std::vector<int64_t>> goff(nr);
     for (int r = 0; r < nr; ++r) {
-        rbase[r] = (int64_t)ctx->h_perm.size();
+        rbase[r] = (int64_t)G.h_perm.size();
         const int L = P.nlocal[r];
         goff[r].assign(L + 1, 0);
         for (int64_t q = 0; q < n; ++q) goff[r][P.g2l[(size_t)hg[sel[q]] * nr + r] + 1]++;
         for (int k = 0; k < L; ++k) goff[r][k + 1] += goff[r][k];
         std::vector<int64_t> fill(goff[r].begin(), goff[r].end() - 1);
-        ctx->h_perm.resize(ctx->h_perm.size() + n);
+        G.h_perm.resize(G.h_perm.size() + n);
         for (int64_t q = 0; q < n; ++q) {
             const int k = P.g2l[(size_t)hg[sel[q]] * nr + r];
-            ctx->h_perm[rbase[r] + fill[k]++] = sel[q];
+            G.h_perm[rbase[r] + fill[k]++] = sel[q];
         }
     }
-    rbase[nr] = (int64_t)ctx->h_perm.size();
-    for (int64_t q = 0; q < n; ++q) ctx->h_perm.push_back(sel[q]);  // Stokes: every realization
-    if ((int64_t)ctx->h_perm.size() > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
+    rbase[nr] = (int64_t)G.h_perm.size();
+    for (int64_t q = 0; q < n; ++q) G.h_perm.push_back(sel[q]);  // Stokes: every realization
+    if ((int64_t)G.h_perm.size() > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
     int64_t slot = 0;
     for (size_t pidx = 0; pidx < ctx->pair_sub.size(); ++pidx) {
         const int i = ctx->pair_sub[pidx], k = ctx->pair_k[pidx];
@@ -742,32 +761,32 @@ int build_groups(sdmm_ctx* ctx, int64_t n, const std::vector<int>* subset, const
         const int ext = R + ctx->sub_ker[i];
         const int64_t g0 = r >= 0 ? goff[r][k] : 0, g1 = r >= 0 ? goff[r][k + 1] : n;
         const int64_t base = r >= 0 ? rbase[r] : rbase[nr];
-        ctx->h_item0.push_back((int)ctx->h_awork.size());
+        G.h_item0.push_back((int)G.h_awork.size());
         for (int64_t c0 = g0; c0 < g1; c0 += 64) {
             const int cnt = (int)std::min<int64_t>(64, g1 - c0);
             for (int row0 = 0; row0 < R; row0 += 64)
-                ctx->h_work.push_back(make_int4(i, k, row0 | (cnt << 16), (int)(base + c0)));
-            ctx->h_awork.push_back(make_int4(i, k, cnt, (int)(base + c0)));
-            ctx->h_slot.push_back(slot);
+                G.h_work.push_back(make_int4(i, k, row0 | (cnt << 16), (int)(base + c0)));
+            G.h_awork.push_back(make_int4(i, k, cnt, (int)(base + c0)));
+            G.h_slot.push_back(slot);
             slot += (int64_t)ext + (int64_t)ext * ext;
         }
     }
-    ctx->h_item0.push_back((int)ctx->h_awork.size());
-    ctx->nwork = (int)ctx->h_work.size();
-    ctx->nawork = (int)ctx->h_awork.size();
-    ctx->part_total = slot;
+    G.h_item0.push_back((int)G.h_awork.size());
+    G.nwork = (int)G.h_work.size();
+    G.nawork = (int)G.h_awork.size();
+    G.part_total = slot;
     int rc;
     auto grow = [&](DevBuf& b, size_t bytes) { return b.bytes < bytes ? alloc(ctx, b, bytes) : SDMM_OK; };
-    if ((rc = grow(ctx->d_perm, ctx->h_perm.size() * 4))) return rc;
-    if ((rc = grow(ctx->d_work, ctx->h_work.size() * 16))) return rc;
-    if ((rc = grow(ctx->d_awork, ctx->h_awork.size() * 16))) return rc;
-    if ((rc = grow(ctx->d_slot, ctx->h_slot.size() * 8))) return rc;
-    if ((rc = grow(ctx->d_item0, ctx->h_item0.size() * 4))) return rc;
-    HIPCHK(hipMemcpyAsync(ctx->d_perm.p, ctx->h_perm.data(), ctx->h_perm.size() * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ctx->d_work.p, ctx->h_work.data(), ctx->h_work.size() * 16, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ctx->d_awork.p, ctx->h_awork.data(), ctx->h_awork.size() * 16, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ctx->d_slot.p, ctx->h_slot.data(), ctx->h_slot.size() * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ctx->d_item0.p, ctx->h_item0.data(), ctx->h_item0.size() * 4, hipMemcpyHostToDevice, st));
+    if ((rc = grow(G.d_perm, G.h_perm.size() * 4))) return rc;
+    if ((rc = grow(G.d_work, G.h_work.size() * 16))) return rc;
+    if ((rc = grow(G.d_awork, G.h_awork.size() * 16))) return rc;
+    if ((rc = grow(G.d_slot, G.h_slot.size() * 8))) return rc;
+    if ((rc = grow(G.d_item0, G.h_item0.size() * 4))) return rc;
+    HIPCHK(hipMemcpyAsync(G.d_perm.p, G.h_perm.data(), G.h_perm.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(G.d_work.p, G.h_work.data(), G.h_work.size() * 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(G.d_awork.p, G.h_awork.data(), G.h_awork.size() * 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(G.d_slot.p, G.h_slot.data(), G.h_slot.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(G.d_item0.p, G.h_item0.data(), G.h_item0.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));  // the host vectors are reused by the next chunk
     return SDMM_OK;
 }
@@ -796,7 +815,7 @@ int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
     if ((rc = alloc(ctx, ctx->w_relres, n * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_status, n * 4))) return rc;
     if ((rc = alloc(ctx, ctx->w_active, n * 4))) return rc;
-    if ((rc = alloc(ctx, ctx->w_any, 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_any, 8 * kMaxLanes))) return rc;   // per lane: active count, timed count
     if ((rc = alloc(ctx, ctx->w_alpha, n * std::max(1, ctx->P.n_kernel) * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_Y, (size_t)n * ctx->SR * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_slot_q, n * 4))) return rc;
@@ -886,6 +905,10 @@ int sdmm_destroy(sdmm_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->lane_stream) (void)hipStreamDestroy(ctx->lane_stream);
+    if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+    for (hipEvent_t e : ctx->lane_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->kev)
@@ -1101,6 +1124,10 @@ int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value) {
         case SDMM_OPT_KERNEL_TIMING:
             ctx->opt_ktime = value ? 1 : 0;
             return SDMM_OK;
+        case SDMM_OPT_CG_LANES:
+            if (value < 1 || value > kMaxLanes) return fail(ctx, SDMM_EINVAL, "cg_lanes must be 1 or 2");
+            ctx->opt_lanes = (int)value;
+            return SDMM_OK;
         default:
             return fail(ctx, SDMM_EINVAL, "unknown option");
     }
@@ -1108,49 +1135,104 @@ int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value) {
 
 namespace {
 
-// The batch through CG with S slots (all on stream st).  Slots are filled in
-// batch order; when at least a sixteenth of them hold finished realizations and
-// some are still pending, the finished ones are retired (their iterations and
+// The batch through CG with S slots.  Slots are filled in batch order; when
+// at least a sixteenth of a lane's slots hold finished realizations and some
+// are still pending, the finished ones are retired (their iterations and
 // status counted, their outputs already written by the kernels) and pending
 // ones start in their place, so the operator keeps about S realizations in
-// flight instead of draining once per chunk.  Once nothing is pending, the
-// operator drops finished realizations when they are a quarter of its work.
-// A realization's arithmetic does not depend on its slot or its neighbours,
-// so results do not depend on S.
+// flight instead of draining once per chunk.  Once nothing is pending, a
+// lane drops finished realizations from its operator when they are a quarter
+// of its work.  With opt_lanes = 2 (and at least 2 kMinLaneSlots slots) the
+// slots are split into two lanes with their own groups, graph and stream:
+// the lanes' iterations are independent, so one lane's product (FP64 MFMA)
+// overlaps the other's update (HBM) on the device.  A realization's
+// arithmetic does not depend on its slot, lane or neighbours, so results do
+// not depend on S or on the lanes.
+constexpr int64_t kMinLaneSlots = 64;
+
+struct Lane {
+    int id = 0;
+    int64_t base = 0, S = 0;              // slots base .. base + S - 1 of the workspace
+    hipStream_t s = nullptr;
+    Groups* G = nullptr;
+    CgArgs a{};
+    double* Y = nullptr;
+    std::vector<int> slot_q, init, sel;
+    std::vector<int64_t> slot_g;          // global index of each slot's realization
+    std::vector<int32_t> act, itv, stv;
+    int64_t in_work = 0;                  // slots covered by the operator work list
+    int64_t groups = 0;
+    bool timed = false, done = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
 int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double rtol, int32_t max_iter,
                 double* lambda, int32_t* iters, double* relres, int32_t* status, hipStream_t st, int64_t& tot_it,
                 bool& bad, bool& brk) {
     int rc;
     S = std::max<int64_t>(1, std::min(S, n));
     if ((rc = fetch_gidx(ctx, gidx, n, st))) return rc;
-    CgArgs a = cg_args(ctx, S, gidx, lambda);
-    a.rtol = rtol;
-    a.max_iter = max_iter;
-    a.slot_q = ctx->w_slot_q.as<int>();
-    a.init_slots = ctx->w_init.as<int>();
-    a.iters_out = iters;
-    a.relres_out = relres;
-    a.status_out = status;
-    double* Y = ctx->w_Y.as<double>();
-    const int* pos = ctx->d_pos.as<int>();
-    std::vector<int> slot_q(S, -1), init, sel;
-    std::vector<int64_t> slot_g(S, 0);   // global index of each slot's realization
-    std::vector<int32_t> act(S), itv(S), stv(S);
-    int64_t next = 0;                    // next batch position to start
-    int64_t in_work = 0;                 // slots covered by the operator work list
+    int nl = (ctx->opt_lanes > 1 && S >= 2 * kMinLaneSlots) ? 2 : 1;
+    if (nl == 2 && !ctx->lane_stream) {
+        if (hipStreamCreateWithFlags(&ctx->lane_stream, hipStreamNonBlocking) != hipSuccess) ctx->lane_stream = nullptr;
+        for (hipEvent_t& e : ctx->lane_ev)
+            if (ctx->lane_stream && !e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+    }
+    if (nl == 2 && (!ctx->lane_stream || !ctx->lane_ev[0] || !ctx->lane_ev[1])) nl = 1;
+    // the active counts are read back into pinned memory, so queueing a lane's
+    // read-back does not wait for its group
+    if (!ctx->h_count && hipHostMalloc((void**)&ctx->h_count, 8 * kMaxLanes) != hipSuccess) {
+        ctx->h_count = nullptr;
+        return fail(ctx, SDMM_ENOMEM, "pinned host memory for the CG counts");
+    }
+    const int M = ctx->P.M;
     const int group = ctx->opt_check;
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    // Kernel timing samples the second iteration of one check group in
-    // kTimeEvery (the other groups replay the captured graph): the
-    // active realizations are counted just before it (into the second int of
-    // any_active), then the product and the update are launched with events
-    // that take the time stamps of their own dispatch packets.
     const bool ktime = ctx->opt_ktime != 0;
-    constexpr int kTimeEvery = 4;
+    constexpr int kTimeEvery = 4;   // one check group in kTimeEvery of lane 0 is timed
+    Lane lanes[kMaxLanes];
+    const CgArgs a0 = cg_args(ctx, S, gidx, lambda);
+    for (int k = 0; k < nl; ++k) {
+        Lane& L = lanes[k];
+        L.id = k;
+        L.base = k == 0 ? 0 : S / 2;
+        L.S = nl == 1 ? S : (k == 0 ? S / 2 : S - S / 2);
+        L.s = k == 0 ? st : ctx->lane_stream;
+        L.G = &ctx->grp[k];
+        CgArgs& a = L.a;
+        a = a0;
+        a.n = L.S;
+        a.rtol = rtol;
+        a.max_iter = max_iter;
+        a.r += L.base * M;
+        a.p += L.base * M;
+        a.rr += L.base;
+        a.r0 += L.base;
+        a.iters += L.base;
+        a.relres += L.base;
+        a.status += L.base;
+        a.active += L.base;
+        a.any_active += 2 * k;
+        a.slot_q = ctx->w_slot_q.as<int>() + L.base;
+        a.init_slots = ctx->w_init.as<int>() + L.base;
+        a.iters_out = iters;
+        a.relres_out = relres;
+        a.status_out = status;
+        L.Y = ctx->w_Y.as<double>() + L.base * ctx->SR;
+        L.slot_q.assign(L.S, -1);
+        L.slot_g.assign(L.S, 0);
+        L.act.resize(L.S);
+        L.itv.resize(L.S);
+        L.stv.resize(L.S);
+    }
+    int64_t next = 0;   // next batch position to start
     int ngroup = 0;
-    const int tq = group > 1 ? 1 : 0;
-    int32_t* tcount = a.any_active + 1;
     if (ktime) {
         while ((int)ctx->kev.size() < 4) {
             hipEvent_t e = nullptr;
@@ -1158,137 +1240,169 @@ int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double
             ctx->kev.push_back(e);
         }
     }
-    auto body = [&](hipStream_t s, bool timed_group) -> hipError_t {
+    const int* pos = ctx->d_pos.as<int>();
+    // one check group of iterations of a lane; a timed group counts the
+    // active slots before its second iteration and launches that
+    // iteration's product and update with events that take the time stamps
+    // of their own dispatch packets
+    auto body = [&](Lane& L, bool timed_group) -> hipError_t {
+        const int tq = group > 1 ? 1 : 0;
         hipError_t e = hipSuccess;
         for (int q = 0; q < group && e == hipSuccess; ++q) {
             const bool timed = timed_group && q == tq;
-            if (timed && (e = launch_count_active(a.active, S, tcount, s)) != hipSuccess) break;
-            e = launch_cg_apply_mfma(a, a.p, Y, ctx->SR, ctx->d_work.as<int4>(), ctx->nwork,
-                                     ctx->d_perm.as<int>(), ctx->max_R, s, timed ? ctx->kev[0] : nullptr,
+            if (timed && (e = launch_count_active(L.a.active, L.S, L.a.any_active + 1, L.s)) != hipSuccess) break;
+            e = launch_cg_apply_mfma(L.a, L.a.p, L.Y, ctx->SR, L.G->d_work.as<int4>(), L.G->nwork,
+                                     L.G->d_perm.as<int>(), ctx->max_R, L.s, timed ? ctx->kev[0] : nullptr,
                                      timed ? ctx->kev[1] : nullptr);
             if (e == hipSuccess)
-                e = launch_cg_update2(a, Y, ctx->SR, pos, s, timed ? ctx->kev[2] : nullptr,
+                e = launch_cg_update2(L.a, L.Y, ctx->SR, pos, L.s, timed ? ctx->kev[2] : nullptr,
                                       timed ? ctx->kev[3] : nullptr);
         }
         return e;
     };
-    // after the group has synchronized: add the sampled launch durations
-    int32_t tactive = 0;
-    auto add_times = [&]() -> int {
-        float ma = 0.f, mu = 0.f;
-        HIPCHK(hipEventElapsedTime(&ma, ctx->kev[0], ctx->kev[1]));
-        HIPCHK(hipEventElapsedTime(&mu, ctx->kev[2], ctx->kev[3]));
-        ctx->counters.ms_cg_apply += ma;
-        ctx->counters.ms_cg_update += mu;
-        ctx->counters.cg_timed_launches += 1;
-        ctx->counters.cg_timed_active += tactive;
-        ctx->counters.cg_timed_columns += in_work;
-        return SDMM_OK;
-    };
-    auto release_graph = [&]() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-    };
-    auto capture = [&]() -> int {
-        release_graph();
+    auto capture = [&](Lane& L) -> int {
+        L.release();
         if (!ctx->opt_graph) return SDMM_OK;
-        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        hipError_t e = body(st, false);
-        hipError_t e2 = hipStreamEndCapture(st, &graph);
+        HIPCHK(hipStreamBeginCapture(L.s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = body(L, false);
+        hipError_t e2 = hipStreamEndCapture(L.s, &L.graph);
         if (e != hipSuccess || e2 != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            graph = nullptr;
+            if (L.graph) (void)hipGraphDestroy(L.graph);
+            L.graph = nullptr;
             return fail(ctx, SDMM_EDEVICE, "graph capture of the CG iterations failed");
         }
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            graph = nullptr;
-            exec = nullptr;
+        if (hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(L.graph);
+            L.graph = nullptr;
+            L.exec = nullptr;
             return fail(ctx, SDMM_EDEVICE, "graph instantiation failed");
         }
         return SDMM_OK;
     };
-    // pending realizations into the free slots, and their CG started
-    auto admit = [&]() -> int {
-        init.clear();
-        for (int64_t l = 0; l < S && next < n; ++l) {
-            if (slot_q[l] >= 0) continue;
-            slot_q[l] = (int)next;
-            slot_g[l] = ctx->h_gidx[next];
+    // pending realizations into the lane's free slots, and their CG started
+    auto admit = [&](Lane& L) -> int {
+        L.init.clear();
+        for (int64_t l = 0; l < L.S && next < n; ++l) {
+            if (L.slot_q[l] >= 0) continue;
+            L.slot_q[l] = (int)next;
+            L.slot_g[l] = ctx->h_gidx[next];
             ++next;
-            init.push_back((int)l);
+            L.init.push_back((int)l);
         }
-        if (init.empty()) return SDMM_OK;
-        HIPCHK(hipMemcpyAsync(ctx->w_slot_q.p, slot_q.data(), S * 4, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(ctx->w_init.p, init.data(), init.size() * 4, hipMemcpyHostToDevice, st));
-        HIPCHK(launch_cg_init(a, (int64_t)init.size(), st));
-        HIPCHK(hipStreamSynchronize(st));   // the host vectors change before the next admission
+        if (L.init.empty()) return SDMM_OK;
+        HIPCHK(hipMemcpyAsync(ctx->w_slot_q.as<int>() + L.base, L.slot_q.data(), L.S * 4, hipMemcpyHostToDevice,
+                              L.s));
+        HIPCHK(hipMemcpyAsync(ctx->w_init.as<int>() + L.base, L.init.data(), L.init.size() * 4,
+                              hipMemcpyHostToDevice, L.s));
+        HIPCHK(launch_cg_init(L.a, (int64_t)L.init.size(), L.s));
+        HIPCHK(hipStreamSynchronize(L.s));   // the host vectors change before the next admission
         return SDMM_OK;
     };
-    // finished realizations leave their slots (all occupied slots when `all`)
-    auto retire = [&](bool all) -> int {
-        HIPCHK(hipMemcpyAsync(act.data(), a.active, S * 4, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(itv.data(), a.iters, S * 4, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(stv.data(), a.status, S * 4, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        for (int64_t l = 0; l < S; ++l) {
-            if (slot_q[l] < 0 || (act[l] && !all)) continue;
-            tot_it += itv[l];
-            bad |= stv[l] != SDMM_CG_CONVERGED;
-            brk |= stv[l] == SDMM_CG_BREAKDOWN;
-            slot_q[l] = -1;
+    // finished realizations leave the lane's slots (all occupied slots when `all`)
+    auto retire = [&](Lane& L, bool all) -> int {
+        HIPCHK(hipMemcpyAsync(L.act.data(), L.a.active, L.S * 4, hipMemcpyDeviceToHost, L.s));
+        HIPCHK(hipMemcpyAsync(L.itv.data(), L.a.iters, L.S * 4, hipMemcpyDeviceToHost, L.s));
+        HIPCHK(hipMemcpyAsync(L.stv.data(), L.a.status, L.S * 4, hipMemcpyDeviceToHost, L.s));
+        HIPCHK(hipStreamSynchronize(L.s));
+        for (int64_t l = 0; l < L.S; ++l) {
+            if (L.slot_q[l] < 0 || (L.act[l] && !all)) continue;
+            tot_it += L.itv[l];
+            bad |= L.stv[l] != SDMM_CG_CONVERGED;
+            brk |= L.stv[l] == SDMM_CG_BREAKDOWN;
+            L.slot_q[l] = -1;
         }
         return SDMM_OK;
     };
-    // operator work over the occupied slots, and a new graph for it
-    auto regroup = [&]() -> int {
-        sel.clear();
-        for (int64_t l = 0; l < S; ++l)
-            if (slot_q[l] >= 0) sel.push_back((int)l);
+    // operator work over the lane's occupied slots, and a new graph for it
+    auto regroup = [&](Lane& L) -> int {
+        L.sel.clear();
+        for (int64_t l = 0; l < L.S; ++l)
+            if (L.slot_q[l] >= 0) L.sel.push_back((int)l);
         int r2;
-        if ((r2 = build_groups(ctx, S, &sel, slot_g.data(), st))) return r2;
-        in_work = (int64_t)sel.size();
-        return capture();
+        if ((r2 = build_groups(ctx, *L.G, L.S, &L.sel, L.slot_g.data(), L.s))) return r2;
+        L.in_work = (int64_t)L.sel.size();
+        return capture(L);
     };
-    if ((rc = admit()) || (rc = regroup())) {
-        release_graph();
-        return rc;
-    }
-    const int64_t refill = std::max<int64_t>(1, S / 16);
-    // every realization stops within max_iter iterations of its start
-    const int64_t max_groups = (n / refill + 2) * ((int64_t)max_iter / group + 2);
-    int32_t count = (int32_t)S;
-    for (int64_t g = 0;; ++g) {
-        if (g > max_groups) {
-            release_graph();
-            return fail(ctx, SDMM_EDEVICE, "the CG driver did not finish");
-        }
-        // one check group in kTimeEvery is timed (eager, with events); the
-        // others replay the captured graph when there is one
-        const bool timed_group = ktime && (ngroup++ % kTimeEvery == 0);
-        hipError_t e = (exec && !timed_group) ? hipGraphLaunch(exec, st) : body(st, timed_group);
-        if (e == hipSuccess) e = launch_count_active(a.active, S, a.any_active, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(&count, a.any_active, 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess && timed_group) e = hipMemcpyAsync(&tactive, tcount, 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-            release_graph();
-            return fail(ctx, SDMM_EDEVICE, hipGetErrorString(e));
-        }
+    // queue the lane's next check group and the read-back of its active count
+    auto launch = [&](Lane& L) -> int {
+        L.timed = ktime && L.id == 0 && (ngroup++ % kTimeEvery == 0);
+        hipError_t e = (L.exec && !L.timed) ? hipGraphLaunch(L.exec, L.s) : body(L, L.timed);
+        if (e == hipSuccess) e = launch_count_active(L.a.active, L.S, L.a.any_active, L.s);
+        if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_count + 2 * L.id, L.a.any_active, 8, hipMemcpyDeviceToHost, L.s);
+        if (e != hipSuccess) return fail(ctx, SDMM_EDEVICE, hipGetErrorString(e));
         ctx->counters.cg_launches += group;
-        if (timed_group && (rc = add_times())) break;
-        if (count == 0 && next >= n) break;
-        if (next < n && S - count >= refill) {
-            if ((rc = retire(false)) || (rc = admit()) || (rc = regroup())) break;
-        } else if (next >= n && count < 0.75 * in_work) {
-            if ((rc = retire(false)) || (rc = regroup())) break;
+        ++L.groups;
+        return SDMM_OK;
+    };
+    // the lane's group has finished: timing, then retire / refill / compact
+    auto service = [&](Lane& L) -> int {
+        HIPCHK(hipStreamSynchronize(L.s));
+        const int32_t count = ctx->h_count[2 * L.id], tactive = ctx->h_count[2 * L.id + 1];
+        if (L.timed) {
+            float ma = 0.f, mu = 0.f;
+            HIPCHK(hipEventElapsedTime(&ma, ctx->kev[0], ctx->kev[1]));
+            HIPCHK(hipEventElapsedTime(&mu, ctx->kev[2], ctx->kev[3]));
+            ctx->counters.ms_cg_apply += ma;
+            ctx->counters.ms_cg_update += mu;
+            ctx->counters.cg_timed_launches += 1;
+            ctx->counters.cg_timed_active += tactive;
+            ctx->counters.cg_timed_columns += L.in_work;
+        }
+        int r2;
+        const int64_t refill = std::max<int64_t>(1, L.S / 16);
+        if (count == 0 && next >= n) {
+            L.done = true;
+            return retire(L, true);
+        }
+        if (next < n && L.S - count >= refill) {
+            if ((r2 = retire(L, false)) || (r2 = admit(L)) || (r2 = regroup(L))) return r2;
+        } else if (next >= n && count < 0.75 * L.in_work) {
+            if ((r2 = retire(L, false)) || (r2 = regroup(L))) return r2;
+        }
+        return SDMM_OK;
+    };
+    auto release_all = [&]() {
+        for (int k = 0; k < nl; ++k) lanes[k].release();
+    };
+    // the second lane starts after the work already queued on st
+    if (nl == 2) {
+        HIPCHK(hipEventRecord(ctx->lane_ev[0], st));
+        HIPCHK(hipStreamWaitEvent(ctx->lane_stream, ctx->lane_ev[0], 0));
+    }
+    for (int k = 0; k < nl && !rc; ++k)
+        if (!(rc = admit(lanes[k]))) rc = regroup(lanes[k]);
+    // every realization stops within max_iter iterations of its start
+    const int64_t max_groups = (n / std::max<int64_t>(1, S / (16 * nl)) + 2) * ((int64_t)max_iter / group + 2);
+    for (int k = 0; k < nl && !rc; ++k) {
+        Lane& L = lanes[k];
+        if (L.in_work == 0) {
+            L.done = true;
+            continue;
+        }
+        rc = launch(L);
+    }
+    // round robin: each lane is serviced when its group ends and relaunched at
+    // once, while the other lane's group keeps the device busy
+    for (bool busy = true; busy && !rc;) {
+        busy = false;
+        for (int k = 0; k < nl && !rc; ++k) {
+            Lane& L = lanes[k];
+            if (L.done) continue;
+            if (L.groups > max_groups) {
+                rc = fail(ctx, SDMM_EDEVICE, "the CG driver did not finish");
+                break;
+            }
+            if ((rc = service(L))) break;
+            if (!L.done) {
+                if ((rc = launch(L))) break;
+                busy = true;
+            }
         }
     }
-    release_graph();
-    if (rc) return rc;
-    return retire(true);
+    // nothing of either lane is in flight when their graphs are destroyed
+    for (int k = 0; k < nl; ++k) (void)hipStreamSynchronize(lanes[k].s);
+    release_all();
+    return rc;
 }
 
 hipStream_t work_stream(sdmm_ctx* ctx, hipStream_t user) {
@@ -1422,16 +1536,17 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const
         const int64_t* g = gidx + c0;
         const double* lam = lambda + c0 * M;
         if ((rc = fetch_gidx(ctx, g, cn, st))) return rc;
-        if ((rc = build_groups(ctx, cn, nullptr, ctx->h_gidx.data(), st))) return rc;
+        Groups& G = ctx->grp[0];
+        if ((rc = build_groups(ctx, G, cn, nullptr, ctx->h_gidx.data(), st))) return rc;
         CgArgs a = cg_args(ctx, cn, g, const_cast<double*>(lam));
         if (ctx->P.n_kernel > 0) {
             HIPCHK(launch_cg_apply_mfma(a, lam, ctx->w_Y.as<double>(), ctx->SR,
-                                        ctx->d_work.as<int4>(), ctx->nwork, ctx->d_perm.as<int>(), ctx->max_R, st));
+                                        G.d_work.as<int4>(), G.nwork, G.d_perm.as<int>(), ctx->max_R, st));
             HIPCHK(launch_gather_global(ctx->w_Y.as<double>(), ctx->SR, ctx->d_pos.as<int>(), M, cn,
                                         ctx->w_Slam.as<double>(), st));
             HIPCHK(launch_alpha(a, ctx->w_Slam.as<double>(), ctx->w_alpha.as<double>(), st));
         }
-        if (ctx->d_part.bytes < (size_t)ctx->part_total * 8 && (rc = alloc(ctx, ctx->d_part, ctx->part_total * 8)))
+        if (ctx->d_part.bytes < (size_t)G.part_total * 8 && (rc = alloc(ctx, ctx->d_part, G.part_total * 8)))
             return rc;
         MomArgs m{};
         m.n = cn;
@@ -1457,9 +1572,9 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const
         m.lam1 = ctx->d_lam1.as<double>();
         m.lam2 = ctx->d_lam2.as<double>();
         m.wsum = ctx->d_wsum.as<double>();
-        HIPCHK(launch_accumulate_chunks(m, ctx->d_awork.as<int4>(), ctx->nawork, ctx->d_perm.as<int>(),
-                                        ctx->d_slot.as<int64_t>(), ctx->d_part.as<double>(), ctx->d_pair_sub.as<int>(),
-                                        ctx->d_pair_k.as<int>(), ctx->d_item0.as<int>(), (int)ctx->pair_sub.size(),
+        HIPCHK(launch_accumulate_chunks(m, G.d_awork.as<int4>(), G.nawork, G.d_perm.as<int>(),
+                                        G.d_slot.as<int64_t>(), ctx->d_part.as<double>(), ctx->d_pair_sub.as<int>(),
+                                        ctx->d_pair_k.as<int>(), G.d_item0.as<int>(), (int)ctx->pair_sub.size(),
                                         ctx->max_ext, st));
         HIPCHK(hipStreamSynchronize(st));  // the group tables are rebuilt by the next chunk
     }

@@ -74,7 +74,7 @@ EXPORTS = {
     "sdmm_get_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CCounters)]),
     "sdmm_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
 }
-OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2, "kernel_timing": 3}
+OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2, "kernel_timing": 3, "cg_lanes": 4}
 
 _LIB = None
 

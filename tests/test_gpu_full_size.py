@@ -180,9 +180,10 @@ CG_CONVERGED, CG_MAXITER = 0, 1   # status values of sdmm_solve_interface
 
 def test_cg_slot_refill_keeps_results():
     """The CG keeps a fixed number of realizations in flight and starts a
-    pending realization in each finished one's slot.  Every output must be
-    bit-identical whatever the slot count, also for realizations that stop at
-    max_iter, and the iteration counter must add up the same."""
+    pending realization in each finished one's slot; with enough slots they
+    are split into two lanes on two streams.  Every output must be
+    bit-identical whatever the slot count and lanes, also for realizations
+    that stop at max_iter, and the iteration counter must add up the same."""
     print("case: CG slot refill on cfg1", flush=True)
     ctx = gpu_ctx(problem("cfg1"), "fp64")
     n = ctx.sizes()["n_real"]
@@ -192,9 +193,11 @@ def test_cg_slot_refill_keeps_results():
     _, lam_r, it_r, rr_r, st_r, _ = gpu_solve(ctx, idx, rtol=1e-10)
     tot_r = ctx.counters()["cg_iterations"] - c0
     assert (st_r == CG_CONVERGED).all() and tot_r == int(it_r.sum())
-    for slots in (50, 3):
-        print("case: cfg1 with %d CG slots" % slots, flush=True)
+    # 361 slots run as two lanes on two streams; one lane, 50 and 3 slots must agree
+    for slots, lanes in ((n, 1), (50, 2), (3, 2)):
+        print("case: cfg1 with %d CG slots, lanes option %d" % (slots, lanes), flush=True)
         ctx.set_option("cg_chunk", slots)
+        ctx.set_option("cg_lanes", lanes)
         c0 = ctx.counters()["cg_iterations"]
         _, lam, it, rr, st, _ = gpu_solve(ctx, idx, rtol=1e-10)
         assert ctx.counters()["cg_iterations"] - c0 == tot_r
@@ -202,6 +205,7 @@ def test_cg_slot_refill_keeps_results():
         assert np.array_equal(it, it_r) and np.array_equal(rr, rr_r) and np.array_equal(st, st_r)
     print("case: cfg1 stopped at max_iter with 7 and 361 slots", flush=True)
     out = []
+    ctx.set_option("cg_lanes", 2)
     for slots in (7, n):
         ctx.set_option("cg_chunk", slots)
         _, lam, it, rr, st, _ = gpu_solve(ctx, idx, rtol=1e-10, max_iter=40, allow_notconv=True)
