@@ -262,6 +262,20 @@ def read_traffic(kernel, workload):
         return None
 
 
+def cg_whole(sum_R, sum_R2, M, real_iters, ms_cg):
+    """The whole CG of a step against both peaks: the product's and the
+    update's algorithmic bytes and the product's flops over every
+    realization-iteration, divided by the CG wall time.  The library runs two
+    lanes whose kernels overlap on the device, so this is the figure that
+    per-launch durations (which include the co-running kernel) understate."""
+    b = 8.0 * (M + sum_R) + 8.0 * (sum_R + 6 * M)
+    f = 2.0 * sum_R2
+    t = ms_cg * 1e-3
+    return {"realization_iterations": real_iters, "bytes_per_unit": b, "flops_per_unit": f,
+            "gbps": b * real_iters / t / 1e9, "frac_hbm": b * real_iters / t / PEAK_HBM,
+            "tflops": f * real_iters / t / 1e12, "frac_fp64_mfma": f * real_iters / t / PEAK_FP64}
+
+
 def kernel_rooflines(sz, sum_R, sum_R2, d, basis_ms, prec, workload):
     """Per-kernel roofline entries.  The algorithmic unit of the CG kernels is
     one realization-iteration (one CG iteration of one realization still
@@ -374,7 +388,8 @@ def main():
                      "cg_iterations_mean": d["cg_iterations"] / max(1, d["realizations"]),
                      "refinement_group_steps_per_unit": (ctx.counters()["refinement_steps"] / sz["n_units"]
                                                    if prec == "mixed" else 0.0),
-                     "cg_launches_per_step": d["cg_launches"] / args.steps}
+                     "cg_launches_per_step": d["cg_launches"] / args.steps,
+                     "cg_whole": cg_whole(sum_R, sum_R2, M, d["cg_iterations"] / args.steps, sms)}
     main_r = res[args.precision]
     kmain = kern[args.precision]
     # dominant kernel: largest share of the step (sampled CG launches scaled

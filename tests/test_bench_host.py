@@ -64,3 +64,15 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, cwd=ROOT, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_whole_cg_figure_adds_both_kernels():
+    """The whole-CG figure counts the product's and the update's algorithmic
+    bytes, 8 (M + sum R_i) + 8 (sum R_i + 6 M) per realization-iteration, and
+    the product's 2 sum R_i^2 flops, over the CG wall time."""
+    w = bench.cg_whole(2560, 181248, 1280, 1.0e6, 100.0)
+    assert w["bytes_per_unit"] == 8 * (1280 + 2560) + 8 * (2560 + 6 * 1280) == 112640
+    assert w["gbps"] == pytest.approx(112640 * 1.0e6 / 0.1 / 1e9)
+    assert w["frac_hbm"] == pytest.approx(w["gbps"] / 8000.0)
+    assert w["tflops"] == pytest.approx(2 * 181248 * 1.0e6 / 0.1 / 1e12)
+    assert w["frac_fp64_mfma"] == pytest.approx(w["tflops"] / 78.6)
