@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--cg-chunk", type=int, default=0, help="realizations in flight in the CG (0: autotune)")
+    ap.add_argument("--cg-lanes", type=int, default=0, choices=[0, 1, 2],
+                    help="CG lanes (0: the library default, two lanes whose kernels overlap)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -369,6 +371,8 @@ def main():
     stokes_ms = ctx.counters()["ms_basis_stokes"]
     g = torch.arange(n, dtype=torch.int64, device="cuda")
     lam = torch.zeros((n, M), dtype=torch.float64, device="cuda")
+    if args.cg_lanes:
+        ctx.set_option("cg_lanes", args.cg_lanes)
     if args.cg_chunk > 0:
         chunk = args.cg_chunk
         ctx.set_option("cg_chunk", chunk)
@@ -410,7 +414,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
            "config": {"workload": args.workload, "n_real": n, "M": M, "basis_units": sz["n_units"],
-                      "precision": args.precision, "rtol": args.rtol, "cg_chunk": chunk},
+                      "precision": args.precision, "rtol": args.rtol, "cg_chunk": chunk,
+                      "cg_lanes": args.cg_lanes or 2},
            "basis_builds_per_s": main_r["basis_builds_per_s"],
            "fp64": res.get("fp64"), "mixed": res.get("mixed"), "stokes_basis_ms": stokes_ms,
            "roofline": roof, "kernels": kmain}

@@ -228,9 +228,10 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
  *   SDMM_OPT_CG_CHECK  iterations between host convergence checks (1..1024,
  *                      default 64)
  *   SDMM_OPT_CG_GRAPH  1 = replay the iteration group as a captured HIP graph
- *   SDMM_OPT_CG_LANES  2 (default) = split the slots into two lanes with their
- *                      own streams, so that one lane's operator product
- *                      overlaps the other's update on the device; 1 = one
+ *   SDMM_OPT_CG_LANES  2 (default) = from 2048 slots on, split the slots into
+ *                      two lanes with their own streams, so that one lane's
+ *                      operator product overlaps the other's update on the
+ *                      device; 1 = one lane
  *   SDMM_OPT_KERNEL_TIMING 1 = time one iteration of every fourth check group
  *                      with HIP events and sum the durations into the
  *                      counters (those groups run eagerly, the others replay

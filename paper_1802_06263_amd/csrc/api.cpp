@@ -1148,7 +1148,7 @@ namespace {
 // overlaps the other's update (HBM) on the device.  A realization's
 // arithmetic does not depend on its slot, lane or neighbours, so results do
 // not depend on S or on the lanes.
-constexpr int64_t kMinLaneSlots = 64;
+constexpr int64_t kMinLaneSlots = 1024;   // smaller lanes gain nothing and cost latency
 
 struct Lane {
     int id = 0;

@@ -138,6 +138,9 @@ class GpuBackend:
         self.torch = torch
         self.ctx = sdmm.Context(0)
         self.ctx.set_problem(prob)
+        # the engines already overlap on the device; lanes would add streams
+        # beyond the device's hardware queues
+        self.ctx.set_option("cg_lanes", 1)
         self.sizes = self.ctx.sizes()
         self.stream = torch.cuda.Stream()
         self.ctx.build_flux_basis(precision, stream=self.stream)

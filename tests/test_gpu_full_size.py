@@ -180,10 +180,9 @@ CG_CONVERGED, CG_MAXITER = 0, 1   # status values of sdmm_solve_interface
 
 def test_cg_slot_refill_keeps_results():
     """The CG keeps a fixed number of realizations in flight and starts a
-    pending realization in each finished one's slot; with enough slots they
-    are split into two lanes on two streams.  Every output must be
-    bit-identical whatever the slot count and lanes, also for realizations
-    that stop at max_iter, and the iteration counter must add up the same."""
+    pending realization in each finished one's slot.  Every output must be
+    bit-identical whatever the slot count, also for realizations that stop at
+    max_iter, and the iteration counter must add up the same."""
     print("case: CG slot refill on cfg1", flush=True)
     ctx = gpu_ctx(problem("cfg1"), "fp64")
     n = ctx.sizes()["n_real"]
@@ -193,7 +192,6 @@ def test_cg_slot_refill_keeps_results():
     _, lam_r, it_r, rr_r, st_r, _ = gpu_solve(ctx, idx, rtol=1e-10)
     tot_r = ctx.counters()["cg_iterations"] - c0
     assert (st_r == CG_CONVERGED).all() and tot_r == int(it_r.sum())
-    # 361 slots run as two lanes on two streams; one lane, 50 and 3 slots must agree
     for slots, lanes in ((n, 1), (50, 2), (3, 2)):
         print("case: cfg1 with %d CG slots, lanes option %d" % (slots, lanes), flush=True)
         ctx.set_option("cg_chunk", slots)
@@ -211,6 +209,26 @@ def test_cg_slot_refill_keeps_results():
         _, lam, it, rr, st, _ = gpu_solve(ctx, idx, rtol=1e-10, max_iter=40, allow_notconv=True)
         out.append((lam.cpu().numpy(), it, rr, st))
     assert (out[0][3] == CG_MAXITER).all() and (out[0][1] == 40).all()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    ctx.close()
+
+
+def test_cg_two_lanes_keep_results():
+    """From 2048 slots the CG runs two lanes on two streams whose kernels
+    overlap; the outputs must be bit-identical to one lane."""
+    print("case: cfg2 with 4096 slots, two lanes against one", flush=True)
+    ctx = gpu_ctx(problem("cfg2"), "fp64")
+    n = ctx.sizes()["n_real"]
+    idx = np.arange(n)
+    ctx.set_option("cg_chunk", 4096)
+    out = []
+    for lanes in (2, 1):
+        ctx.set_option("cg_lanes", lanes)
+        c0 = ctx.counters()["cg_iterations"]
+        _, lam, it, rr, st, _ = gpu_solve(ctx, idx, rtol=1e-8)
+        out.append((lam.cpu().numpy(), it, rr, st, ctx.counters()["cg_iterations"] - c0))
+    assert (out[0][3] == CG_CONVERGED).all()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
     ctx.close()
