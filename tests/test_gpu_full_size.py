@@ -231,4 +231,13 @@ def test_cg_two_lanes_keep_results():
     assert (out[0][3] == CG_CONVERGED).all()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+    print("case: cfg2 stopped at max_iter, two lanes against one", flush=True)
+    out = []
+    for lanes in (2, 1):
+        ctx.set_option("cg_lanes", lanes)
+        _, lam, it, rr, st, _ = gpu_solve(ctx, idx, rtol=1e-8, max_iter=40, allow_notconv=True)
+        out.append((lam.cpu().numpy(), it, rr, st))
+    assert (out[0][3] == CG_MAXITER).all() and (out[0][1] == 40).all()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
     ctx.close()
