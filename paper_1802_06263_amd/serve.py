@@ -132,6 +132,8 @@ class Engine:
 class GpuBackend:
     """Library context of one problem with its basis built and resident."""
 
+    batch_per_slots = 2   # largest batch, in multiples of the autotuned CG slot count
+
     def __init__(self, prob, precision, autotune, max_batch):
         import torch
         from . import sdmm
@@ -150,7 +152,10 @@ class GpuBackend:
         if autotune:
             n = min(self.sizes["n_real"], 8192)
             g = torch.arange(n, dtype=torch.int64, device="cuda")
-            self.max_batch = min(max_batch, max(256, self.ctx.autotune(g, stream=self.stream)))
+            # the CG refills its slots from the batch, so a batch may hold more
+            # realizations than there are slots without draining between them
+            slots = self.ctx.autotune(g, stream=self.stream)
+            self.max_batch = min(max_batch, max(256, self.batch_per_slots * slots))
             self.stream.synchronize()
 
     def solve(self, gidx, rtol, accumulate):
