@@ -86,3 +86,24 @@ def test_set_problem_rejects_bad_input():
     with pytest.raises(sdmm.SdmmError):
         ctx.set_problem(p)
     ctx.close()
+
+
+def test_options_are_validated():
+    """The CG tuning options accept their documented ranges only (a host-only
+    context is enough: options need no device)."""
+    from paper_1802_06263_amd import sdmm
+    ctx = sdmm.Context(-1)
+    ctx.set_option("cg_chunk", 0)
+    ctx.set_option("cg_chunk", 4096)
+    ctx.set_option("cg_check", 1)
+    ctx.set_option("cg_check", 1024)
+    ctx.set_option("cg_lanes", 1)
+    ctx.set_option("cg_lanes", 2)
+    ctx.set_option("cg_graph", 0)
+    ctx.set_option("kernel_timing", 1)
+    for name, bad in (("cg_lanes", 0), ("cg_lanes", 3), ("cg_check", 0), ("cg_check", 1025), ("cg_chunk", -1)):
+        with pytest.raises(sdmm.SdmmError):
+            ctx.set_option(name, bad)
+    rc = ctx.lib.sdmm_set_option(ctx.h, 99, 1)
+    assert rc == sdmm.EINVAL
+    ctx.close()

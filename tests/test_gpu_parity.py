@@ -124,6 +124,12 @@ def test_edge_cases(cfg0):
     # max_iter too small: ENOTCONV with the per-realization status filled
     _, lam, it, rr, st, rc = gpu_solve(ctx, [0, 1], rtol=1e-12, max_iter=1, allow_notconv=True)
     assert rc == sdmm.ENOTCONV and (st == 1).all() and (it == 1).all()
+    # the same realization several times in one batch: every copy takes its
+    # own CG slot and all copies give identical outputs
+    _, lam2, it2, rr2, st2, _ = gpu_solve(ctx, [3, 3, 7, 3], rtol=1e-12)
+    l2 = lam2.cpu().numpy()
+    assert np.array_equal(l2[0], l2[1]) and np.array_equal(l2[0], l2[3]) and not np.array_equal(l2[0], l2[2])
+    assert it2[0] == it2[1] == it2[3] and rr2[0] == rr2[1] == rr2[3] and (st2 == 0).all()
     with pytest.raises(sdmm.SdmmError):
         ctx.solve_interface(g, lam, rtol=-1.0)
     with pytest.raises(sdmm.SdmmError):
