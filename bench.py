@@ -378,7 +378,7 @@ def main():
         ctx.set_option("cg_chunk", chunk)
     else:
         chunk = ctx.autotune(g, rtol=args.rtol)
-        log("autotuned CG chunk: %d realizations" % chunk)
+        log("autotuned CG slots: %d realizations in flight" % chunk)
     ctx.set_option("kernel_timing", 1)
     other = "fp64" if args.precision == "mixed" else "mixed"
     res, kern = {}, {}

@@ -253,7 +253,8 @@ class Context:
         return g, G[:nk]
 
     def autotune(self, gidx, rtol=1e-8, max_iter=None, stream=None):
-        """Pick the CG chunk size on gidx (int64 device tensor); returns it."""
+        """Pick the CG slot count (realizations in flight) on gidx (int64 device
+        tensor); sets it as the cg_chunk option and returns it."""
         out = ctypes.c_int64()
         if max_iter is None:
             max_iter = 10 * self._sizes["M"]
