@@ -111,7 +111,7 @@ struct sdmm_ctx {
     std::vector<hipEvent_t> kev;   // event pool of the kernel timing
     hipStream_t cap_stream = nullptr;
     hipStream_t lane_stream = nullptr;   // the second CG lane
-    hipEvent_t lane_ev[2] = {};          // fork / join of the second lane
+    hipEvent_t lane_ev = nullptr;        // the second lane starts after the work queued before it
     int opt_lanes = 2;                   // CG lanes (1 or 2)
     int32_t* h_count = nullptr;          // pinned: per lane the active count and the timed count
     sdmm_counters counters{};
@@ -907,8 +907,7 @@ int sdmm_destroy(sdmm_ctx* ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->lane_stream) (void)hipStreamDestroy(ctx->lane_stream);
     if (ctx->h_count) (void)hipHostFree(ctx->h_count);
-    for (hipEvent_t e : ctx->lane_ev)
-        if (e) (void)hipEventDestroy(e);
+    if (ctx->lane_ev) (void)hipEventDestroy(ctx->lane_ev);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->kev)
@@ -1180,12 +1179,12 @@ int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double
     S = std::max<int64_t>(1, std::min(S, n));
     if ((rc = fetch_gidx(ctx, gidx, n, st))) return rc;
     int nl = (ctx->opt_lanes > 1 && S >= 2 * kMinLaneSlots) ? 2 : 1;
-    if (nl == 2 && !ctx->lane_stream) {
-        if (hipStreamCreateWithFlags(&ctx->lane_stream, hipStreamNonBlocking) != hipSuccess) ctx->lane_stream = nullptr;
-        for (hipEvent_t& e : ctx->lane_ev)
-            if (ctx->lane_stream && !e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
-    }
-    if (nl == 2 && (!ctx->lane_stream || !ctx->lane_ev[0] || !ctx->lane_ev[1])) nl = 1;
+    if (nl == 2 && !ctx->lane_stream &&
+        hipStreamCreateWithFlags(&ctx->lane_stream, hipStreamNonBlocking) != hipSuccess)
+        ctx->lane_stream = nullptr;
+    if (nl == 2 && !ctx->lane_ev && hipEventCreateWithFlags(&ctx->lane_ev, hipEventDisableTiming) != hipSuccess)
+        ctx->lane_ev = nullptr;
+    if (nl == 2 && (!ctx->lane_stream || !ctx->lane_ev)) nl = 1;
     // the active counts are read back into pinned memory, so queueing a lane's
     // read-back does not wait for its group
     if (!ctx->h_count && hipHostMalloc((void**)&ctx->h_count, 8 * kMaxLanes) != hipSuccess) {
@@ -1366,8 +1365,8 @@ int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double
     };
     // the second lane starts after the work already queued on st
     if (nl == 2) {
-        HIPCHK(hipEventRecord(ctx->lane_ev[0], st));
-        HIPCHK(hipStreamWaitEvent(ctx->lane_stream, ctx->lane_ev[0], 0));
+        HIPCHK(hipEventRecord(ctx->lane_ev, st));
+        HIPCHK(hipStreamWaitEvent(ctx->lane_stream, ctx->lane_ev, 0));
     }
     for (int k = 0; k < nl && !rc; ++k)
         if (!(rc = admit(lanes[k]))) rc = regroup(lanes[k]);
