@@ -1244,10 +1244,13 @@ int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double
     // active slots before its second iteration and launches that
     // iteration's product and update with events that take the time stamps
     // of their own dispatch packets
-    auto body = [&](Lane& L, bool timed_group) -> hipError_t {
-        const int tq = group > 1 ? 1 : 0;
+    // the graph holds `gcap` iterations and is launched group / gcap times per
+    // check group, so that the re-capture after a refill or compaction is short
+    const int gcap = (group > 16 && group % 16 == 0) ? 16 : group;
+    auto body = [&](Lane& L, bool timed_group, int iters) -> hipError_t {
+        const int tq = iters > 1 ? 1 : 0;
         hipError_t e = hipSuccess;
-        for (int q = 0; q < group && e == hipSuccess; ++q) {
+        for (int q = 0; q < iters && e == hipSuccess; ++q) {
             const bool timed = timed_group && q == tq;
             if (timed && (e = launch_count_active(L.a.active, L.S, L.a.any_active + 1, L.s)) != hipSuccess) break;
             e = launch_cg_apply_mfma(L.a, L.a.p, L.Y, ctx->SR, L.G->d_work.as<int4>(), L.G->nwork,
@@ -1263,7 +1266,7 @@ int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double
         L.release();
         if (!ctx->opt_graph) return SDMM_OK;
         HIPCHK(hipStreamBeginCapture(L.s, hipStreamCaptureModeThreadLocal));
-        hipError_t e = body(L, false);
+        hipError_t e = body(L, false, gcap);
         hipError_t e2 = hipStreamEndCapture(L.s, &L.graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (L.graph) (void)hipGraphDestroy(L.graph);
@@ -1325,7 +1328,12 @@ int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double
     // queue the lane's next check group and the read-back of its active count
     auto launch = [&](Lane& L) -> int {
         L.timed = ktime && L.id == 0 && (ngroup++ % kTimeEvery == 0);
-        hipError_t e = (L.exec && !L.timed) ? hipGraphLaunch(L.exec, L.s) : body(L, L.timed);
+        hipError_t e = hipSuccess;
+        if (L.exec && !L.timed) {
+            for (int j = 0; j < group / gcap && e == hipSuccess; ++j) e = hipGraphLaunch(L.exec, L.s);
+        } else {
+            e = body(L, L.timed, group);
+        }
         if (e == hipSuccess) e = launch_count_active(L.a.active, L.S, L.a.any_active, L.s);
         if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_count + 2 * L.id, L.a.any_active, 8, hipMemcpyDeviceToHost, L.s);
         if (e != hipSuccess) return fail(ctx, SDMM_EDEVICE, hipGetErrorString(e));
