@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void stokes_ldl_panel_kernel(const Stokes
     __shared__ double B[kTile * (kTile + 1)];
     const StokesDev s = sd[blockIdx.y];
     const int I = J + 1 + blockIdx.x;
-    if (J >= s.nblk || blockIdx.x >= s.w || I >= s.nblk) return;
+    if (J >= s.nblk || (int)blockIdx.x >= s.w || I >= s.nblk) return;
     const double* Td = tile_ptr(tiles, s, J, J);
     double* T = tile_ptr(tiles, s, I, J);
     const int tid = threadIdx.x;
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void stokes_fwd_update_kernel(const Stoke
     const StokesDev s = sd[blockIdx.y];
     const int I = J + 1 + blockIdx.x;
     const int c0 = blockIdx.z * kTile;
-    if (J >= s.nblk || blockIdx.x >= s.w || I >= s.nblk || c0 >= s.ncol) return;
+    if (J >= s.nblk || (int)blockIdx.x >= s.w || I >= s.nblk || c0 >= s.ncol) return;
     const int64_t ld = (int64_t)s.nblk * kTile;
     const double* T = tile_ptr(tiles, s, I, J);
     for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
