@@ -244,11 +244,12 @@ def test_cg_two_lanes_keep_results():
 
 
 def test_mixed_moments_match_fp64_cfg2():
-    """Full-size precision property on the 6561-realization layout: the moments
-    from the mixed-precision basis (FP32 factor, FP64-refined responses) match
-    those of the FP64 basis to 1e-8 relative in every field.  The FP64 path
-    itself is checked against the oracle on the smaller layouts; the CG runs to
-    rtol 1e-12 so that the comparison measures the basis, not the stopping."""
+    """Full-size precision property on the 6561-realization layout: the whole
+    mixed-precision path (FP32 factor, FP64-refined responses, then CG and
+    moments) gives the moments of the FP64 path to 1e-8 relative in every
+    field.  The FP64 path itself is checked against the oracle on the smaller
+    layouts.  The CG runs to rtol 1e-12 so that the comparison measures the
+    basis, not the stopping."""
     print("case: cfg2 moments, mixed against FP64", flush=True)
     from paper_1802_06263_amd.sdmm import FIELDS as SFIELDS
     mom = {}
@@ -261,6 +262,32 @@ def test_mixed_moments_match_fp64_cfg2():
         mom[prec] = {f: ctx.get_moments(f) for f in SFIELDS}
         if prec == "mixed":
             assert ctx.counters()["max_refine_residual"] <= 1e-12
+        ctx.close()
+    for f in SFIELDS:
+        (m64, v64), (mmx, vmx) = mom["fp64"][f], mom["mixed"][f]
+        em, ev = rel(mmx, m64), rel(vmx, v64)
+        print("  %s: mean %.2e, variance %.2e" % (f, em, ev), flush=True)
+        assert em < 1e-8 and ev < 1e-8, f
+
+
+def test_mixed_basis_moments_match_fp64_cfg3():
+    """The same property for the bases of the uneven layout (54273
+    realizations), with the interface solution held fixed: both contexts
+    accumulate the moments of one FP64 CG solution, so the comparison sees
+    only the bases and fine responses.  (Through the whole path the CG
+    stopping dominates there: the FP64 moments of lambda at rtol 1e-10 and
+    1e-11 differ by 5e-7.)"""
+    print("case: cfg3 moments of one interface solution, mixed against FP64 basis", flush=True)
+    from paper_1802_06263_amd.sdmm import FIELDS as SFIELDS
+    ctxs = {prec: gpu_ctx(problem("cfg3"), prec) for prec in ("fp64", "mixed")}
+    assert ctxs["mixed"].counters()["max_refine_residual"] <= 1e-12
+    n = ctxs["fp64"].sizes()["n_real"]
+    g, lam, it, rr, st, _ = gpu_solve(ctxs["fp64"], np.arange(n), rtol=1e-8)
+    assert (st == CG_CONVERGED).all()
+    mom = {}
+    for prec, ctx in ctxs.items():
+        ctx.accumulate_moments(g, lam)
+        mom[prec] = {f: ctx.get_moments(f) for f in SFIELDS}
         ctx.close()
     for f in SFIELDS:
         (m64, v64), (mmx, vmx) = mom["fp64"][f], mom["mixed"][f]
