@@ -11,8 +11,9 @@ projected onto the compatible loads and the solution is taken orthogonal
 motions that the BJS term leaves free.
 
 Readings: Q2-Q1 on rectangles (the numerical cases of the paper use the
-triangular pair); 3x3 Gauss per element; the velocity (inflow) is imposed on
-the whole Stokes outer boundary; the BJS coefficient uses the deterministic
+triangular pair); 3x3 Gauss per element; the velocity (inflow, optionally
+with a linear shear profile in y) is imposed on the whole Stokes outer
+boundary; the BJS coefficient uses the deterministic
 permeability k_bjs, so every Stokes operator is deterministic.
 """
 import numpy as np
@@ -35,6 +36,23 @@ def _dl2(s):
 
 def _l1(s):
     return np.stack([1 - s, s])
+
+
+def bjs_coefficient(nu, alpha, k_bjs):
+    """Friction coefficient of the BJS condition (Section 2, eq. BJS):
+    nu alpha / sqrt(K) with the deterministic permeability of the BJS term."""
+    return nu * alpha / np.sqrt(k_bjs)
+
+
+def bjs_edge_mass(coef, h):
+    """3x3 matrix of coef * int u_tau v_tau over one fine edge of length h for
+    the three Q2 trace nodes of that edge (the BJS term of the form a~_i of
+    Section 3.2), by 3-point Gauss on [0, 1] scaled by h."""
+    m = np.zeros((3, 3))
+    for qk, sq in enumerate(_Q):
+        Lv = _l2(sq)
+        m += _W[qk] * np.outer(Lv, Lv)
+    return coef * h * m
 
 
 def element_matrices(hx, hy, nu):
@@ -101,7 +119,7 @@ class StokesLocal:
         self.sides = {}
         dirichlet_nodes = set()
         bjs_rows, bjs_cols, bjs_vals = [], [], []
-        coef = nu * float(ph["alpha"]) / np.sqrt(float(ph["k_bjs"]))
+        coef = bjs_coefficient(nu, float(ph["alpha"]), float(ph["k_bjs"]))
         R = layout.sub_dofs[i].size
         self.R = R
         Q = np.zeros((R, self.nvel))
@@ -146,14 +164,13 @@ class StokesLocal:
                                 if normal[c] != 0.0:
                                     Q[q, 2 * enodes[a] + c] += normal[c] * ints[nd]
                 if f.kind == "sd":
-                    # BJS: coef * int u_tau v_tau on this fine edge (1-D Q2 mass)
-                    for qk, sq in enumerate(_Q):
-                        Lv = _l2(sq)
-                        for a in range(3):
-                            for b in range(3):
-                                bjs_rows.append(2 * enodes[a] + tang)
-                                bjs_cols.append(2 * enodes[b] + tang)
-                                bjs_vals.append(coef * _W[qk] * h * Lv[a] * Lv[b])
+                    # BJS: coef * int u_tau v_tau on this fine edge
+                    me = bjs_edge_mass(coef, h)
+                    for a in range(3):
+                        for b in range(3):
+                            bjs_rows.append(2 * enodes[a] + tang)
+                            bjs_cols.append(2 * enodes[b] + tang)
+                            bjs_vals.append(me[a, b])
         if bjs_vals:
             A = A + sp.coo_matrix((bjs_vals, (bjs_rows, bjs_cols)), shape=(self.nvel, self.nvel)).tocsr()
         self.A, self.B, self.Q = A, B, Q
@@ -165,7 +182,11 @@ class StokesLocal:
         self.floating = layout.is_floating(i)
         self.uD = np.zeros(self.nvel)
         inflow = ph["inflow"]
-        self.uD[2 * dd] = inflow[0]
+        # outer velocity (u_x, u_y) = (inflow_x + shear y, inflow_y); shear = 0
+        # gives the constant inflow of the configurations
+        shear = float(ph.get("inflow_shear", 0.0))
+        ynode = y0 + 0.5 * hy * (dd // self.nnx)
+        self.uD[2 * dd] = inflow[0] + shear * ynode
         self.uD[2 * dd + 1] = inflow[1]
         # kernel of a~_i for floating subdomains: rigid motions left free by BJS
         self.Z = None
