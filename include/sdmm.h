@@ -34,6 +34,7 @@
 #ifndef SDMM_H
 #define SDMM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -47,9 +48,17 @@ extern "C" {
 #define SDMM_ENOTCONV (-4)   /* some realization did not converge (status set) */
 #define SDMM_EBREAKDOWN (-5) /* CG breakdown (p^T S p <= 0 or NaN)             */
 #define SDMM_ESTATE (-6)     /* call made in the wrong order                   */
+#define SDMM_EBUSY (-7)      /* the resource is held by a call still running  */
 
 #define SDMM_PREC_FP64 0     /* factor and solves in FP64                      */
 #define SDMM_PREC_MIXED 1    /* FP32 factor and solves + FP64 refinement       */
+
+/* methods of sdmm_build_flux_basis (Section 5) */
+#define SDMM_METHOD_STOCHASTIC 0    /* Method S3 (Section 5.4): a basis for every  */
+                                    /* local KL realization, built once           */
+#define SDMM_METHOD_DETERMINISTIC 1 /* Method S2 (Section 5.3): a basis for every  */
+                                    /* global realization, built per batch inside */
+                                    /* sdmm_solve_interface                        */
 
 /* status values written per realization by sdmm_solve_interface */
 #define SDMM_CG_CONVERGED 0
@@ -63,7 +72,7 @@ extern "C" {
 #define SDMM_FIELD_STOKES_U 3 /* Stokes Q2 nodal velocities (x, y per node)    */
 #define SDMM_FIELD_STOKES_P 4 /* Stokes Q1 nodal pressures                     */
 
-/* index maps of sdmm_get_index_map */
+/* index maps of sdmm_get_index_maps */
 #define SDMM_MAP_INTERFACES 0 /* n_iface x 5: i, j, kind (0 ss 1 sd 2 dd), ndof, offset */
 #define SDMM_MAP_SUB_PTR 1    /* n_sub + 1: CSR pointer into the DOF list       */
 #define SDMM_MAP_SUB_DOFS 2   /* global mortar DOF of each local mortar DOF     */
@@ -74,15 +83,29 @@ extern "C" {
 
 typedef struct sdmm_ctx sdmm_ctx;
 
+/* Optional device allocator (for instance a framework's caching allocator).
+ * alloc returns a device pointer on `device` of at least `bytes` bytes,
+ * aligned to 256 bytes, or NULL on failure (the library then returns
+ * ENOMEM); release gives back a pointer that alloc returned, with the same
+ * size.  The library calls them from the host thread that calls it, with
+ * `device` current; `user` is passed through.  Without an allocator the
+ * library uses hipMalloc / hipFree. */
+typedef struct {
+    void* (*alloc)(size_t bytes, int device, void* user);
+    void (*release)(void* ptr, size_t bytes, int device, void* user);
+    void* user;
+} sdmm_alloc;
+
 /*
  * Problem description (Section 3.1: N_s Stokes subdomains numbered first,
  * then N_d Darcy subdomains; Section 3.3: mortar spaces; Section 2.1 and
  * eq. covariance: KL regions; Section 4: collocation rule).  All arrays are
  * host memory and are copied by sdmm_set_problem.
  *
- * Outer boundary: the velocity (inflow_x, inflow_y) is imposed on the whole
- * Stokes outer boundary; the Darcy outer boundary has p = p_bottom on
- * y = domain[2] and no flow elsewhere.  Body forces and sources are zero.
+ * Outer boundary: the velocity (inflow_x + inflow_shear y, inflow_y) is
+ * imposed on the whole Stokes outer boundary; the Darcy outer boundary has
+ * p = p_bottom on y = domain[2] and no flow elsewhere.  Body forces and
+ * sources are zero.
  * The GPU path requires p_bottom == 0 (the Darcy complementary solution is
  * then zero).
  */
@@ -91,6 +114,7 @@ typedef struct {
     double alpha;            /* BJS friction coefficient (eq. BJS)            */
     double k_bjs;            /* permeability in the BJS term (deterministic)  */
     double inflow_x, inflow_y;
+    double inflow_shear;     /* d(u_x)/dy of the imposed outer velocity       */
     double p_bottom;
     double domain[4];        /* x0 x1 y0 y1                                   */
     int32_t n_sub;
@@ -150,77 +174,98 @@ typedef struct {
 } sdmm_counters;
 
 /* Create a context on HIP device `device`.  Ownership of *out passes to the
- * caller, who releases it with sdmm_destroy.  EINVAL for a bad device.
- * device = -1 creates a context without a GPU: sdmm_set_problem, the sizes,
- * index maps, collocation and KL queries work; every call that computes on
- * the device returns ESTATE. */
-int sdmm_create(int device, sdmm_ctx** out);
+ * caller, who releases it with sdmm_destroy (which releases every problem
+ * of the context).  alloc may be NULL (hipMalloc / hipFree); the library
+ * copies the structure.  EINVAL for a bad device.  device = -1 creates a
+ * context without a GPU: sdmm_set_problem, the sizes, index maps,
+ * collocation and KL queries work; every call that computes on the device
+ * returns ESTATE. */
+int sdmm_create(int device, const sdmm_alloc* alloc, sdmm_ctx** out);
 int sdmm_destroy(sdmm_ctx* ctx);
 /* Message of the last failure on ctx; owned by ctx, valid until the next call. */
 const char* sdmm_last_error(const sdmm_ctx* ctx);
 
-/* Build meshes, interfaces and mortar maps (Section 3.1, 3.3), the KL
- * modes of every region (Section 2.1, eq. Fred with the separable kernel
- * of eq. covariance), the collocation points, weights and global->local
- * index table (Section 4; Step 4 of Method S3), and upload the Darcy KL
- * tables and Stokes operators.  Replaces any previous problem.  EINVAL
- * when subdomains do not tile, a region is not a union of Darcy
- * subdomains, a mortar has more DOFs per interface than the fine trace, or
- * p_bottom != 0. */
-int sdmm_set_problem(sdmm_ctx* ctx, const sdmm_problem* p);
-int sdmm_get_sizes(sdmm_ctx* ctx, sdmm_sizes* out);
+/* Add a problem to the context: build meshes, interfaces and mortar maps
+ * (Section 3.1, 3.3), the KL modes of every region (Section 2.1, eq. Fred
+ * with the separable kernel of eq. covariance), the collocation points,
+ * weights and global->local index table (Section 4; Step 4 of Method S3),
+ * and upload the Darcy KL tables and Stokes operators.  *problem_id (host)
+ * receives the problem's id, which every later call on it names; a context
+ * holds any number of problems, each with its own device state, streams,
+ * options and counters.  EINVAL when subdomains do not tile, a region is
+ * not a union of Darcy subdomains, a mortar has more DOFs per interface
+ * than the fine trace, or p_bottom != 0. */
+int sdmm_set_problem(sdmm_ctx* ctx, const sdmm_problem* p, int64_t* problem_id);
+/* Release one problem and all its device state (EINVAL for an unknown id). */
+int sdmm_release_problem(sdmm_ctx* ctx, int64_t id);
+int sdmm_get_sizes(sdmm_ctx* ctx, int64_t id, sdmm_sizes* out);
 /* Copy an integer index map (SDMM_MAP_*) to host `out` (capacity cap
  * entries); *n_out receives its length.  EINVAL if cap is too small. */
-int sdmm_get_index_map(sdmm_ctx* ctx, int kind, int64_t* out, int64_t cap, int64_t* n_out);
+int sdmm_get_index_maps(sdmm_ctx* ctx, int64_t id, int kind, int64_t* out, int64_t cap, int64_t* n_out);
 /* Collocation points (n_real x n_term, row-major) and weights (n_real) to
  * host memory; either pointer may be NULL. */
-int sdmm_get_collocation(sdmm_ctx* ctx, double* points, double* weights);
+int sdmm_get_collocation(sdmm_ctx* ctx, int64_t id, double* points, double* weights);
 /* KL eigenvalues sigma^2 lambda_a lambda_b of the kept modes of one region
  * and their 1-D mode indices (a, b) (host arrays of nterm and 2 nterm). */
-int sdmm_get_kl(sdmm_ctx* ctx, int region, double* lam, int32_t* modes);
+int sdmm_get_kl(sdmm_ctx* ctx, int64_t id, int region, double* lam, int32_t* modes);
 
-/* Method S3 pre-computation loop (Section 5.4): for every Darcy subdomain
- * and every local realization k of its region, build K (eq. KLapprox),
- * the RT0-Q0 operator and its banded factor, solve for every mortar basis
- * function (eqs. starDproblem1-2) and store S_{H,i}^{(k)}; for every Stokes
- * subdomain do the same once (eqs. starSproblem1-2) together with the
- * complementary solution (eqs. barSproblem1-2) that gives g_H.
- * precision: SDMM_PREC_FP64 or SDMM_PREC_MIXED. */
-int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream);
+/* Flux basis (Section 5).
+ * method SDMM_METHOD_STOCHASTIC, Method S3 pre-computation loop (Section
+ * 5.4): for every Darcy subdomain and every local realization k of its
+ * region, build K (eq. KLapprox), the RT0-Q0 operator and its banded
+ * factor, solve for every mortar basis function (eqs. starDproblem1-2) and
+ * store S_{H,i}^{(k)}; for every Stokes subdomain do the same once (eqs.
+ * starSproblem1-2) together with the complementary solution (eqs.
+ * barSproblem1-2) that gives g_H.
+ * method SDMM_METHOD_DETERMINISTIC, Method S2 (Section 5.3): only the
+ * Stokes part is built here; every sdmm_solve_interface call then builds
+ * S_{H,i} for each Darcy subdomain and each realization of its batch from
+ * that realization's own KL field, and solves with it.
+ * precision: SDMM_PREC_FP64 or SDMM_PREC_MIXED (FP32 factor and multi-RHS
+ * solves with FP32 accumulation, FP64 refinement of every response).
+ * Returns ENOTCONV (the basis is still stored) when the mixed refinement of
+ * some right-hand-side group stops above its tolerance. */
+int sdmm_build_flux_basis(sdmm_ctx* ctx, int64_t id, int method, int precision, void* stream);
 /* Copy S_{H,i}^{(k)} (R_i x R_i, column-major with leading dimension ld,
- * host) of subdomain `sub` and local realization k (k = 0 for Stokes).
- * The signs of Stokes-Stokes mortar DOFs are included. */
-int sdmm_get_basis(sdmm_ctx* ctx, int sub, int k, double* S, int64_t ld);
+ * host) of subdomain `sub` and local realization k (k = 0 for Stokes) of a
+ * stochastic basis.  The signs of Stokes-Stokes mortar DOFs are included. */
+int sdmm_get_basis(sdmm_ctx* ctx, int64_t id, int sub, int k, double* S, int64_t ld);
 
 /* The interface right-hand side g_H (host, M values; Section 5.1, the
  * complementary Stokes solutions of eqs. barSproblem1-2 tested with the
  * mortar functions) and the FETI matrix G (host, n_kernel x M, one row per
  * rigid-motion mode of a floating Stokes subdomain: its velocity trace on
  * the mortar functions).  Either pointer may be NULL.  Needs a built basis. */
-int sdmm_get_interface_data(sdmm_ctx* ctx, double* g, double* G);
+int sdmm_get_interface_data(sdmm_ctx* ctx, int64_t id, double* g, double* G);
 
-/* Solve S_H lambda = g_H (Section 5.1) for n global collocation points
- * with indices gidx (device int64, n), by CG with S_H applied from the
- * basis cache (Section 5.3, linear combinations of phi) and, with floating
- * Stokes subdomains, the FETI projection.  lambda_0 = 0; a realization
- * stops when ||r_k|| <= rtol ||r_0||.  Outputs (device): lambda (n x M,
- * row-major), iters (int32 n), relres (double n), status (int32 n,
- * SDMM_CG_*); iters/relres/status may be NULL.  Returns ENOTCONV when some
- * realization hit max_iter (outputs still filled). */
-int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol,
-                         int32_t max_iter, double* lambda, int32_t* iters, double* relres,
-                         int32_t* status, void* stream);
+/* Solve S_H lambda = g_H (Section 5.1) for n realizations by CG with S_H
+ * applied as linear combinations of the basis (Section 5.3) and, with
+ * floating Stokes subdomains, the FETI projection.
+ *   gidx (device int64, n): global collocation indices; or NULL, and then
+ *   y (device double, n x n_term, row-major) gives each realization's
+ *   point in the stochastic space directly (an off-grid request; needs
+ *   SDMM_METHOD_DETERMINISTIC, since a stochastic basis exists only for
+ *   the collocation points of the local grids).
+ * lambda_0 = 0; a realization stops when ||r_k|| <= rtol ||r_0||.  Outputs
+ * (device): lambda (n x M, row-major), iters (int32 n), relres (double n),
+ * status (int32 n, SDMM_CG_*); iters/relres/status may be NULL.  Returns
+ * ENOTCONV when some realization hit max_iter (outputs still filled). */
+int sdmm_solve_interface(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, const double* y, double rtol,
+                         int32_t max_iter, double* lambda, int32_t* iters, double* relres, int32_t* status,
+                         void* stream);
 /* Add n realizations to the moment accumulators (Section 2, Step 6 of
- * Method S3): gidx (device int64 n), lambda (device n x M from
- * sdmm_solve_interface), weights (device double n, or NULL for the
- * collocation weights of the points). */
-int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const double* lambda,
-                            const double* weights, void* stream);
-/* Mean and variance (host arrays of field_size[field]) of one field. */
-int sdmm_get_moments(sdmm_ctx* ctx, int field, double* mean, double* var);
-int sdmm_reset_moments(sdmm_ctx* ctx);
+ * Method S3): gidx (device int64 n) or, for off-grid requests, NULL and y
+ * (device n x n_term) as in sdmm_solve_interface; lambda (device n x M from
+ * sdmm_solve_interface); weights (device double n, or NULL for the
+ * collocation weights of the points; required with y). */
+int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, const double* y,
+                            const double* lambda, const double* weights, void* stream);
+/* Mean and variance (host arrays of cap >= field_size[field] entries) of one
+ * field; EINVAL if cap is too small. */
+int sdmm_get_moments(sdmm_ctx* ctx, int64_t id, int field, double* mean, double* var, int64_t cap);
+int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
 
-/* Tuning knobs of the batched CG (used by the autotuner):
+/* Tuning knobs of the batched CG of one problem (used by the autotuner):
  *   SDMM_OPT_CG_CHUNK  realizations in flight in the CG (slots; a finished
  *                      realization's slot is refilled from the batch) and
  *                      per moment pass (0 = sized so their vectors fit a
@@ -242,7 +287,7 @@ int sdmm_reset_moments(sdmm_ctx* ctx);
 #define SDMM_OPT_CG_GRAPH 2
 #define SDMM_OPT_KERNEL_TIMING 3
 #define SDMM_OPT_CG_LANES 4
-int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value);
+int sdmm_set_option(sdmm_ctx* ctx, int64_t id, int option, int64_t value);
 /* Autotuner of the batched CG: runs the first min(n, 16384) realizations of
  * gidx (device int64, n) through the whole CG (rtol, max_iter as in
  * sdmm_solve_interface) once per candidate slot count (all of the sample,
@@ -250,9 +295,9 @@ int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value);
  * for a ~200 MB cache budget) and keeps the fastest as SDMM_OPT_CG_CHUNK; *chunk_out (host, may be NULL)
  * receives it.  Needs a built basis; results of later solves do not depend
  * on the choice.  Counters are left as they were.  Runs on `stream`. */
-int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,
-                  int64_t* chunk_out);
-int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out);
+int sdmm_autotune(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter,
+                  void* stream, int64_t* chunk_out);
+int sdmm_get_counters(sdmm_ctx* ctx, int64_t id, sdmm_counters* out);
 
 #ifdef __cplusplus
 }

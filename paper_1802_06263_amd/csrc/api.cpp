@@ -21,11 +21,19 @@ namespace {
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    const sdmm_alloc* al = nullptr;   // the allocator that gave p (null: hipMalloc)
+    int dev = 0;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (al)
+                al->release(p, bytes, dev, al->user);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
+        al = nullptr;
     }
     template <class T>
     T* as() const { return reinterpret_cast<T*>(p); }
@@ -48,8 +56,11 @@ struct Groups {
 
 constexpr int kMaxLanes = 2;   // CG lanes: halves of the slots on their own streams
 
-struct sdmm_ctx {
+// State of one problem of a context (every call names its problem id).
+struct Prob {
     int device = 0;
+    const sdmm_alloc* alloc = nullptr;   // the context's allocator, or null
+    int method = SDMM_METHOD_STOCHASTIC;
     bool host_only = false;  // device -1: problem setup and maps only
     std::string err;
     bool have_problem = false;
@@ -120,7 +131,7 @@ struct sdmm_ctx {
 
 namespace {
 
-int fail(sdmm_ctx* c, int code, const std::string& msg) {
+int fail(Prob* c, int code, const std::string& msg) {
     if (c) c->err = msg;
     return code;
 }
@@ -132,27 +143,34 @@ int fail(sdmm_ctx* c, int code, const std::string& msg) {
             return fail(ctx, SDMM_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-int alloc(sdmm_ctx* ctx, DevBuf& b, size_t bytes) {
+int alloc(Prob* ctx, DevBuf& b, size_t bytes) {
     b.release();
     if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(&b.p, bytes);
-    if (e != hipSuccess) {
-        b.p = nullptr;
-        return fail(ctx, SDMM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    if (ctx->alloc) {
+        b.p = ctx->alloc->alloc(bytes, ctx->device, ctx->alloc->user);
+        if (!b.p) return fail(ctx, SDMM_ENOMEM, "the allocator gave no " + std::to_string(bytes) + " bytes");
+        b.al = ctx->alloc;
+        b.dev = ctx->device;
+    } else {
+        hipError_t e = hipMalloc(&b.p, bytes);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            return fail(ctx, SDMM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
     }
     b.bytes = bytes;
     return SDMM_OK;
 }
 
 template <class T>
-int upload(sdmm_ctx* ctx, DevBuf& b, const std::vector<T>& v) {
+int upload(Prob* ctx, DevBuf& b, const std::vector<T>& v) {
     int rc = alloc(ctx, b, v.size() * sizeof(T));
     if (rc) return rc;
     if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return SDMM_OK;
 }
 
-DarcyTables darcy_tables(sdmm_ctx* c) {
+DarcyTables darcy_tables(Prob* c) {
     DarcyTables t;
     t.dar = c->d_dar.as<DarcyDev>();
     t.units = c->d_units.as<UnitDev>();
@@ -175,7 +193,7 @@ DarcyTables darcy_tables(sdmm_ctx* c) {
     return t;
 }
 
-int setup_device(sdmm_ctx* ctx) {
+int setup_device(Prob* ctx) {
     Problem& P = ctx->P;
     const int nsub = (int)P.subs.size();
     // ---- Darcy tables and units
@@ -574,7 +592,7 @@ int setup_device(sdmm_ctx* ctx) {
     return SDMM_OK;
 }
 
-int build_stokes(sdmm_ctx* ctx, hipStream_t st) {
+int build_stokes(Prob* ctx, hipStream_t st) {
     Problem& P = ctx->P;
     const int ns = (int)ctx->sdev.size();
     HIPCHK(hipMemsetAsync(ctx->d_g.p, 0, ctx->d_g.bytes, st));
@@ -660,7 +678,7 @@ int build_stokes(sdmm_ctx* ctx, hipStream_t st) {
     return SDMM_OK;
 }
 
-CgArgs cg_args(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double* lam) {
+CgArgs cg_args(Prob* ctx, int64_t n, const int64_t* gidx, double* lam) {
     CgArgs a{};
     a.n = n;
     a.M = ctx->P.M;
@@ -696,7 +714,7 @@ CgArgs cg_args(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double* lam) {
 
 // Every global index must address a collocation point; checked on the
 // device before any kernel dereferences the global->local table.
-int check_indices(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
+int check_indices(Prob* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
     int32_t bad = 0;
     HIPCHK(hipMemsetAsync(ctx->d_flag.p, 0, 4, st));
     HIPCHK(launch_validate_index(gidx, n, ctx->P.nreal, ctx->d_flag.as<int32_t>(), st));
@@ -709,7 +727,7 @@ int check_indices(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st)
 // Sort the batch by local realization index, region by region, and cut the
 // (subdomain, local realization) groups into chunks of at most 64
 // realizations (moment work items) and 64 rows of S (operator work items).
-int fetch_gidx(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
+int fetch_gidx(Prob* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
     ctx->h_gidx.resize(n);
     HIPCHK(hipMemcpyAsync(ctx->h_gidx.data(), gidx, n * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -718,7 +736,7 @@ int fetch_gidx(sdmm_ctx* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
 
 // subset: positions of the realizations to include (null means all n);
 // hg: host global index of every position.
-int build_groups(sdmm_ctx* ctx, Groups& G, int64_t n, const std::vector<int>* subset, const int64_t* hg,
+int build_groups(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* subset, const int64_t* hg,
                  hipStream_t st) {
     const Problem& P = ctx->P;
     std::vector<int> all;
@@ -795,14 +813,14 @@ int build_groups(sdmm_ctx* ctx, Groups& G, int64_t n, const std::vector<int>* su
 // vectors (lambda, r, p and the subdomain-local operator results) are kept
 // within ~200 MB so that they stay resident in the 256 MB last-level cache
 // between the product and the update.
-int64_t chunk_size(sdmm_ctx* ctx, int64_t n) {
+int64_t chunk_size(Prob* ctx, int64_t n) {
     if (ctx->opt_chunk > 0) return std::min<int64_t>(n, ctx->opt_chunk);
     const int64_t per = (3 * (int64_t)ctx->P.M + ctx->SR) * 8 + 64;
     const int64_t c = std::max<int64_t>(256, (int64_t)(200.0 * 1024 * 1024) / per);
     return std::min(n, c);
 }
 
-int ensure_workspace(sdmm_ctx* ctx, int64_t n) {
+int ensure_workspace(Prob* ctx, int64_t n) {
     if (n <= ctx->w_cap) return SDMM_OK;
     const size_t M = ctx->P.M;
     int rc;
@@ -831,7 +849,7 @@ namespace {
 // One launch per shape class, each on its own stream (forked from and joined
 // back into `st`), largest class first; a single class runs on `st` itself.
 template <class F>
-hipError_t launch_classes(sdmm_ctx* ctx, hipStream_t st, F&& launch) {
+hipError_t launch_classes(Prob* ctx, hipStream_t st, F&& launch) {
     DarcyTables t = darcy_tables(ctx);
     const int nc = (int)ctx->classes.size();
     if (nc == 1) {
@@ -868,25 +886,24 @@ hipError_t launch_classes(sdmm_ctx* ctx, hipStream_t st, F&& launch) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int sdmm_create(int device, sdmm_ctx** out) {
-    if (!out) return SDMM_EINVAL;
+// A new problem slot on the context's device (device -1: host only).
+int impl_create(int device, const sdmm_alloc* al, Prob** out) {
     *out = nullptr;
+    Prob* c = new (std::nothrow) Prob();
+    if (!c) return SDMM_ENOMEM;
+    c->device = device;
+    c->alloc = al;
     if (device == -1) {
-        sdmm_ctx* c = new (std::nothrow) sdmm_ctx();
-        if (!c) return SDMM_ENOMEM;
-        c->device = -1;
         c->host_only = true;
         *out = c;
         return SDMM_OK;
     }
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SDMM_EINVAL;
-    if (hipSetDevice(device) != hipSuccess) return SDMM_EDEVICE;
-    sdmm_ctx* c = new (std::nothrow) sdmm_ctx();
-    if (!c) return SDMM_ENOMEM;
-    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return SDMM_EDEVICE;
+    }
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) {
             delete c;
@@ -896,7 +913,7 @@ int sdmm_create(int device, sdmm_ctx** out) {
     return SDMM_OK;
 }
 
-int sdmm_destroy(sdmm_ctx* ctx) {
+int impl_destroy(Prob* ctx) {
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) {
         delete ctx;
@@ -920,10 +937,8 @@ int sdmm_destroy(sdmm_ctx* ctx) {
     return SDMM_OK;
 }
 
-const char* sdmm_last_error(const sdmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-int sdmm_set_problem(sdmm_ctx* ctx, const sdmm_problem* p) {
-    if (!ctx || !p) return fail(ctx, SDMM_EINVAL, "null argument");
+int impl_set_problem(Prob* ctx, const sdmm_problem* p) {
     if (!ctx->host_only) {
         HIPCHK(hipSetDevice(ctx->device));
         HIPCHK(hipDeviceSynchronize());
@@ -943,7 +958,7 @@ int sdmm_set_problem(sdmm_ctx* ctx, const sdmm_problem* p) {
     return SDMM_OK;
 }
 
-int sdmm_get_sizes(sdmm_ctx* ctx, sdmm_sizes* o) {
+int impl_get_sizes(Prob* ctx, sdmm_sizes* o) {
     if (!ctx || !o) return fail(ctx, SDMM_EINVAL, "null argument");
     if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
     const Problem& P = ctx->P;
@@ -974,7 +989,7 @@ int sdmm_get_sizes(sdmm_ctx* ctx, sdmm_sizes* o) {
     return SDMM_OK;
 }
 
-int sdmm_get_index_map(sdmm_ctx* ctx, int kind, int64_t* out, int64_t cap, int64_t* n_out) {
+int impl_get_index_map(Prob* ctx, int kind, int64_t* out, int64_t cap, int64_t* n_out) {
     if (!ctx || !n_out) return fail(ctx, SDMM_EINVAL, "null argument");
     if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
     const Problem& P = ctx->P;
@@ -1004,7 +1019,7 @@ int sdmm_get_index_map(sdmm_ctx* ctx, int kind, int64_t* out, int64_t cap, int64
     return SDMM_OK;
 }
 
-int sdmm_get_collocation(sdmm_ctx* ctx, double* points, double* weights) {
+int impl_get_collocation(Prob* ctx, double* points, double* weights) {
     if (!ctx) return SDMM_EINVAL;
     if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
     const Problem& P = ctx->P;
@@ -1014,7 +1029,7 @@ int sdmm_get_collocation(sdmm_ctx* ctx, double* points, double* weights) {
     return SDMM_OK;
 }
 
-int sdmm_get_kl(sdmm_ctx* ctx, int region, double* lam, int32_t* modes) {
+int impl_get_kl(Prob* ctx, int region, double* lam, int32_t* modes) {
     if (!ctx) return SDMM_EINVAL;
     if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
     if (region < 0 || region >= ctx->P.n_region) return fail(ctx, SDMM_EINVAL, "bad region");
@@ -1029,11 +1044,14 @@ int sdmm_get_kl(sdmm_ctx* ctx, int region, double* lam, int32_t* modes) {
     return SDMM_OK;
 }
 
-int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
+int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
     if (precision != SDMM_PREC_FP64 && precision != SDMM_PREC_MIXED) return fail(ctx, SDMM_EINVAL, "bad precision");
+    if (method != SDMM_METHOD_STOCHASTIC && method != SDMM_METHOD_DETERMINISTIC)
+        return fail(ctx, SDMM_EINVAL, "bad method");
+    if (method == SDMM_METHOD_DETERMINISTIC) return fail(ctx, SDMM_EINVAL, "deterministic basis not available");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
@@ -1078,7 +1096,7 @@ int sdmm_build_flux_basis(sdmm_ctx* ctx, int precision, void* stream) {
     return SDMM_OK;
 }
 
-int sdmm_get_basis(sdmm_ctx* ctx, int sub, int k, double* S, int64_t ld) {
+int impl_get_basis(Prob* ctx, int sub, int k, double* S, int64_t ld) {
     if (!ctx || !S) return fail(ctx, SDMM_EINVAL, "null argument");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (sub < 0 || sub >= (int)ctx->P.subs.size()) return fail(ctx, SDMM_EINVAL, "bad subdomain");
@@ -1094,7 +1112,7 @@ int sdmm_get_basis(sdmm_ctx* ctx, int sub, int k, double* S, int64_t ld) {
     return SDMM_OK;
 }
 
-int sdmm_get_interface_data(sdmm_ctx* ctx, double* g, double* G) {
+int impl_get_interface_data(Prob* ctx, double* g, double* G) {
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
@@ -1106,7 +1124,7 @@ int sdmm_get_interface_data(sdmm_ctx* ctx, double* g, double* G) {
     return SDMM_OK;
 }
 
-int sdmm_set_option(sdmm_ctx* ctx, int option, int64_t value) {
+int impl_set_option(Prob* ctx, int option, int64_t value) {
     if (!ctx) return SDMM_EINVAL;
     switch (option) {
         case SDMM_OPT_CG_CHUNK:
@@ -1172,7 +1190,7 @@ struct Lane {
     }
 };
 
-int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double rtol, int32_t max_iter,
+int solve_batch(Prob* ctx, int64_t n, int64_t S, const int64_t* gidx, double rtol, int32_t max_iter,
                 double* lambda, int32_t* iters, double* relres, int32_t* status, hipStream_t st, int64_t& tot_it,
                 bool& bad, bool& brk) {
     int rc;
@@ -1412,7 +1430,7 @@ int solve_batch(sdmm_ctx* ctx, int64_t n, int64_t S, const int64_t* gidx, double
     return rc;
 }
 
-hipStream_t work_stream(sdmm_ctx* ctx, hipStream_t user) {
+hipStream_t work_stream(Prob* ctx, hipStream_t user) {
     // graph capture needs a stream other than the legacy null stream
     if (!ctx->opt_graph) return user;
     if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
@@ -1422,9 +1440,10 @@ hipStream_t work_stream(sdmm_ctx* ctx, hipStream_t user) {
 
 }  // namespace
 
-int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, double* lambda,
-                         int32_t* iters, double* relres, int32_t* status, void* stream) {
+int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, double rtol, int32_t max_iter,
+                         double* lambda, int32_t* iters, double* relres, int32_t* status, void* stream) {
     if (!ctx) return SDMM_EINVAL;
+    if (n > 0 && !gidx && y) return fail(ctx, SDMM_EINVAL, "off-grid points need the deterministic method");
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (n < 0 || (n > 0 && (!gidx || !lambda)) || !(rtol > 0) || max_iter < 1)
@@ -1457,7 +1476,7 @@ int sdmm_solve_interface(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double r
     return SDMM_OK;
 }
 
-int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,
+int impl_autotune(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,
                   int64_t* chunk_out) {
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
@@ -1524,9 +1543,10 @@ int sdmm_autotune(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, double rtol, in
     return SDMM_OK;
 }
 
-int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const double* lambda, const double* weights,
-                            void* stream) {
+int impl_accumulate_moments(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, const double* lambda,
+                            const double* weights, void* stream) {
     if (!ctx) return SDMM_EINVAL;
+    if (n > 0 && !gidx && y) return fail(ctx, SDMM_EINVAL, "off-grid points need the deterministic method");
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (n < 0 || (n > 0 && (!gidx || !lambda))) return fail(ctx, SDMM_EINVAL, "invalid arguments");
@@ -1588,7 +1608,7 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t n, const int64_t* gidx, const
     return SDMM_OK;
 }
 
-int sdmm_reset_moments(sdmm_ctx* ctx) {
+int impl_reset_moments(Prob* ctx) {
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
@@ -1601,10 +1621,11 @@ int sdmm_reset_moments(sdmm_ctx* ctx) {
     return SDMM_OK;
 }
 
-int sdmm_get_moments(sdmm_ctx* ctx, int field, double* mean, double* var) {
+int impl_get_moments(Prob* ctx, int field, double* mean, double* var, int64_t cap) {
     if (!ctx || !mean || !var) return fail(ctx, SDMM_EINVAL, "null argument");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (field < 0 || field > 4) return fail(ctx, SDMM_EINVAL, "bad field");
+    if (cap < ctx->field_size[field]) return fail(ctx, SDMM_EINVAL, "output capacity too small");
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipDeviceSynchronize());
     const int64_t n = ctx->field_size[field];
@@ -1649,7 +1670,7 @@ int sdmm_get_moments(sdmm_ctx* ctx, int field, double* mean, double* var) {
     return SDMM_OK;
 }
 
-int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out) {
+int impl_get_counters(Prob* ctx, sdmm_counters* out) {
     if (!ctx || !out) return fail(ctx, SDMM_EINVAL, "null argument");
     if (ctx->host_only) {
         *out = ctx->counters;
@@ -1673,5 +1694,166 @@ int sdmm_get_counters(sdmm_ctx* ctx, sdmm_counters* out) {
     *out = ctx->counters;
     return SDMM_OK;
 }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The C ABI: a context is a device, an optional allocator and a table of
+// problems; every call on a problem names its id.
+// ---------------------------------------------------------------------------
+struct sdmm_ctx {
+    int device = 0;
+    bool host_only = false;
+    bool have_alloc = false;
+    sdmm_alloc alloc{};
+    std::string err;
+    std::map<int64_t, std::unique_ptr<Prob, int (*)(Prob*)>> probs;
+    int64_t next_id = 1;
+};
+
+namespace {
+
+int ctx_fail(sdmm_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+// the problem `id` of c, or an error
+int find(sdmm_ctx* c, int64_t id, Prob** out) {
+    if (!c) return SDMM_EINVAL;
+    auto it = c->probs.find(id);
+    if (it == c->probs.end()) return ctx_fail(c, SDMM_EINVAL, "unknown problem id " + std::to_string(id));
+    *out = it->second.get();
+    return SDMM_OK;
+}
+
+// a call's status, with the problem's message copied to the context on failure
+int relay(sdmm_ctx* c, Prob* p, int rc) {
+    if (rc != SDMM_OK) c->err = p->err.empty() ? "error " + std::to_string(rc) : p->err;
+    return rc;
+}
+
+#define WITH_PROB(call)                          \
+    do {                                         \
+        Prob* p_ = nullptr;                      \
+        int rc_ = find(ctx, id, &p_);            \
+        if (rc_) return rc_;                     \
+        p_->err.clear();                         \
+        return relay(ctx, p_, call);             \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int sdmm_create(int device, const sdmm_alloc* alloc, sdmm_ctx** out) {
+    if (!out) return SDMM_EINVAL;
+    *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->release)) return SDMM_EINVAL;
+    if (device != -1) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SDMM_EINVAL;
+        if (hipSetDevice(device) != hipSuccess) return SDMM_EDEVICE;
+    }
+    sdmm_ctx* c = new (std::nothrow) sdmm_ctx();
+    if (!c) return SDMM_ENOMEM;
+    c->device = device;
+    c->host_only = device == -1;
+    if (alloc) {
+        c->alloc = *alloc;
+        c->have_alloc = true;
+    }
+    *out = c;
+    return SDMM_OK;
+}
+
+int sdmm_destroy(sdmm_ctx* ctx) {
+    if (!ctx) return SDMM_EINVAL;
+    ctx->probs.clear();
+    delete ctx;
+    return SDMM_OK;
+}
+
+const char* sdmm_last_error(const sdmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sdmm_set_problem(sdmm_ctx* ctx, const sdmm_problem* p, int64_t* problem_id) {
+    if (!ctx) return SDMM_EINVAL;
+    if (!p || !problem_id) return ctx_fail(ctx, SDMM_EINVAL, "null argument");
+    Prob* q = nullptr;
+    int rc = impl_create(ctx->device, ctx->have_alloc ? &ctx->alloc : nullptr, &q);
+    if (rc) return ctx_fail(ctx, rc, "could not create the problem's device state");
+    std::unique_ptr<Prob, int (*)(Prob*)> holder(q, impl_destroy);
+    rc = impl_set_problem(q, p);
+    if (rc) return relay(ctx, q, rc);
+    const int64_t id = ctx->next_id++;
+    ctx->probs.emplace(id, std::move(holder));
+    *problem_id = id;
+    return SDMM_OK;
+}
+
+int sdmm_release_problem(sdmm_ctx* ctx, int64_t id) {
+    Prob* p = nullptr;
+    int rc = find(ctx, id, &p);
+    if (rc) return rc;
+    ctx->probs.erase(id);
+    return SDMM_OK;
+}
+
+int sdmm_get_sizes(sdmm_ctx* ctx, int64_t id, sdmm_sizes* o) {
+    if (ctx && !o) return ctx_fail(ctx, SDMM_EINVAL, "null argument");
+    WITH_PROB(impl_get_sizes(p_, o));
+}
+
+int sdmm_get_index_maps(sdmm_ctx* ctx, int64_t id, int kind, int64_t* out, int64_t cap, int64_t* n_out) {
+    WITH_PROB(impl_get_index_map(p_, kind, out, cap, n_out));
+}
+
+int sdmm_get_collocation(sdmm_ctx* ctx, int64_t id, double* points, double* weights) {
+    WITH_PROB(impl_get_collocation(p_, points, weights));
+}
+
+int sdmm_get_kl(sdmm_ctx* ctx, int64_t id, int region, double* lam, int32_t* modes) {
+    WITH_PROB(impl_get_kl(p_, region, lam, modes));
+}
+
+int sdmm_build_flux_basis(sdmm_ctx* ctx, int64_t id, int method, int precision, void* stream) {
+    WITH_PROB(impl_build_flux_basis(p_, method, precision, stream));
+}
+
+int sdmm_get_basis(sdmm_ctx* ctx, int64_t id, int sub, int k, double* S, int64_t ld) {
+    WITH_PROB(impl_get_basis(p_, sub, k, S, ld));
+}
+
+int sdmm_get_interface_data(sdmm_ctx* ctx, int64_t id, double* g, double* G) {
+    WITH_PROB(impl_get_interface_data(p_, g, G));
+}
+
+int sdmm_solve_interface(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, const double* y, double rtol,
+                         int32_t max_iter, double* lambda, int32_t* iters, double* relres, int32_t* status,
+                         void* stream) {
+    WITH_PROB(impl_solve_interface(p_, n, gidx, y, rtol, max_iter, lambda, iters, relres, status, stream));
+}
+
+int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, const double* y,
+                            const double* lambda, const double* weights, void* stream) {
+    WITH_PROB(impl_accumulate_moments(p_, n, gidx, y, lambda, weights, stream));
+}
+
+int sdmm_get_moments(sdmm_ctx* ctx, int64_t id, int field, double* mean, double* var, int64_t cap) {
+    WITH_PROB(impl_get_moments(p_, field, mean, var, cap));
+}
+
+int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id) { WITH_PROB(impl_reset_moments(p_)); }
+
+int sdmm_set_option(sdmm_ctx* ctx, int64_t id, int option, int64_t value) {
+    WITH_PROB(impl_set_option(p_, option, value));
+}
+
+int sdmm_autotune(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter,
+                  void* stream, int64_t* chunk_out) {
+    WITH_PROB(impl_autotune(p_, n, gidx, rtol, max_iter, stream, chunk_out));
+}
+
+int sdmm_get_counters(sdmm_ctx* ctx, int64_t id, sdmm_counters* out) { WITH_PROB(impl_get_counters(p_, out)); }
 
 }  // extern "C"

@@ -518,9 +518,11 @@ static std::string build_stokes(Problem& P, int i, StokesHost& S) {
     for (char c : dir) nd_dir += c;
     S.floating = nd_dir == 0;
     S.uD.assign(S.nvel, 0.0);
+    // imposed outer velocity (inflow_x + inflow_shear y, inflow_y)
     for (int n = 0; n < nnx * nny; ++n)
         if (dir[n]) {
-            S.uD[2 * n] = in.inflow_x;
+            const double yn = s.y0 + 0.5 * hy * (n / nnx);
+            S.uD[2 * n] = in.inflow_x + in.inflow_shear * yn;
             S.uD[2 * n + 1] = in.inflow_y;
         }
     // kernel of the velocity form for floating subdomains

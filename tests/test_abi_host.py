@@ -34,9 +34,31 @@ def test_device_calls_fail_cleanly_without_gpu():
     sdmm = _lib()
     lib = sdmm.load()
     h = ctypes.c_void_p()
-    assert lib.sdmm_create(-1, ctypes.byref(h)) == 0
-    assert lib.sdmm_build_flux_basis(h, 0, None) == sdmm.ESTATE  # no problem yet
+    assert lib.sdmm_create(-1, None, ctypes.byref(h)) == 0
+    assert lib.sdmm_build_flux_basis(h, 1, 0, 0, None) == sdmm.EINVAL  # no problem 1 yet
     assert lib.sdmm_destroy(h) == 0
+    ctx = sdmm.Context(-1)
+    pid = ctx.set_problem(problem("cfg0"))
+    assert lib.sdmm_build_flux_basis(ctx.h, pid, 0, 0, None) == sdmm.ESTATE  # host-only context
+    ctx.close()
+
+
+def test_problem_ids():
+    """A context holds several problems; each call names one by its id."""
+    sdmm = _lib()
+    ctx = sdmm.Context(-1)
+    a = ctx.set_problem(problem("cfg0"))
+    b = ctx.set_problem(problem("cfg1"))
+    assert a != b
+    assert ctx.sizes(a)["M"] == 12 and ctx.sizes(b)["M"] == 288
+    assert ctx.sizes()["M"] == 288   # the newest problem is the default one
+    ctx.release_problem(b)
+    with pytest.raises(sdmm.SdmmError) as e:
+        ctx.sizes(b)
+    assert e.value.code == sdmm.EINVAL
+    assert ctx.sizes(a)["n_real"] == 16
+    assert ctx.lib.sdmm_release_problem(ctx.h, 12345) == sdmm.EINVAL
+    ctx.close()
 
 
 @pytest.mark.parametrize("name", ["cfg0", "cfg1", "cfg2", "cfg3"])
@@ -93,6 +115,7 @@ def test_options_are_validated():
     context is enough: options need no device)."""
     from paper_1802_06263_amd import sdmm
     ctx = sdmm.Context(-1)
+    pid = ctx.set_problem(problem("cfg0"))
     ctx.set_option("cg_chunk", 0)
     ctx.set_option("cg_chunk", 4096)
     ctx.set_option("cg_check", 1)
@@ -104,6 +127,6 @@ def test_options_are_validated():
     for name, bad in (("cg_lanes", 0), ("cg_lanes", 3), ("cg_check", 0), ("cg_check", 1025), ("cg_chunk", -1)):
         with pytest.raises(sdmm.SdmmError):
             ctx.set_option(name, bad)
-    rc = ctx.lib.sdmm_set_option(ctx.h, 99, 1)
+    rc = ctx.lib.sdmm_set_option(ctx.h, pid, 99, 1)
     assert rc == sdmm.EINVAL
     ctx.close()
