@@ -98,6 +98,7 @@ def test_feti_floating_stokes_parity():
         mg, vg = ctx.get_moments(f)
         mo, vo = mom[f]
         assert rel(mg, mo) < 1e-9, f
+        assert np.abs(vg - vo).max() < 1e-9 * max(np.abs(vo).max(), 1e-12 * np.abs(mo).max() ** 2), f
     ctx.close()
 
 
