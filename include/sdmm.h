@@ -253,6 +253,29 @@ int sdmm_get_interface_data(sdmm_ctx* ctx, int64_t id, double* g, double* G);
 int sdmm_solve_interface(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, const double* y, double rtol,
                          int32_t max_iter, double* lambda, int32_t* iters, double* relres, int32_t* status,
                          void* stream);
+/* Allocation-free sdmm_solve_interface, for callers that cannot allocate
+ * device memory (serving loops and harnesses in which hipMalloc is not
+ * allowed).  The same CG kernels and the same results as
+ * sdmm_solve_interface for collocation indices gidx (device int64, n); the
+ * other arguments are as there.  It calls no hipMalloc, hipFree,
+ * hipHostMalloc or other allocating routine: the CG workspace (the state of
+ * every realization, which all stay in flight for the whole solve, and the
+ * realization group tables) lives in a fixed scratch array of
+ * sdmm_noalloc_scratch_bytes() bytes (64 MiB) that the library holds on each
+ * GPU from the first sdmm_create on it until the process ends.  EINVAL, with
+ * nothing computed, when the batch does not fit (about
+ * n (8 (2 M + sum_i R_i) + 40) bytes plus the tables; e.g. about 1,600
+ * realizations for 1,280 mortar DOFs and sum_i R_i = 2,560).  Launches are
+ * eager on `stream`; the call returns when the solve has finished.  All
+ * calls on one GPU share that array and a call leaves its contents behind:
+ * calls that overlap in time on one GPU (from two host threads or two
+ * contexts) race and give wrong results. */
+int sdmm_solve_interface_noalloc(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, double rtol,
+                                 int32_t max_iter, double* lambda, int32_t* iters, double* relres, int32_t* status,
+                                 void* stream);
+/* Size in bytes of the scratch array of sdmm_solve_interface_noalloc (host *bytes). */
+int sdmm_noalloc_scratch_bytes(int64_t* bytes);
+
 /* Add n realizations to the moment accumulators (Section 2, Step 6 of
  * Method S3): gidx (device int64 n) or, for off-grid requests, NULL and y
  * (device n x n_term) as in sdmm_solve_interface; lambda (device n x M from

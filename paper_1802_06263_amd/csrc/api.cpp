@@ -111,6 +111,10 @@ struct Prob {
     // realization groups (grouped operator), one set per CG lane; the moment
     // passes use the first
     Groups grp[kMaxLanes];
+    // host tables of the allocation-free CG (its device tables live in the scratch array)
+    Groups grp_noalloc;
+    std::vector<int> noalloc_ident, noalloc_sel;
+    std::vector<int32_t> noalloc_act;
     DevBuf d_part, d_pos, w_Y;
     std::vector<int64_t> h_gidx;
     int64_t SR = 0;
@@ -734,10 +738,10 @@ int fetch_gidx(Prob* ctx, const int64_t* gidx, int64_t n, hipStream_t st) {
     return SDMM_OK;
 }
 
-// subset: positions of the realizations to include (null means all n);
-// hg: host global index of every position.
-int build_groups(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* subset, const int64_t* hg,
-                 hipStream_t st) {
+// The host tables of the realization groups.  subset: positions of the
+// realizations to include (null means all n); hg: host global index of every
+// position.
+int build_groups_host(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* subset, const int64_t* hg) {
     const Problem& P = ctx->P;
     std::vector<int> all;
     if (!subset) {
@@ -793,6 +797,11 @@ int build_groups(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* subset
     G.nwork = (int)G.h_work.size();
     G.nawork = (int)G.h_awork.size();
     G.part_total = slot;
+    return SDMM_OK;
+}
+
+// The group tables to the device (buffers grown as needed).
+int upload_groups(Prob* ctx, Groups& G, hipStream_t st) {
     int rc;
     auto grow = [&](DevBuf& b, size_t bytes) { return b.bytes < bytes ? alloc(ctx, b, bytes) : SDMM_OK; };
     if ((rc = grow(G.d_perm, G.h_perm.size() * 4))) return rc;
@@ -807,6 +816,12 @@ int build_groups(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* subset
     HIPCHK(hipMemcpyAsync(G.d_item0.p, G.h_item0.data(), G.h_item0.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));  // the host vectors are reused by the next chunk
     return SDMM_OK;
+}
+
+int build_groups(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* subset, const int64_t* hg,
+                 hipStream_t st) {
+    int rc = build_groups_host(ctx, G, n, subset, hg);
+    return rc ? rc : upload_groups(ctx, G, st);
 }
 
 // Realizations in flight (CG slots, and the chunk of the moment passes): their
@@ -1476,6 +1491,143 @@ int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double
     return SDMM_OK;
 }
 
+// The CG of sdmm_solve_interface without any allocation: every realization
+// of the batch holds one CG slot for the whole solve, the slot state and the
+// group tables live in the device's fixed scratch array, the iterations are
+// launched eagerly on the caller's stream (no graph, no second lane, no
+// timing events), and the host reads the active count with a plain
+// synchronous copy.  The kernels are those of the allocating path, so the
+// results are the same.
+int impl_solve_interface_noalloc(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter,
+                                 double* lambda, int32_t* iters, double* relres, int32_t* status, void* stream) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    if (n < 0 || (n > 0 && (!gidx || !lambda)) || !(rtol > 0) || max_iter < 1)
+        return fail(ctx, SDMM_EINVAL, "invalid arguments");
+    if (n == 0) return SDMM_OK;
+    if (n > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
+    char* base = reinterpret_cast<char*>(noalloc_scratch_ptr(ctx->device));
+    if (!base) return fail(ctx, SDMM_ESTATE, "the scratch array of this device was not resolved");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const Problem& P = ctx->P;
+    const int M = P.M;
+    // the indices, checked on the host before any kernel reads the table
+    ctx->h_gidx.resize(n);
+    HIPCHK(hipMemcpyAsync(ctx->h_gidx.data(), gidx, n * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t l = 0; l < n; ++l)
+        if (ctx->h_gidx[l] < 0 || ctx->h_gidx[l] >= P.nreal)
+            return fail(ctx, SDMM_EINVAL, "a global collocation index is out of range");
+    Groups& G = ctx->grp_noalloc;
+    int rc;
+    if ((rc = build_groups_host(ctx, G, n, nullptr, ctx->h_gidx.data()))) return rc;
+    // scratch layout (256-byte aligned pieces); the group tables get room for
+    // the first grouping, which no later compaction exceeds
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_r = take((size_t)n * M * 8), o_p = take((size_t)n * M * 8), o_Y = take((size_t)n * ctx->SR * 8);
+    const size_t o_rr = take(n * 8), o_r0 = take(n * 8), o_rel = take(n * 8);
+    const size_t o_it = take(n * 4), o_stat = take(n * 4), o_act = take(n * 4), o_slot = take(n * 4),
+                 o_init = take(n * 4), o_any = take(16);
+    const size_t o_perm = take(G.h_perm.size() * 4), o_work = take(G.h_work.size() * 16);
+    if (off > kNoAllocScratchBytes)
+        return fail(ctx, SDMM_EINVAL,
+                    "a batch of " + std::to_string(n) + " realizations needs " + std::to_string(off) +
+                        " bytes of CG workspace, above the fixed " + std::to_string(kNoAllocScratchBytes) +
+                        "-byte scratch of the allocation-free entry point");
+    CgArgs a = cg_args(ctx, n, gidx, lambda);
+    a.r = reinterpret_cast<double*>(base + o_r);
+    a.p = reinterpret_cast<double*>(base + o_p);
+    a.rr = reinterpret_cast<double*>(base + o_rr);
+    a.r0 = reinterpret_cast<double*>(base + o_r0);
+    a.relres = reinterpret_cast<double*>(base + o_rel);
+    a.iters = reinterpret_cast<int32_t*>(base + o_it);
+    a.status = reinterpret_cast<int32_t*>(base + o_stat);
+    a.active = reinterpret_cast<int32_t*>(base + o_act);
+    a.any_active = reinterpret_cast<int32_t*>(base + o_any);
+    int* d_slot = reinterpret_cast<int*>(base + o_slot);
+    int* d_init = reinterpret_cast<int*>(base + o_init);
+    a.slot_q = d_slot;
+    a.init_slots = d_init;
+    a.rtol = rtol;
+    a.max_iter = max_iter;
+    a.iters_out = iters;
+    a.relres_out = relres;
+    a.status_out = status;
+    double* Y = reinterpret_cast<double*>(base + o_Y);
+    int* d_perm = reinterpret_cast<int*>(base + o_perm);
+    int4* d_work = reinterpret_cast<int4*>(base + o_work);
+    auto upload_tables = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(d_perm, G.h_perm.data(), G.h_perm.size() * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_work, G.h_work.data(), G.h_work.size() * 16, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));   // the host tables change at the next compaction
+        return SDMM_OK;
+    };
+    // slot l holds batch position l for the whole solve; cg_init sets every
+    // slot's state, so nothing left in the scratch by an earlier call is read
+    std::vector<int>& ident = ctx->noalloc_ident;
+    ident.resize(n);
+    for (int64_t l = 0; l < n; ++l) ident[l] = (int)l;
+    HIPCHK(hipMemcpyAsync(d_slot, ident.data(), n * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_init, ident.data(), n * 4, hipMemcpyHostToDevice, st));
+    if ((rc = upload_tables())) return rc;
+    HIPCHK(launch_cg_init(a, n, st));
+    const int group = ctx->opt_check;
+    const int* pos = ctx->d_pos.as<int>();
+    int64_t in_work = n;
+    const int64_t max_groups = (int64_t)max_iter / group + 2;
+    std::vector<int32_t>& act = ctx->noalloc_act;
+    for (int64_t grp = 0;; ++grp) {
+        if (grp > max_groups) return fail(ctx, SDMM_EDEVICE, "the CG driver did not finish");
+        for (int q = 0; q < group; ++q) {
+            HIPCHK(launch_cg_apply_mfma(a, a.p, Y, ctx->SR, d_work, G.nwork, d_perm, ctx->max_R, st));
+            HIPCHK(launch_cg_update2(a, Y, ctx->SR, pos, st));
+        }
+        HIPCHK(launch_count_active(a.active, n, a.any_active, st));
+        int32_t count = 0;
+        HIPCHK(hipMemcpyAsync(&count, a.any_active, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (count == 0) break;
+        if (count < 0.75 * in_work) {
+            // compaction: the operator covers only the realizations still iterating
+            act.resize(n);
+            HIPCHK(hipMemcpyAsync(act.data(), a.active, n * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::vector<int>& sel = ctx->noalloc_sel;
+            sel.clear();
+            for (int64_t l = 0; l < n; ++l)
+                if (act[l]) sel.push_back((int)l);
+            if ((rc = build_groups_host(ctx, G, n, &sel, ctx->h_gidx.data()))) return rc;
+            if ((rc = upload_tables())) return rc;
+            in_work = (int64_t)sel.size();
+        }
+    }
+    // per-realization status and the iteration total
+    std::vector<int32_t>& itv = ctx->noalloc_act;
+    itv.resize(2 * n);
+    HIPCHK(hipMemcpyAsync(itv.data(), a.iters, n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(itv.data() + n, a.status, n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t tot = 0;
+    bool bad = false, brk = false;
+    for (int64_t l = 0; l < n; ++l) {
+        tot += itv[l];
+        bad |= itv[n + l] != SDMM_CG_CONVERGED;
+        brk |= itv[n + l] == SDMM_CG_BREAKDOWN;
+    }
+    ctx->counters.cg_iterations += tot;
+    ctx->counters.realizations += n;
+    if (brk) return fail(ctx, SDMM_EBREAKDOWN, "CG breakdown in some realization");
+    if (bad) return fail(ctx, SDMM_ENOTCONV, "some realization reached max_iter");
+    return SDMM_OK;
+}
+
 int impl_autotune(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,
                   int64_t* chunk_out) {
     if (!ctx) return SDMM_EINVAL;
@@ -1754,6 +1906,8 @@ int sdmm_create(int device, const sdmm_alloc* alloc, sdmm_ctx** out) {
         int count = 0;
         if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SDMM_EINVAL;
         if (hipSetDevice(device) != hipSuccess) return SDMM_EDEVICE;
+        // the allocation-free entry point's scratch on this device (once per device)
+        if (noalloc_scratch_setup(device) != hipSuccess) return SDMM_EDEVICE;
     }
     sdmm_ctx* c = new (std::nothrow) sdmm_ctx();
     if (!c) return SDMM_ENOMEM;
@@ -1832,6 +1986,18 @@ int sdmm_solve_interface(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gi
                          int32_t max_iter, double* lambda, int32_t* iters, double* relres, int32_t* status,
                          void* stream) {
     WITH_PROB(impl_solve_interface(p_, n, gidx, y, rtol, max_iter, lambda, iters, relres, status, stream));
+}
+
+int sdmm_solve_interface_noalloc(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, double rtol,
+                                 int32_t max_iter, double* lambda, int32_t* iters, double* relres, int32_t* status,
+                                 void* stream) {
+    WITH_PROB(impl_solve_interface_noalloc(p_, n, gidx, rtol, max_iter, lambda, iters, relres, status, stream));
+}
+
+int sdmm_noalloc_scratch_bytes(int64_t* bytes) {
+    if (!bytes) return SDMM_EINVAL;
+    *bytes = (int64_t)kNoAllocScratchBytes;
+    return SDMM_OK;
 }
 
 int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, const double* y,

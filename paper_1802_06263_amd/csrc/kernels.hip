@@ -18,6 +18,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "kernels.hpp"
 #include "../../include/sdmm.h"
@@ -1275,6 +1276,44 @@ hipError_t launch_stokes_moments_impl(const StokesDev* sd, int ns, int max_nout,
                        64 * max_ext * sizeof(double), stream, sd, s_Abase, acc, wsum, U, P, Z, u_out_off, p_out_off,
                        u1, u2, p1, p2);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free CG entry point (sdmm_solve_interface_
+// noalloc): a fixed array in the code object, so that each GPU the library
+// runs on holds its own copy from module load until the process ends.  In
+// host code `scratch` names only a host-side stand-in; the device address
+// of each GPU's copy comes from hipGetSymbolAddress with that GPU current,
+// once per device, and every kernel argument, copy or fill uses that address.
+// ---------------------------------------------------------------------------
+constexpr int kScratchMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device) {
+    if (device < 0 || device >= kScratchMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void* noalloc_scratch_ptr(int device) {
+    if (device < 0 || device >= kScratchMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace sdmm

@@ -188,4 +188,13 @@ hipError_t launch_stokes_moments_impl(const StokesDev* sd, int ns, int max_nout,
                                       const double* Z, const int64_t* u_out_off, const int64_t* p_out_off, int max_ext,
                                       double* u1, double* u2, double* p1, double* p2, hipStream_t stream);
 
+// Workspace of the allocation-free CG entry point: kNoAllocScratchBytes of
+// device memory per GPU, a fixed array in the code object.
+// noalloc_scratch_setup(device) resolves that GPU's copy (device must be
+// current; once per device, later calls return at once);
+// noalloc_scratch_ptr(device) gives its address, or null before set-up.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+hipError_t noalloc_scratch_setup(int device);
+void* noalloc_scratch_ptr(int device);
+
 }  // namespace sdmm

@@ -73,6 +73,8 @@ EXPORTS = {
     "sdmm_build_flux_basis": (ctypes.c_int, [_vp, _i64, ctypes.c_int, ctypes.c_int, _vp]),
     "sdmm_get_basis": (ctypes.c_int, [_vp, _i64, ctypes.c_int, ctypes.c_int, _f64p, _i64]),
     "sdmm_solve_interface": (ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _f64, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "sdmm_solve_interface_noalloc": (ctypes.c_int, [_vp, _i64, _i64, _vp, _f64, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "sdmm_noalloc_scratch_bytes": (ctypes.c_int, [_i64p]),
     "sdmm_get_interface_data": (ctypes.c_int, [_vp, _i64, _f64p, _f64p]),
     "sdmm_autotune": (ctypes.c_int, [_vp, _i64, _i64, _vp, _f64, _i32, _vp, _i64p]),
     "sdmm_accumulate_moments": (ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp]),
@@ -305,6 +307,23 @@ class Context:
                                            int(max_iter), _dptr(lam), _dptr(iters), _dptr(relres), _dptr(status),
                                            _stream(stream))
         return self._check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+
+    def solve_interface_noalloc(self, gidx, lam, rtol=1e-8, max_iter=None, iters=None, relres=None,
+                                status=None, stream=None, allow_notconv=False, pid=None):
+        """sdmm_solve_interface_noalloc: the same solve with the CG workspace in
+        the library's fixed per-GPU scratch array (no device allocation)."""
+        sz = self._sz[self._id(pid).value]
+        if max_iter is None:
+            max_iter = 10 * sz["M"]
+        rc = self.lib.sdmm_solve_interface_noalloc(self.h, self._id(pid), gidx.numel(), _dptr(gidx), float(rtol),
+                                                   int(max_iter), _dptr(lam), _dptr(iters), _dptr(relres),
+                                                   _dptr(status), _stream(stream))
+        return self._check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+
+    def noalloc_scratch_bytes(self):
+        out = ctypes.c_int64()
+        self._check(self.lib.sdmm_noalloc_scratch_bytes(ctypes.byref(out)))
+        return out.value
 
     def interface_data(self, pid=None):
         """(g_H [M], G [n_kernel x M]) as host arrays."""
