@@ -182,8 +182,14 @@ class Oracle:
         return fields, it, rel, ok
 
     def realization_S2(self, l, rtol=1e-8, max_iter=None):
+        return self.point_S2(self.grid.points[l], rtol=rtol, max_iter=max_iter)
+
+    def point_S2(self, y, rtol=1e-8, max_iter=None):
+        """Method S2 (Section 5.3) at one point y of the stochastic space, on
+        the collocation grid or not: every S_{H,i} is built from the local
+        problems of y's own KL field (eq. KLapprox), then CG on S_H."""
         L = self.L
-        y = self.grid.points[l]
+        y = np.asarray(y, dtype=np.float64)
         dls = {i: self.darcy_local(i, y) for i in self.darcy_ids}
         S_loc = [None] * L.nsub
         for i in self.darcy_ids:
