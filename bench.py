@@ -1,17 +1,26 @@
 """Benchmark of the stochastic multiscale flux basis hot path on one MI355X.
 
-One step = the whole hot path over one batch: the stochastic flux basis of
-every (Darcy subdomain, local KL realization) unit, the interface CG to
-rtol 1e-8 for every global collocation point, and the moment accumulation.
-The Stokes basis (deterministic, one local realization) is built once before
-the timed region and reported separately.
+One step = the whole hot path over one batch: the flux basis of every
+(Darcy subdomain, local KL realization) unit and of every Stokes subdomain,
+the interface CG to rtol 1e-8 for every global collocation point, the
+moment accumulation and the expansion of the moments to the fine fields.
+`value` is global realizations per second of that step, inputs resident in
+HBM; the rate with both bases resident (CG and moments only) is reported
+beside it.
 
 Both precisions run on identical inputs; `value` is the one named by
---precision.  Every CG kernel launch in the timed region is bracketed by HIP
-events on the stream it runs on; the dominant kernel's algorithmic bytes (or
-flops) per launch over its average launch duration give `roofline`.  The CPU
-baseline (the oracle, one thread, bounded sample) runs in a child process
-started before the GPU is touched.
+--precision.  Each precision block states the error of every field's mean
+and variance against the FP64 path at CG rtol 1e-11 (which the GPU tests tie
+to the oracle), and the number of realizations that did not converge (the
+bench exits non-zero if any did).  One CG iteration in every 16th
+convergence-check group is timed with HIP events on its stream while the
+other CG lane is idle, so each kernel's duration is its own; the dominant
+kernel's algorithmic flops (or bytes) per launch over its average launch
+duration give `roofline`, priced with the per-realization-iteration counts
+of the scope table (2 sum_i R_i^2 flops; 5 M 8 bytes for the whole CG).  A
+second workload block (`cfg3`: uneven subdomains, 54,273 realizations) runs
+one step per precision.  The CPU baseline (the oracle, one thread, bounded
+sample) runs in a child process started before the GPU is touched.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -52,6 +61,7 @@ def parse():
     ap.add_argument("--cg-chunk", type=int, default=0, help="realizations in flight in the CG (0: autotune)")
     ap.add_argument("--cg-lanes", type=int, default=0, choices=[0, 1, 2],
                     help="CG lanes (0: the library default, two lanes whose kernels overlap)")
+    ap.add_argument("--no-cfg3", action="store_true", help="skip the uneven-layout block")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -192,37 +202,83 @@ def start_cpu_baseline(args):
 # ---------------------------------------------------------------------------
 # GPU path
 
+FIELD_NAMES = ("lambda", "darcy_p", "darcy_u", "stokes_u", "stokes_p")
+PEAK_FP32_MFMA = 157.3e12
+TIME_EVERY = 16   # one timed CG iteration per 16 check groups of the first lane
 
-def gpu_step(ctx, prec, g, lam, rtol, torch):
-    ctx.build_flux_basis(prec)
-    ctx.solve_interface(g, lam, rtol=rtol, allow_notconv=True)
+
+def gpu_step(ctx, prec, g, lam, st, rtol, torch):
+    """One pass of the hot path; returns the number of realizations that did
+    not converge."""
+    ctx.build_flux_basis(prec)            # Darcy units and Stokes subdomains
+    ctx.solve_interface(g, lam, rtol=rtol, status=st, allow_notconv=True)
+    ctx.reset_moments()
     ctx.accumulate_moments(g, lam)
+    ctx.finalize_moments()                # moments expanded to the fine fields
     torch.cuda.synchronize()
+    return int((st != 0).sum().item())
 
 
 COUNTER_KEYS = ("cg_iterations", "realizations", "cg_launches", "cg_timed_launches", "cg_timed_active", "cg_timed_columns",
                 "ms_cg_apply", "ms_cg_update", "basis_solves_darcy", "units_built")
 
 
-def time_path(ctx, prec, g, lam, rtol, steps, warmup, torch):
+def time_path(ctx, prec, g, lam, st, rtol, steps, warmup, torch):
     for _ in range(warmup):
-        gpu_step(ctx, prec, g, lam, rtol, torch)
-    ctx.reset_moments()
+        gpu_step(ctx, prec, g, lam, st, rtol, torch)
     torch.cuda.synchronize()
     c0 = ctx.counters()
-    basis_ms, solve_ms = [], []
-    t0 = time.perf_counter()
+    ms = {"basis_darcy": [], "basis_stokes": [], "cg": [], "moments": [], "step": []}
+    bad = 0
     for s in range(steps):
-        gpu_step(ctx, prec, g, lam, rtol, torch)
+        t0 = time.perf_counter()
+        bad += gpu_step(ctx, prec, g, lam, st, rtol, torch)
+        ms["step"].append((time.perf_counter() - t0) * 1e3)
         c = ctx.counters()
-        basis_ms.append(c["ms_basis_darcy"])
-        solve_ms.append(c["ms_solve"])
-        log("%s step %d: basis %.2f ms, CG %.1f ms" % (prec, s, basis_ms[-1], solve_ms[-1]))
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+        ms["basis_darcy"].append(c["ms_basis_darcy"])
+        ms["basis_stokes"].append(c["ms_basis_stokes"])
+        ms["cg"].append(c["ms_solve"])
+        ms["moments"].append(c["ms_moments"])
+        log("%s step %d: %.1f ms (Darcy basis %.2f, Stokes basis %.1f, CG %.1f, moments %.2f)"
+            % (prec, s, ms["step"][-1], ms["basis_darcy"][-1], ms["basis_stokes"][-1], ms["cg"][-1],
+               ms["moments"][-1]))
     c1 = ctx.counters()
     d = {k: c1[k] - c0[k] for k in COUNTER_KEYS}
-    return dt, sum(basis_ms) / steps, sum(solve_ms) / steps, d
+    return {k: sum(v) / steps for k, v in ms.items()}, d, bad
+
+
+def field_moments(ctx):
+    return {f: ctx.get_moments(f) for f in FIELD_NAMES}
+
+
+def moment_errors(mom, ref):
+    """Per field: largest error of the mean relative to the largest |mean|, and
+    of the variance relative to the largest |variance|."""
+    out = {}
+    for f in FIELD_NAMES:
+        m, v = mom[f]
+        mr, vr = ref[f]
+        sm = max(abs(mr).max(), 1e-300)
+        sv = max(abs(vr).max(), 1e-12 * sm * sm)
+        out[f] = {"mean": float(abs(m - mr).max() / sm), "var": float(abs(v - vr).max() / sv)}
+    return out
+
+
+REF_RTOL = 1e-11
+
+
+def reference_moments(ctx, g, lam, st, torch):
+    """The FP64 path at CG rtol 1e-11 (iteration limit 50 M) over the whole
+    grid: three orders of magnitude below the timed solves' stopping error."""
+    ctx.build_flux_basis("fp64")
+    ctx.solve_interface(g, lam, rtol=REF_RTOL, max_iter=50 * ctx.sizes()["M"], status=st, allow_notconv=True)
+    ctx.reset_moments()
+    ctx.accumulate_moments(g, lam)
+    ctx.finalize_moments()
+    torch.cuda.synchronize()
+    if int((st != 0).sum().item()):
+        raise RuntimeError("the reference solve did not converge everywhere")
+    return field_moments(ctx)
 
 
 def kernel_source_hash(kernel):
@@ -264,13 +320,13 @@ def read_traffic(kernel, workload):
         return None
 
 
-def cg_whole(sum_R, sum_R2, M, real_iters, ms_cg):
-    """The whole CG of a step against both peaks: the product's and the
-    update's algorithmic bytes and the product's flops over every
-    realization-iteration, divided by the CG wall time.  The library runs two
-    lanes whose kernels overlap on the device, so this is the figure that
-    per-launch durations (which include the co-running kernel) understate."""
-    b = 8.0 * (M + sum_R) + 8.0 * (sum_R + 6 * M)
+def cg_whole(M, sum_R2, real_iters, ms_cg):
+    """The whole CG of a step against both peaks, priced with the scope
+    table's counts per realization-iteration: 5 M 8 bytes (the CG vectors
+    streamed once) and 2 sum_i R_i^2 flops (the basis products), over the CG
+    wall time.  The two lanes' kernels overlap on the device, so this is the
+    step-level figure; the per-kernel entries time each kernel alone."""
+    b = 5.0 * M * 8
     f = 2.0 * sum_R2
     t = ms_cg * 1e-3
     return {"realization_iterations": real_iters, "bytes_per_unit": b, "flops_per_unit": f,
@@ -278,62 +334,94 @@ def cg_whole(sum_R, sum_R2, M, real_iters, ms_cg):
             "tflops": f * real_iters / t / 1e12, "frac_fp64_mfma": f * real_iters / t / PEAK_FP64}
 
 
-def kernel_rooflines(sz, sum_R, sum_R2, d, basis_ms, prec, workload):
+def kernel_rooflines(sz, M, sum_R2, d, ms, prec, workload):
     """Per-kernel roofline entries.  The algorithmic unit of the CG kernels is
     one realization-iteration (one CG iteration of one realization still
     iterating); the library times one (product, update) launch pair per
-    convergence-check group and counts the realizations active in it.  The
-    unit of the basis kernel is one full build (a single launch)."""
-    M = sz["M"]
+    timed check group, with the other lane idle, and counts the realizations
+    active in it.  The product is priced by its 2 sum_i R_i^2 flops (FP64
+    MFMA; 2 M 8 bytes of vectors, above the ridge), the update by the 7 M 8
+    bytes an unfused update streams (the operator result, p, r and lambda
+    read; lambda, r and p written).  The basis builds are one unit per step."""
     out = {}
     nl = d["cg_timed_launches"]
     if nl:
         act = d["cg_timed_active"] / nl
-        # CG update: reads the subdomain-local product Y (sum R_i), p, r and
-        # lambda (M each); writes lambda, r and p (M each)
-        b_upd = 8.0 * (sum_R + 6 * M)
+        b_upd = 7.0 * M * 8
         avg = d["ms_cg_update"] * 1e-3 / nl
-        per_launch = b_upd * act
-        out["cg_update"] = {"kernel": "cg_update2_kernel", "bound": "hbm", "achieved": per_launch / avg / 1e9,
-                            "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": per_launch / avg / PEAK_HBM,
+        out["cg_update"] = {"kernel": "cg_update2_kernel", "bound": "hbm", "achieved": b_upd * act / avg / 1e9,
+                            "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": b_upd * act / avg / PEAK_HBM,
                             "avg_launch_us": avg * 1e6, "timed_launches": nl, "active_per_launch": act,
-                            "bytes_per_unit": b_upd, "algorithmic_bytes_per_launch": per_launch,
+                            "bytes_per_unit": b_upd, "algorithmic_bytes_per_launch": b_upd * act,
                             "sampled_ms": d["ms_cg_update"]}
         t = read_traffic("cg_update2", workload)
         out["cg_update"]["traffic"] = t * act if t is not None else None
-        # CG product: 2 sum R_i^2 flops; reads p (global layout, M) and writes
-        # Y in the subdomain-local layout (sum R_i)
-        # the bound is whichever peak the launch's algorithmic work takes longer at
         f_app = 2.0 * sum_R2
-        b_app = 8.0 * (M + sum_R)
+        b_app = 2.0 * M * 8
         avg = d["ms_cg_apply"] * 1e-3 / nl
-        if f_app / PEAK_FP64 >= b_app / PEAK_HBM:
-            roof = {"bound": "mfma", "achieved": f_app * act / avg / 1e12, "peak": PEAK_FP64 / 1e12,
-                    "unit": "TFLOP/s", "frac": f_app * act / avg / PEAK_FP64}
-        else:
-            roof = {"bound": "hbm", "achieved": b_app * act / avg / 1e9, "peak": PEAK_HBM / 1e9,
-                    "unit": "GB/s", "frac": b_app * act / avg / PEAK_HBM}
-        out["cg_apply"] = {"kernel": "cg_apply_mfma_kernel", **roof,
-                           "gbps": b_app * act / avg / 1e9, "frac_hbm": b_app * act / avg / PEAK_HBM,
-                           "tflops": f_app * act / avg / 1e12,
-                           "frac_fp64_mfma": f_app * act / avg / PEAK_FP64, "avg_launch_us": avg * 1e6,
-                           "timed_launches": nl, "active_per_launch": act,
-                           "columns_per_launch": d["cg_timed_columns"] / nl,
-                           "bytes_per_unit": b_app, "flops_per_unit": f_app,
-                           "algorithmic_bytes_per_launch": b_app * act,
-                           "sampled_ms": d["ms_cg_apply"]}
+        out["cg_apply"] = {"kernel": "cg_apply_mfma_kernel", "bound": "mfma", "achieved": f_app * act / avg / 1e12,
+                           "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": f_app * act / avg / PEAK_FP64,
+                           "avg_launch_us": avg * 1e6, "timed_launches": nl, "active_per_launch": act,
+                           "columns_per_launch": d["cg_timed_columns"] / nl, "flops_per_unit": f_app,
+                           "bytes_per_unit": b_app, "gbps": b_app * act / avg / 1e9,
+                           "frac_hbm": b_app * act / avg / PEAK_HBM, "sampled_ms": d["ms_cg_apply"]}
         t = read_traffic("cg_apply_mfma", workload)
         out["cg_apply"]["traffic"] = t * act if t is not None else None
-    # Darcy basis build: banded factor + forward/backward flops; factor,
-    # diagonal-block inverse and solve launches per shape class, timed together
-    # with HIP events.  Both precisions compute on FP64 MFMA (mixed stores the
-    # factor in FP32), so the peak is the FP64 MFMA one.
-    ach = sz["darcy_flops"] / (basis_ms * 1e-3)
+    # Darcy basis build: banded factor + forward/backward flops of every unit;
+    # the mixed path computes them on FP32 MFMA, the FP64 path on FP64 MFMA
+    peak = PEAK_FP32_MFMA if prec == "mixed" else PEAK_FP64
+    ach = sz["darcy_flops"] / (ms["basis_darcy"] * 1e-3)
     out["darcy_basis"] = {"kernel": "darcy_factor_kernel + darcy_inverse_kernel + darcy_solve_%s_kernel" % prec,
-                          "bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                          "frac": ach / PEAK_FP64, "avg_launch_us": basis_ms * 1e3, "launches": 3,
+                          "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                          "frac": ach / peak, "avg_launch_us": ms["basis_darcy"] * 1e3,
                           "algorithmic_flops_per_launch": sz["darcy_flops"], "traffic": None}
     return out
+
+
+def run_workload(ctx, args, workload, precs, steps, warmup, chunk, torch, np):
+    """Both precisions on one workload: timing, rooflines, moment errors."""
+    sz = ctx.sizes()
+    n, M = sz["n_real"], sz["M"]
+    R = np.diff(ctx.index_map("sub_ptr"))
+    sum_R2 = int((R.astype(np.int64) ** 2).sum())
+    g = torch.arange(n, dtype=torch.int64, device="cuda")
+    lam = torch.zeros((n, M), dtype=torch.float64, device="cuda")
+    st = torch.zeros(n, dtype=torch.int32, device="cuda")
+    if chunk > 0:
+        ctx.set_option("cg_chunk", chunk)
+    else:
+        ctx.build_flux_basis("fp64")
+        chunk = ctx.autotune(g, rtol=args.rtol)
+        log("%s: autotuned CG slots: %d realizations in flight" % (workload, chunk))
+    ctx.set_option("stokes_rebuild", 1)
+    ctx.set_option("kernel_timing", TIME_EVERY)
+    res, kern = {}, {}
+    for prec in precs:
+        ms, d, bad = time_path(ctx, prec, g, lam, st, args.rtol, steps, warmup, torch)
+        kern[prec] = kernel_rooflines(sz, M, sum_R2, d, ms, prec, workload)
+        mom = field_moments(ctx)
+        dt = ms["step"] * 1e-3
+        res[prec] = {"ms_per_step": ms["step"], "realizations_per_s": n / dt,
+                     "realizations_per_s_basis_resident": n / (dt - 1e-3 * (ms["basis_darcy"] + ms["basis_stokes"])),
+                     "ms_basis_darcy": ms["basis_darcy"], "ms_basis_stokes": ms["basis_stokes"], "ms_cg": ms["cg"],
+                     "ms_moments_expand": ms["moments"],
+                     "basis_builds_per_s": sz["n_units"] / (ms["basis_darcy"] * 1e-3),
+                     "local_solves_per_s": d["basis_solves_darcy"] / (steps * ms["basis_darcy"] * 1e-3),
+                     "cg_iterations_mean": d["cg_iterations"] / max(1, d["realizations"]),
+                     "not_converged": bad,
+                     "refinement_group_steps_per_unit": (ctx.counters()["refinement_steps"] / sz["n_units"]
+                                                         if prec == "mixed" else 0.0),
+                     "max_refine_residual": ctx.counters()["max_refine_residual"] if prec == "mixed" else 0.0,
+                     "cg_launches_per_step": d["cg_launches"] / steps,
+                     "cg_whole": cg_whole(M, sum_R2, d["cg_iterations"] / steps, ms["cg"]),
+                     "basis_roofline": {k: kern[prec]["darcy_basis"][k] for k in ("bound", "achieved", "peak",
+                                                                                  "unit", "frac")},
+                     "_mom": mom}
+    ref = reference_moments(ctx, g, lam, st, torch)
+    for prec in precs:
+        res[prec]["moment_error_vs_fp64_rtol_1e-11"] = moment_errors(res[prec].pop("_mom"), ref)
+    info = {"n_real": n, "M": M, "basis_units": sz["n_units"], "cg_chunk": chunk}
+    return res, kern, info
 
 
 def main():
@@ -352,74 +440,55 @@ def main():
     from paper_1802_06263_amd import sdmm
     from workloads import problem
 
-    prob = problem(args.workload)
-    ctx = sdmm.Context(0)
-    ctx.set_problem(prob)
-    sz = ctx.sizes()
-    n, M = sz["n_real"], sz["M"]
-    R = np.diff(ctx.index_map("sub_ptr"))
-    sum_R, sum_R2 = int(R.sum()), int((R.astype(np.int64) ** 2).sum())
-    log("%s: %d realizations, M = %d, %d basis units" % (args.workload, n, M, sz["n_units"]))
     if args.copy_probe:
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)   # an elementwise kernel: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
         del src, dst
-    ctx.build_flux_basis("fp64")
-    torch.cuda.synchronize()
-    stokes_ms = ctx.counters()["ms_basis_stokes"]
-    g = torch.arange(n, dtype=torch.int64, device="cuda")
-    lam = torch.zeros((n, M), dtype=torch.float64, device="cuda")
+    other = "fp64" if args.precision == "mixed" else "mixed"
+    precs = (args.precision,) if args.single else (other, args.precision)
+    ctx = sdmm.Context(0)
+    ctx.set_problem(problem(args.workload))
     if args.cg_lanes:
         ctx.set_option("cg_lanes", args.cg_lanes)
-    if args.cg_chunk > 0:
-        chunk = args.cg_chunk
-        ctx.set_option("cg_chunk", chunk)
-    else:
-        chunk = ctx.autotune(g, rtol=args.rtol)
-        log("autotuned CG slots: %d realizations in flight" % chunk)
-    ctx.set_option("kernel_timing", 1)
-    other = "fp64" if args.precision == "mixed" else "mixed"
-    res, kern = {}, {}
-    for prec in ((args.precision,) if args.single else (other, args.precision)):
-        dt, bms, sms, d = time_path(ctx, prec, g, lam, args.rtol, args.steps, args.warmup, torch)
-        kern[prec] = kernel_rooflines(sz, sum_R, sum_R2, d, bms, prec, args.workload)
-        res[prec] = {"ms_per_step": dt * 1e3, "realizations_per_s": n / dt,
-                     "realizations_per_s_basis_resident": n / (dt - bms * 1e-3), "ms_basis": bms, "ms_cg": sms,
-                     "basis_builds_per_s": sz["n_units"] / (bms * 1e-3),
-                     "local_solves_per_s": d["basis_solves_darcy"] / (args.steps * bms * 1e-3),
-                     "cg_iterations_mean": d["cg_iterations"] / max(1, d["realizations"]),
-                     "refinement_group_steps_per_unit": (ctx.counters()["refinement_steps"] / sz["n_units"]
-                                                   if prec == "mixed" else 0.0),
-                     "cg_launches_per_step": d["cg_launches"] / args.steps,
-                     "cg_whole": cg_whole(sum_R, sum_R2, M, d["cg_iterations"] / args.steps, sms)}
+    log("%s: %d realizations, M = %d, %d basis units" % (args.workload, ctx.sizes()["n_real"], ctx.sizes()["M"],
+                                                         ctx.sizes()["n_units"]))
+    res, kern, info = run_workload(ctx, args, args.workload, precs, args.steps, args.warmup, args.cg_chunk, torch,
+                                   np)
+    ctx.close()
     main_r = res[args.precision]
     kmain = kern[args.precision]
-    # dominant kernel: largest share of the step (sampled CG launches scaled
-    # to every iteration of the step)
-    share = {k: v["avg_launch_us"] for k, v in kmain.items()}   # the basis: one build per step
+    # dominant kernel: largest estimated share of the step (the sampled CG
+    # launches scaled to every launch of the step; a basis build is one launch)
+    share = {"darcy_basis": kmain["darcy_basis"]["avg_launch_us"]}
     for k in ("cg_update", "cg_apply"):
         if k in kmain:
-            share[k] = kmain[k]["avg_launch_us"] * res[args.precision]["cg_launches_per_step"]
+            share[k] = kmain[k]["avg_launch_us"] * main_r["cg_launches_per_step"]
     for k in share:
         kmain[k]["est_ms_per_step"] = share[k] * 1e-3
     dom = max(share, key=share.get)
     r = kmain[dom]
     roof = {"kernel": r["kernel"], "bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
-            "unit": r["unit"], "frac": r["frac"], "traffic": r["traffic"],
-            "avg_launch_us": r["avg_launch_us"]}
+            "unit": r["unit"], "frac": r["frac"], "traffic": r["traffic"], "avg_launch_us": r["avg_launch_us"]}
     out = {"metric": METRIC, "value": main_r["realizations_per_s"], "unit": "realizations/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_r["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
-           "config": {"workload": args.workload, "n_real": n, "M": M, "basis_units": sz["n_units"],
-                      "precision": args.precision, "rtol": args.rtol, "cg_chunk": chunk,
+           "config": {"workload": args.workload, **info, "precision": args.precision, "rtol": args.rtol,
                       "cg_lanes": args.cg_lanes or 2},
            "basis_builds_per_s": main_r["basis_builds_per_s"],
-           "fp64": res.get("fp64"), "mixed": res.get("mixed"), "stokes_basis_ms": stokes_ms,
-           "roofline": roof, "kernels": kmain}
-    ctx.close()
+           "fp64": res.get("fp64"), "mixed": res.get("mixed"), "roofline": roof, "kernels": kmain}
+    if not args.no_cfg3 and args.workload != "cfg3":
+        ctx = sdmm.Context(0)
+        ctx.set_problem(problem("cfg3"))
+        log("cfg3: %d realizations, M = %d, %d basis units" % (ctx.sizes()["n_real"], ctx.sizes()["M"],
+                                                               ctx.sizes()["n_units"]))
+        r3, k3, i3 = run_workload(ctx, args, "cfg3", precs, 1, 1, CFG3_CHUNK, torch, np)
+        ctx.close()
+        out["cfg3"] = {"config": i3, "fp64": r3.get("fp64"), "mixed": r3.get("mixed"),
+                       "kernels": k3[args.precision]}
+    bad = sum(res[p]["not_converged"] for p in precs)
     if child is not None:
         log("waiting for the CPU baseline")
         so, _ = child.communicate()
@@ -429,6 +498,12 @@ def main():
             log("CPU baseline failed (exit %d)" % child.returncode)
             out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+    if bad:
+        log("%d realizations did not converge" % bad)
+        sys.exit(1)
+
+
+CFG3_CHUNK = 5120   # CG slots on the uneven layout (what the autotuner picks there)
 
 
 if __name__ == "__main__":

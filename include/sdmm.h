@@ -163,14 +163,16 @@ typedef struct {
     double ms_solve;              /* last solve_interface                       */
     double max_refine_residual;   /* largest relative residual after refinement */
     /* per-kernel timing of the CG iterations while SDMM_OPT_KERNEL_TIMING is
-     * on: one iteration of every fourth convergence-check group is bracketed
-     * by HIP events on the stream the kernels run on; sums over all solves */
+     * on: one iteration of every n-th convergence-check group is bracketed
+     * by HIP events on the stream the kernels run on, with the other CG lane
+     * idle meanwhile; sums over all solves */
     int64_t cg_launches;          /* product launches (= update launches), all   */
     int64_t cg_timed_launches;    /* sampled (product, update) launch pairs     */
     int64_t cg_timed_active;      /* realizations still iterating in them        */
     int64_t cg_timed_columns;     /* realization columns the products covered    */
     double ms_cg_apply;           /* summed duration of the sampled products     */
     double ms_cg_update;          /* summed duration of the sampled updates      */
+    double ms_moments;            /* last expansion of the moments to the fields */
 } sdmm_counters;
 
 /* Create a context on HIP device `device`.  Ownership of *out passes to the
@@ -276,6 +278,40 @@ int sdmm_solve_interface_noalloc(sdmm_ctx* ctx, int64_t id, int64_t n, const int
 /* Size in bytes of the scratch array of sdmm_solve_interface_noalloc (host *bytes). */
 int sdmm_noalloc_scratch_bytes(int64_t* bytes);
 
+/* CG streams: continuous batching of the collocation loop (Section 5.4,
+ * main loop, Steps 3-5).  A stream keeps `slots` CG slots on the device;
+ * realizations of any number of requests occupy them as they free up, so a
+ * request submitted while others are iterating starts at the next
+ * convergence check instead of waiting for a batch to finish.  Results are
+ * those of sdmm_solve_interface (fixed-order reductions: a realization's
+ * answer does not depend on what shares the slots with it).
+ *   open    slots (1 .. 2^24), rtol and max_iter as in sdmm_solve_interface,
+ *           stream: the hipStream_t every later call of the stream uses;
+ *           *sid (host) receives the stream id.  Allocates the stream's
+ *           workspace (about slots (8 (3 M + sum_i R_i) + 56) bytes).
+ *   submit  n collocation indices gidx (host int64, checked) and the
+ *           request's outputs (device): lambda (n x M), iters / relres /
+ *           status (n each, may be NULL); *ticket (host) names the request.
+ *           Nothing runs until sdmm_stream_run.
+ *   run     up to max_groups convergence-check groups (SDMM_OPT_CG_CHECK
+ *           iterations each): at every check, finished realizations leave
+ *           their slots (their outputs are copied to their requests) and
+ *           queued ones start in the freed slots.  done (host, capacity cap)
+ *           receives the tickets of the requests completed during the call,
+ *           *n_done their number, *in_flight (may be NULL) the realizations
+ *           still iterating or queued.  Returns when max_groups groups ran
+ *           or nothing is left; the outputs of the completed requests are
+ *           then valid.
+ *   close   waits for the stream and releases it.
+ * EINVAL for unknown ids or bad arguments. */
+int sdmm_stream_open(sdmm_ctx* ctx, int64_t id, int64_t slots, double rtol, int32_t max_iter, void* stream,
+                     int64_t* sid);
+int sdmm_stream_submit(sdmm_ctx* ctx, int64_t id, int64_t sid, int64_t n, const int64_t* gidx, double* lambda,
+                       int32_t* iters, double* relres, int32_t* status, int64_t* ticket);
+int sdmm_stream_run(sdmm_ctx* ctx, int64_t id, int64_t sid, int32_t max_groups, int64_t* done, int64_t cap,
+                    int64_t* n_done, int64_t* in_flight);
+int sdmm_stream_close(sdmm_ctx* ctx, int64_t id, int64_t sid);
+
 /* Add n realizations to the moment accumulators (Section 2, Step 6 of
  * Method S3): gidx (device int64 n) or, for off-grid requests, NULL and y
  * (device n x n_term) as in sdmm_solve_interface; lambda (device n x M from
@@ -286,6 +322,12 @@ int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t*
 /* Mean and variance (host arrays of cap >= field_size[field] entries) of one
  * field; EINVAL if cap is too small. */
 int sdmm_get_moments(sdmm_ctx* ctx, int64_t id, int field, double* mean, double* var, int64_t cap);
+/* Expand the accumulated moments to the fine Darcy and Stokes fields on the
+ * device (Section 2: E[u] and E[u^2] of every velocity and pressure DOF from
+ * the accumulated mortar coefficients and the stored responses), enqueued on
+ * `stream`; sdmm_get_moments then only copies.  sdmm_get_moments expands by
+ * itself when the accumulators changed since the last expansion. */
+int sdmm_finalize_moments(sdmm_ctx* ctx, int64_t id, void* stream);
 int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
 
 /* Tuning knobs of the batched CG of one problem (used by the autotuner):
@@ -300,16 +342,22 @@ int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
  *                      two lanes with their own streams, so that one lane's
  *                      operator product overlaps the other's update on the
  *                      device; 1 = one lane
- *   SDMM_OPT_KERNEL_TIMING 1 = time one iteration of every fourth check group
- *                      with HIP events and sum the durations into the
- *                      counters (those groups run eagerly, the others replay
- *                      the captured graph)
+ *   SDMM_OPT_KERNEL_TIMING n > 0 = time one iteration of every n-th check
+ *                      group of the first lane with HIP events and sum the
+ *                      durations into the counters; the second lane is
+ *                      drained first and waits for the timed pair, so the
+ *                      timed kernels run alone (those groups run eagerly,
+ *                      the others replay the captured graph); 0 = off
+ *   SDMM_OPT_STOKES_REBUILD 1 = every sdmm_build_flux_basis rebuilds the
+ *                      Stokes basis too (0, the default: built once, since
+ *                      it does not depend on the realization)
  * Results do not depend on any of them. */
 #define SDMM_OPT_CG_CHUNK 0
 #define SDMM_OPT_CG_CHECK 1
 #define SDMM_OPT_CG_GRAPH 2
 #define SDMM_OPT_KERNEL_TIMING 3
 #define SDMM_OPT_CG_LANES 4
+#define SDMM_OPT_STOKES_REBUILD 5
 int sdmm_set_option(sdmm_ctx* ctx, int64_t id, int option, int64_t value);
 /* Autotuner of the batched CG: runs the first min(n, 16384) realizations of
  * gidx (device int64, n) through the whole CG (rtol, max_iter as in

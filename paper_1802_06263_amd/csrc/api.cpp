@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <string>
@@ -56,6 +57,67 @@ struct Groups {
 
 constexpr int kMaxLanes = 2;   // CG lanes: halves of the slots on their own streams
 
+// A CG stream (continuous batching): a fixed number of CG slots that
+// realizations of any number of submitted requests occupy as they free up.
+// Slot l keeps its lambda, iteration count, residual and status at row l of
+// the stream's own arrays; finished realizations are copied to their
+// request's buffers when they leave their slot.
+struct CgStream {
+    int64_t S = 0;
+    double rtol = 1e-8;
+    int32_t max_iter = 1;
+    hipStream_t st = nullptr;
+    DevBuf r, p, Y, rr, r0, relres, iters, status, active, any, slot_q, init, lam;
+    DevBuf g_slot, g_lam, g_it, g_rel, g_st;   // gather lists of finished realizations
+    Groups G;
+    std::vector<int> init_h, sel;
+    std::vector<int64_t> slot_g, slot_ticket;
+    std::vector<int> slot_row;
+    std::vector<int32_t> act;
+    struct Pending {
+        int64_t ticket, gidx;
+        int row;
+    };
+    std::deque<Pending> queue;
+    struct Req {
+        double* lam;
+        int32_t* it;
+        double* rel;
+        int32_t* st;
+        int64_t remaining;
+    };
+    std::map<int64_t, Req> reqs;
+    int64_t next_ticket = 1, in_work = 0, occupied = 0, groups_run = 0;
+};
+
+
+// Which flux bases the interface operator and the moments use: by default
+// the stochastic basis (Method S3: every local realization of the
+// collocation grid, pairs (i, k) and the global->local table); a
+// deterministic basis built for a batch (Method S2) gives each realization
+// of the batch its own local index in every region.
+struct BasisView {
+    std::vector<int> pair_sub, pair_k;   // (subdomain, local index) pairs
+    std::vector<int32_t> g2l;            // rows by batch position, n_region columns
+    std::vector<int> nlocal;             // local indices per region
+    DevBuf d_pair_sub, d_pair_k, d_sub_Sbase, d_sub_Abase;
+    double* S = nullptr;                 // the basis blocks
+};
+
+// Method S2 state: the batch of the last deterministic solve and its bases.
+struct DetBatch {
+    int64_t n = 0, cap = 0;
+    std::vector<double> y;               // n x n_term points of the batch
+    std::vector<UnitDev> units;
+    std::vector<int> chunk_start;        // unit ranges built per launch (scratch reused)
+    DevBuf d_units, d_order, d_xi, d_pos, d_S, d_X, d_E, d_W32, d_L, d_L32, d_I, d_I32, d_T, d_refine;
+    DevBuf d_unit_of_dk, d_dnlocal, d_dAbase, d_sum, d_tmp;
+    int64_t S_total = 0, X_total = 0, L_chunk = 0, T_chunk = 0, I_chunk = 0, A_base = 0;
+    int precision = SDMM_PREC_FP64;
+    bool valid = false;
+    BasisView view;
+};
+
 // State of one problem of a context (every call names its problem id).
 struct Prob {
     int device = 0;
@@ -96,7 +158,7 @@ struct Prob {
         d_xi, d_supp_ptr, d_supp_e, d_supp_v, d_me_cell;
     DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_E, d_refine, d_I, d_I32;
     DevBuf d_sdev, d_tiles, d_rhs, d_U, d_P, d_bmap, d_Z, d_q_ptr, d_q_col, d_q_val, d_uD, d_uD_off, d_tr_sub, d_tr_r,
-        d_tr_c, d_tr_v, d_cptr, d_ccol, d_cval, d_rhs0, d_res;
+        d_tr_c, d_tr_v, d_rhs0, d_res, d_tiles0, d_linv, d_stmp;
     DevBuf d_g, d_G, d_GtGinv, d_Grow, d_Gval;
     int nGrow = 0;
     DevBuf d_sub_R, d_sub_dof_ptr, d_sub_dofs, d_sub_region, d_sub_Sbase, d_g2l, d_weights;
@@ -122,15 +184,25 @@ struct Prob {
     int64_t opt_chunk = 0;   // realizations per CG chunk, 0 = from the cache budget
     int opt_check = 64;      // iterations between convergence checks
     int opt_graph = 1;       // capture the iteration group in a HIP graph
-    int opt_ktime = 0;       // events around every CG kernel launch
+    int opt_ktime = 0;       // 0: no kernel timing; n: time one iteration of every n-th check group
+    int opt_stokes_rebuild = 0;   // rebuild the Stokes basis on every build_flux_basis
+    bool moments_final = false;   // the field moments in d_mom match the accumulators
     std::vector<hipEvent_t> kev;   // event pool of the kernel timing
     hipStream_t cap_stream = nullptr;
+    hipStream_t stokes_cap = nullptr;        // capture stream of the Stokes graph
+    hipGraph_t stokes_graph = nullptr;
+    hipGraphExec_t stokes_exec = nullptr;
     hipStream_t lane_stream = nullptr;   // the second CG lane
     hipEvent_t lane_ev = nullptr;        // the second lane starts after the work queued before it
     int opt_lanes = 2;                   // CG lanes (1 or 2)
     int32_t* h_count = nullptr;          // pinned: per lane the active count and the timed count
+    std::map<int64_t, std::unique_ptr<CgStream>> streams;   // CG streams (continuous batching)
+    const BasisView* view = nullptr;     // the basis the CG and moments use (null: stochastic)
+    DetBatch det;                        // Method S2
+    int64_t next_stream = 1;
     sdmm_counters counters{};
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[8] = {};
+    bool moments_timed = false;
 };
 
 namespace {
@@ -367,11 +439,10 @@ int setup_device(Prob* ctx) {
     }
     // ---- Stokes
     ctx->sdev.clear();
-    std::vector<int> tr_sub, tr_r, tr_c, bmap, q_ptr, q_col, ccol;
-    std::vector<double> tr_v, Zc, q_val, uD, cval;
-    std::vector<int64_t> cptr;
+    std::vector<int> tr_sub, tr_r, tr_c, bmap, q_ptr, q_col;
+    std::vector<double> tr_v, Zc, q_val, uD;
     std::vector<int64_t> uD_off;
-    int64_t tiles_off = 0, rhs_off = 0, U_off = 0, P_off = 0;
+    int64_t tiles_off = 0, rhs_off = 0, U_off = 0, P_off = 0, linv_off = 0;
     int gcol = 0;
     ctx->max_nblk = ctx->max_w = ctx->max_ncol = 0;
     ctx->max_nout_s = 0;
@@ -400,6 +471,8 @@ int setup_device(Prob* ctx) {
         s.off_S = S_off;
         s.off_dofs = P.sub_ptr[h.sub];
         s.off_G = gcol;
+        s.off_linv = linv_off;
+        linv_off += (int64_t)s.nblk * 4096;
         tiles_off += (int64_t)s.nblk * (s.w + 1) * 4096;
         rhs_off += (int64_t)s.nblk * 64 * s.ncol;
         U_off += (int64_t)s.nvel * s.ncol;
@@ -417,24 +490,6 @@ int setup_device(Prob* ctx) {
             tr_r.push_back(h.ar[q]);
             tr_c.push_back(h.ac[q]);
             tr_v.push_back(h.av[q]);
-        }
-        {
-            // the full symmetric band matrix as CSR, columns ascending per row
-            s.off_cptr = (int64_t)cptr.size();
-            std::vector<std::vector<std::pair<int, double>>> rows(h.nband);
-            for (size_t q = 0; q < h.ar.size(); ++q) {
-                rows[h.ar[q]].push_back({h.ac[q], h.av[q]});
-                if (h.ar[q] != h.ac[q]) rows[h.ac[q]].push_back({h.ar[q], h.av[q]});
-            }
-            for (int r = 0; r < h.nband; ++r) {
-                std::sort(rows[r].begin(), rows[r].end());
-                cptr.push_back((int64_t)ccol.size());
-                for (auto& e : rows[r]) {
-                    ccol.push_back(e.first);
-                    cval.push_back(e.second);
-                }
-            }
-            cptr.push_back((int64_t)ccol.size());
         }
         const int i = h.sub;
         ctx->sub_R[i] = h.R;
@@ -515,9 +570,6 @@ int setup_device(Prob* ctx) {
     UP(ctx->d_tr_r, tr_r);
     UP(ctx->d_tr_c, tr_c);
     UP(ctx->d_tr_v, tr_v);
-    UP(ctx->d_cptr, cptr);
-    UP(ctx->d_ccol, ccol);
-    UP(ctx->d_cval, cval);
     std::vector<int64_t> dofs(P.sub_dofs.begin(), P.sub_dofs.end());
     UP(ctx->d_sub_dofs, dofs);
     UP(ctx->d_sub_dof_ptr, P.sub_ptr);
@@ -561,6 +613,9 @@ int setup_device(Prob* ctx) {
     if ((rc = alloc(ctx, ctx->d_I, std::max<int64_t>(ctx->I_total, 1) * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_T, ctx->T_total * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_tiles, tiles_off * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_tiles0, tiles_off * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_linv, linv_off * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_stmp, rhs_off * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_rhs, rhs_off * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_U, U_off * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_P, P_off * 8))) return rc;
@@ -596,36 +651,84 @@ int setup_device(Prob* ctx) {
     return SDMM_OK;
 }
 
-int build_stokes(Prob* ctx, hipStream_t st) {
+// The device part of the Stokes build (Section 5.1, eqs. starSproblem1-2 and
+// barSproblem1-2 for every Stokes subdomain): assembly into tiles, the band
+// LDL^T, the solves for all R + 1 right-hand sides with two FP64 refinement
+// steps, and the traces that give S, g_H and G.  Only kernels and device
+// copies, so the whole sequence can be captured as one graph.
+int stokes_device_work(Prob* ctx, hipStream_t st) {
     Problem& P = ctx->P;
     const int ns = (int)ctx->sdev.size();
-    HIPCHK(hipMemsetAsync(ctx->d_g.p, 0, ctx->d_g.bytes, st));
-    HIPCHK(hipMemsetAsync(ctx->d_G.p, 0, ctx->d_G.bytes, st));
+    HIPCHK(launch_fill_zero(ctx->d_g.as<double>(), (int64_t)(ctx->d_g.bytes / 8), st));
+    HIPCHK(launch_fill_zero(ctx->d_G.as<double>(), (int64_t)(ctx->d_G.bytes / 8), st));
     if (ns == 0) return SDMM_OK;
     StokesDev* sd = ctx->d_sdev.as<StokesDev>();
     double* tiles = ctx->d_tiles.as<double>();
-    HIPCHK(hipMemsetAsync(ctx->d_tiles.p, 0, ctx->d_tiles.bytes, st));
+    double* x = ctx->d_rhs.as<double>();
+    double* res = ctx->d_res.as<double>();
+    const double* linv = ctx->d_linv.as<double>();
+    // the right-hand sides are solved in place: start from the stored ones
+    HIPCHK(hipMemcpyAsync(ctx->d_rhs.p, ctx->d_rhs0.p, ctx->d_rhs.bytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_fill_zero(tiles, (int64_t)(ctx->d_tiles.bytes / 8), st));
     HIPCHK(launch_stokes_scatter(sd, ns, ctx->d_tr_sub.as<int>(), ctx->d_tr_r.as<int>(), ctx->d_tr_c.as<int>(),
                                  ctx->d_tr_v.as<double>(), ctx->n_trip, tiles, st));
     HIPCHK(launch_stokes_pad_identity(sd, ns, ctx->max_nblk, tiles, st));
-    for (int J = 0; J < ctx->max_nblk; ++J) HIPCHK(launch_stokes_ldl_step(sd, ns, J, ctx->max_w, tiles, st));
-    HIPCHK(launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, ctx->d_rhs.as<double>(), st));
+    // the assembled matrix, kept for the refinement residuals
+    HIPCHK(hipMemcpyAsync(ctx->d_tiles0.p, ctx->d_tiles.p, ctx->d_tiles.bytes, hipMemcpyDeviceToDevice, st));
+    for (int J = 0; J < ctx->max_nblk; ++J)
+        HIPCHK(launch_stokes_ldl_step(sd, ns, J, ctx->max_w, tiles, ctx->d_linv.as<double>(), st));
+    auto solve = [&](double* b) {
+        return launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, linv, b,
+                                   ctx->d_stmp.as<double>(), st);
+    };
+    HIPCHK(solve(x));
     // two steps of FP64 iterative refinement: the LDL^T without pivoting of
     // the saddle matrix loses digits that the refined solution recovers
     for (int step = 0; step < 2; ++step) {
-        HIPCHK(launch_stokes_residual(sd, ns, ctx->max_nblk, ctx->max_ncol, ctx->d_cptr.as<int64_t>(),
-                                      ctx->d_ccol.as<int>(), ctx->d_cval.as<double>(), ctx->d_rhs0.as<double>(),
-                                      ctx->d_rhs.as<double>(), ctx->d_res.as<double>(), st));
-        HIPCHK(launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, ctx->d_res.as<double>(),
-                                   st));
-        HIPCHK(launch_add_inplace(ctx->d_rhs.as<double>(), ctx->d_res.as<double>(),
-                                  (int64_t)(ctx->d_rhs.bytes / 8), st));
+        HIPCHK(launch_stokes_residual(sd, ns, ctx->max_nblk, ctx->max_ncol, ctx->d_tiles0.as<double>(),
+                                      ctx->d_rhs0.as<double>(), x, res, st));
+        HIPCHK(solve(res));
+        HIPCHK(launch_add_inplace(x, res, (int64_t)(ctx->d_rhs.bytes / 8), st));
     }
     HIPCHK(launch_stokes_finish(sd, ns, ctx->max_ncol, ctx->max_R, ctx->d_rhs.as<double>(), ctx->d_bmap.as<int>(),
                                 ctx->d_uD.as<double>(), ctx->d_uD_off.as<int64_t>(), ctx->d_Z.as<double>(),
                                 ctx->d_q_ptr.as<int>(), ctx->d_q_col.as<int>(), ctx->d_q_val.as<double>(),
                                 ctx->d_sub_dofs.as<int64_t>(), ctx->d_U.as<double>(), ctx->d_P.as<double>(),
                                 ctx->d_S.as<double>(), ctx->d_g.as<double>(), ctx->d_G.as<double>(), P.M, st));
+    return SDMM_OK;
+}
+
+int build_stokes(Prob* ctx, hipStream_t st) {
+    Problem& P = ctx->P;
+    if (!ctx->opt_graph) {
+        int rc = stokes_device_work(ctx, st);
+        if (rc) return rc;
+    } else {
+        // about 7,000 small launches per build: captured once as a graph and
+        // replayed on every later build of this problem
+        if (!ctx->stokes_exec) {
+            if (!ctx->stokes_cap && hipStreamCreateWithFlags(&ctx->stokes_cap, hipStreamNonBlocking) != hipSuccess) {
+                ctx->stokes_cap = nullptr;
+                return fail(ctx, SDMM_EDEVICE, "stream for the Stokes graph");
+            }
+            HIPCHK(hipStreamBeginCapture(ctx->stokes_cap, hipStreamCaptureModeThreadLocal));
+            int rc = stokes_device_work(ctx, ctx->stokes_cap);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(ctx->stokes_cap, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess || !g) return fail(ctx, SDMM_EDEVICE, "capture of the Stokes build failed");
+            if (hipGraphInstantiate(&ctx->stokes_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                ctx->stokes_exec = nullptr;
+                return fail(ctx, SDMM_EDEVICE, "instantiation of the Stokes graph failed");
+            }
+            ctx->stokes_graph = g;
+        }
+        HIPCHK(hipGraphLaunch(ctx->stokes_exec, st));
+    }
     // FETI coarse matrix (G^T G)^{-1}: n_kernel x n_kernel, inverted on the host
     const int nk = P.n_kernel;
     if (nk > 0) {
@@ -695,8 +798,8 @@ CgArgs cg_args(Prob* ctx, int64_t n, const int64_t* gidx, double* lam) {
     a.sub_dof_ptr = ctx->d_sub_dof_ptr.as<int64_t>();
     a.sub_dofs = ctx->d_sub_dofs.as<int64_t>();
     a.sub_region = ctx->d_sub_region.as<int>();
-    a.sub_Sbase = ctx->d_sub_Sbase.as<int64_t>();
-    a.S_cache = ctx->d_S.as<double>();
+    a.sub_Sbase = ctx->view ? ctx->view->d_sub_Sbase.as<int64_t>() : ctx->d_sub_Sbase.as<int64_t>();
+    a.S_cache = ctx->view ? ctx->view->S : ctx->d_S.as<double>();
     a.g = ctx->d_g.as<double>();
     a.G = ctx->d_G.as<double>();
     a.GtGinv = ctx->d_GtGinv.as<double>();
@@ -757,18 +860,23 @@ int build_groups_host(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* s
     G.h_slot.clear();
     G.h_item0.clear();
     const int nr = P.n_region;
+    const BasisView* v = ctx->view;
+    const int32_t* g2l = v ? v->g2l.data() : P.g2l.data();
+    const std::vector<int>& nloc = v ? v->nlocal : P.nlocal;
+    const std::vector<int>& pair_sub = v ? v->pair_sub : ctx->pair_sub;
+    const std::vector<int>& pair_k = v ? v->pair_k : ctx->pair_k;
     std::vector<int64_t> rbase(nr + 1);
     std::vector<std::vector<int64_t>> goff(nr);
     for (int r = 0; r < nr; ++r) {
         rbase[r] = (int64_t)G.h_perm.size();
-        const int L = P.nlocal[r];
+        const int L = nloc[r];
         goff[r].assign(L + 1, 0);
-        for (int64_t q = 0; q < n; ++q) goff[r][P.g2l[(size_t)hg[sel[q]] * nr + r] + 1]++;
+        for (int64_t q = 0; q < n; ++q) goff[r][g2l[(size_t)hg[sel[q]] * nr + r] + 1]++;
         for (int k = 0; k < L; ++k) goff[r][k + 1] += goff[r][k];
         std::vector<int64_t> fill(goff[r].begin(), goff[r].end() - 1);
         G.h_perm.resize(G.h_perm.size() + n);
         for (int64_t q = 0; q < n; ++q) {
-            const int k = P.g2l[(size_t)hg[sel[q]] * nr + r];
+            const int k = g2l[(size_t)hg[sel[q]] * nr + r];
             G.h_perm[rbase[r] + fill[k]++] = sel[q];
         }
     }
@@ -776,8 +884,8 @@ int build_groups_host(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* s
     for (int64_t q = 0; q < n; ++q) G.h_perm.push_back(sel[q]);  // Stokes: every realization
     if ((int64_t)G.h_perm.size() > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
     int64_t slot = 0;
-    for (size_t pidx = 0; pidx < ctx->pair_sub.size(); ++pidx) {
-        const int i = ctx->pair_sub[pidx], k = ctx->pair_k[pidx];
+    for (size_t pidx = 0; pidx < pair_sub.size(); ++pidx) {
+        const int i = pair_sub[pidx], k = pair_k[pidx];
         const int R = ctx->sub_R[i];
         const int r = ctx->sub_region[i];
         const int ext = R + ctx->sub_ker[i];
@@ -937,6 +1045,9 @@ int impl_destroy(Prob* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->stokes_exec) (void)hipGraphExecDestroy(ctx->stokes_exec);
+    if (ctx->stokes_graph) (void)hipGraphDestroy(ctx->stokes_graph);
+    if (ctx->stokes_cap) (void)hipStreamDestroy(ctx->stokes_cap);
     if (ctx->lane_stream) (void)hipStreamDestroy(ctx->lane_stream);
     if (ctx->h_count) (void)hipHostFree(ctx->h_count);
     if (ctx->lane_ev) (void)hipEventDestroy(ctx->lane_ev);
@@ -1059,6 +1170,14 @@ int impl_get_kl(Prob* ctx, int region, double* lam, int32_t* modes) {
     return SDMM_OK;
 }
 
+// Mixed-precision refinement of the Darcy responses: corrections until the
+// FP64 residual satisfies max|E - P X| <= kRefineTol max|E| per right-hand-
+// side group, at most kMaxRefine of them.  The flux basis is then evaluated
+// to second order in that residual (darcy_scorr_kernel), so its error is
+// quadratic in kRefineTol; the responses themselves carry it linearly.
+constexpr double kRefineTol = 1e-11;
+constexpr int kMaxRefine = 4;
+
 int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
@@ -1066,11 +1185,15 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     if (precision != SDMM_PREC_FP64 && precision != SDMM_PREC_MIXED) return fail(ctx, SDMM_EINVAL, "bad precision");
     if (method != SDMM_METHOD_STOCHASTIC && method != SDMM_METHOD_DETERMINISTIC)
         return fail(ctx, SDMM_EINVAL, "bad method");
-    if (method == SDMM_METHOD_DETERMINISTIC) return fail(ctx, SDMM_EINVAL, "deterministic basis not available");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
-    if (precision == SDMM_PREC_FP64) {
+    ctx->method = method;
+    ctx->det.valid = false;
+    ctx->det.precision = precision;
+    if (method == SDMM_METHOD_DETERMINISTIC) {
+        // Method S2: the Darcy bases are built per batch inside solve_interface
+    } else if (precision == SDMM_PREC_FP64) {
         HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, int np, hipStream_t q) {
             return launch_darcy_basis_blocked(tc, count, bp, Rs, np, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
                                               ctx->d_L.as<double>(), ctx->d_I.as<double>(), ctx->d_T.as<double>(), q);
@@ -1088,12 +1211,12 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
             return launch_darcy_basis_blocked_mixed(tc, count, bp, Rs, np, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
                                                     ctx->d_E.as<double>(), ctx->d_L32.as<float>(),
                                                     ctx->d_I32.as<float>(),
-                                                    ctx->d_T.as<double>(), ctx->d_W32.as<float>(), 4, 1e-13, max_res,
-                                                    steps, q);
+                                                    ctx->d_T.as<double>(), ctx->d_W32.as<float>(), kMaxRefine,
+                                                    kRefineTol, max_res, steps, q);
         }));
     }
     HIPCHK(hipEventRecord(ctx->ev[1], st));
-    if (!ctx->stokes_built) {
+    if (!ctx->stokes_built || ctx->opt_stokes_rebuild) {
         int rc = build_stokes(ctx, st);
         if (rc) return rc;
         ctx->stokes_built = true;
@@ -1102,12 +1225,24 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     ctx->built_precision = precision;
     ctx->basis_built = true;
     int64_t sd = 0, ss = 0;
-    for (auto& u : ctx->units) sd += ctx->P.darcy[u.d].R;
+    if (method == SDMM_METHOD_STOCHASTIC)
+        for (auto& u : ctx->units) sd += ctx->P.darcy[u.d].R;
     for (auto& s : ctx->P.stokes) ss += s.R;
     ctx->counters.basis_solves_darcy += sd;
     ctx->counters.basis_solves_stokes = ss;
     ctx->counters.complementary_solves = (int64_t)ctx->P.stokes.size();
+    if (method == SDMM_METHOD_DETERMINISTIC) return SDMM_OK;
     ctx->counters.units_built += ctx->n_units;
+    if (precision == SDMM_PREC_MIXED) {
+        // every right-hand-side group must have reached the refinement tolerance
+        double mr = 0.0;
+        HIPCHK(hipMemcpyAsync(&mr, ctx->d_refine.p, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!(mr <= kRefineTol))
+            return fail(ctx, SDMM_ENOTCONV,
+                        "mixed-precision refinement stopped at relative residual " + std::to_string(mr) +
+                            " above " + std::to_string(kRefineTol) + " (the basis is stored)");
+    }
     return SDMM_OK;
 }
 
@@ -1116,12 +1251,20 @@ int impl_get_basis(Prob* ctx, int sub, int k, double* S, int64_t ld) {
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (sub < 0 || sub >= (int)ctx->P.subs.size()) return fail(ctx, SDMM_EINVAL, "bad subdomain");
     const int R = ctx->sub_R[sub];
-    if (k < 0 || k >= ctx->sub_nlocal[sub] || ld < R) return fail(ctx, SDMM_EINVAL, "bad local index or ld");
+    const bool det = ctx->method == SDMM_METHOD_DETERMINISTIC && ctx->sub_region[sub] >= 0;
+    // Method S2: k is the batch position of the last solve
+    const int64_t nk = det ? (ctx->det.valid ? ctx->det.n : 0) : ctx->sub_nlocal[sub];
+    if (k < 0 || k >= nk || ld < R) return fail(ctx, SDMM_EINVAL, "bad local index or ld");
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipDeviceSynchronize());
     std::vector<double> tmp((size_t)R * R);
-    HIPCHK(hipMemcpy(tmp.data(), ctx->d_S.as<double>() + ctx->sub_Sbase[sub] + (int64_t)k * R * R, tmp.size() * 8,
-                     hipMemcpyDeviceToHost));
+    const double* src = ctx->d_S.as<double>() + ctx->sub_Sbase[sub] + (int64_t)k * R * R;
+    if (det) {
+        std::vector<int64_t> sb(ctx->P.subs.size());
+        HIPCHK(hipMemcpy(sb.data(), ctx->det.view.d_sub_Sbase.p, sb.size() * 8, hipMemcpyDeviceToHost));
+        src = ctx->det.d_S.as<double>() + sb[sub] + (int64_t)k * R * R;
+    }
+    HIPCHK(hipMemcpy(tmp.data(), src, tmp.size() * 8, hipMemcpyDeviceToHost));
     for (int j = 0; j < R; ++j)
         for (int m = 0; m < R; ++m) S[(int64_t)j * ld + m] = tmp[(size_t)j * R + m];
     return SDMM_OK;
@@ -1154,7 +1297,11 @@ int impl_set_option(Prob* ctx, int option, int64_t value) {
             ctx->opt_graph = value ? 1 : 0;
             return SDMM_OK;
         case SDMM_OPT_KERNEL_TIMING:
-            ctx->opt_ktime = value ? 1 : 0;
+            if (value < 0 || value > 1 << 20) return fail(ctx, SDMM_EINVAL, "kernel timing period out of range");
+            ctx->opt_ktime = (int)value;
+            return SDMM_OK;
+        case SDMM_OPT_STOKES_REBUILD:
+            ctx->opt_stokes_rebuild = value ? 1 : 0;
             return SDMM_OK;
         case SDMM_OPT_CG_LANES:
             if (value < 1 || value > kMaxLanes) return fail(ctx, SDMM_EINVAL, "cg_lanes must be 1 or 2");
@@ -1227,7 +1374,7 @@ int solve_batch(Prob* ctx, int64_t n, int64_t S, const int64_t* gidx, double rto
     const int M = ctx->P.M;
     const int group = ctx->opt_check;
     const bool ktime = ctx->opt_ktime != 0;
-    constexpr int kTimeEvery = 4;   // one check group in kTimeEvery of lane 0 is timed
+    const int kTimeEvery = std::max(1, ctx->opt_ktime);   // one check group in kTimeEvery of lane 0 is timed
     Lane lanes[kMaxLanes];
     const CgArgs a0 = cg_args(ctx, S, gidx, lambda);
     for (int k = 0; k < nl; ++k) {
@@ -1362,11 +1509,16 @@ int solve_batch(Prob* ctx, int64_t n, int64_t S, const int64_t* gidx, double rto
     auto launch = [&](Lane& L) -> int {
         L.timed = ktime && L.id == 0 && (ngroup++ % kTimeEvery == 0);
         hipError_t e = hipSuccess;
+        // the timed iteration runs alone on the device: the other lane's
+        // group is drained first and its next group waits for the timed pair
+        Lane* other = (L.timed && nl == 2 && !lanes[1].done) ? &lanes[1] : nullptr;
+        if (other) HIPCHK(hipStreamSynchronize(other->s));
         if (L.exec && !L.timed) {
             for (int j = 0; j < group / gcap && e == hipSuccess; ++j) e = hipGraphLaunch(L.exec, L.s);
         } else {
             e = body(L, L.timed, group);
         }
+        if (e == hipSuccess && other) e = hipStreamWaitEvent(other->s, ctx->kev[3], 0);
         if (e == hipSuccess) e = launch_count_active(L.a.active, L.S, L.a.any_active, L.s);
         if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_count + 2 * L.id, L.a.any_active, 8, hipMemcpyDeviceToHost, L.s);
         if (e != hipSuccess) return fail(ctx, SDMM_EDEVICE, hipGetErrorString(e));
@@ -1455,13 +1607,218 @@ hipStream_t work_stream(Prob* ctx, hipStream_t user) {
 
 }  // namespace
 
+// ---- Method S2 (Section 5.3): a deterministic basis for every realization ----
+
+constexpr int kDetChunkUnits = 1024;   // units built per launch (their factor scratch is reused)
+
+// The points of a batch on the host: collocation points of gidx (device) or
+// the caller's off-grid points y (device, n x n_term).
+int det_points(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, hipStream_t st, std::vector<double>& out) {
+    const Problem& P = ctx->P;
+    const int nt = P.nterm;
+    out.assign((size_t)n * nt, 0.0);
+    if (gidx) {
+        int rc;
+        if ((rc = check_indices(ctx, gidx, n, st)) || (rc = fetch_gidx(ctx, gidx, n, st))) return rc;
+        for (int64_t q = 0; q < n; ++q)
+            for (int t = 0; t < nt; ++t) out[(size_t)q * nt + t] = P.node_x[P.ids[(size_t)ctx->h_gidx[q] * nt + t]];
+    } else if (nt > 0) {
+        HIPCHK(hipMemcpyAsync(out.data(), y, out.size() * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (double v : out)
+            if (!std::isfinite(v)) return fail(ctx, SDMM_EINVAL, "a point coordinate is not finite");
+    }
+    return SDMM_OK;
+}
+
+// Units, offsets, device tables and the basis view of a batch of n realizations.
+int det_layout(Prob* ctx, int64_t n) {
+    Problem& P = ctx->P;
+    DetBatch& D = ctx->det;
+    BasisView& V = D.view;
+    const int nsub = (int)P.subs.size(), nr = P.n_region;
+    D.units.clear();
+    D.chunk_start.clear();
+    V.pair_sub.clear();
+    V.pair_k.clear();
+    std::vector<int64_t> sbase(nsub, 0), abase(nsub, 0), dabase;
+    std::vector<int> unit_of_dk, dnl;
+    int64_t S_off = 0, X_off = 0, A_off = ctx->A_total;
+    for (int i = 0; i < nsub; ++i) {
+        sbase[i] = S_off;
+        const int R = ctx->sub_R[i];
+        if (ctx->sub_region[i] >= 0) {
+            S_off += n * (int64_t)R * R;
+            abase[i] = A_off;
+            A_off += n * ((int64_t)R + (int64_t)R * R);
+        } else {
+            S_off += (int64_t)R * R;
+            abase[i] = ctx->sub_Abase[i];
+        }
+    }
+    D.A_base = ctx->A_total;
+    int64_t L_off = 0, T_off = 0, I_off = 0, L_max = 0, T_max = 0, I_max = 0;
+    int in_chunk = 0;
+    unit_of_dk.assign(P.darcy.size() * (size_t)n, -1);
+    for (size_t di = 0; di < P.darcy.size(); ++di) {
+        const DarcyHost& h = P.darcy[di];
+        const int i = h.sub, r = P.subs[i].region;
+        dabase.push_back(abase[i]);
+        dnl.push_back((int)n);
+        for (int64_t q = 0; q < n; ++q) {
+            if (in_chunk == 0) {
+                D.chunk_start.push_back((int)D.units.size());
+                L_off = T_off = I_off = 0;
+            }
+            const int64_t Np = (h.N + 15) / 16 * 16, bp = (h.b + 15) / 16 * 16;
+            UnitDev u{};
+            u.d = (int)di;
+            u.k = (int)q;
+            u.sub = i;
+            u.off_xi = q * P.nterm + P.dim_off[r];
+            u.off_S = sbase[i] + q * (int64_t)h.R * h.R;
+            u.off_X = X_off;
+            u.off_L = L_off;
+            u.off_T = T_off;
+            u.off_I = I_off;
+            X_off += Np * h.R;
+            L_off += Np * (bp + 1);
+            T_off += (int64_t)4 * h.N + h.n_medge;
+            I_off += Np * 16;
+            L_max = std::max(L_max, L_off);
+            T_max = std::max(T_max, T_off);
+            I_max = std::max(I_max, I_off);
+            unit_of_dk[di * (size_t)n + q] = (int)D.units.size();
+            D.units.push_back(u);
+            V.pair_sub.push_back(i);
+            V.pair_k.push_back((int)q);
+            if (++in_chunk == kDetChunkUnits) in_chunk = 0;
+        }
+    }
+    D.chunk_start.push_back((int)D.units.size());
+    for (size_t si = 0; si < P.stokes.size(); ++si) {
+        V.pair_sub.push_back(P.stokes[si].sub);
+        V.pair_k.push_back(0);
+    }
+    V.g2l.assign((size_t)n * nr, 0);
+    for (int64_t q = 0; q < n; ++q)
+        for (int r = 0; r < nr; ++r) V.g2l[(size_t)q * nr + r] = (int32_t)q;
+    V.nlocal.assign(nr, (int)n);
+    int rc;
+    auto grow = [&](DevBuf& b, size_t bytes) { return b.bytes < bytes ? alloc(ctx, b, bytes) : SDMM_OK; };
+    const bool mixed = D.precision == SDMM_PREC_MIXED;
+    if ((rc = grow(D.d_S, S_off * 8)) || (rc = grow(D.d_X, X_off * 8)) || (rc = grow(D.d_T, T_max * 8)) ||
+        (rc = grow(D.d_refine, 16)))
+        return rc;
+    if (mixed) {
+        if ((rc = grow(D.d_E, X_off * 8)) || (rc = grow(D.d_W32, X_off * 4)) || (rc = grow(D.d_L32, L_max * 4)) ||
+            (rc = grow(D.d_I32, std::max<int64_t>(I_max, 1) * 4)))
+            return rc;
+    } else if ((rc = grow(D.d_L, L_max * 8)) || (rc = grow(D.d_I, std::max<int64_t>(I_max, 1) * 8))) {
+        return rc;
+    }
+    // accumulators: the stochastic layout, then the batch's Darcy pairs;
+    // what the first part holds (the Stokes accumulators) is kept
+    if (ctx->d_acc.bytes < (size_t)A_off * 8) {
+        DevBuf nb;
+        if ((rc = alloc(ctx, nb, A_off * 8))) return rc;
+        HIPCHK(hipMemset(nb.p, 0, nb.bytes));
+        HIPCHK(hipMemcpy(nb.p, ctx->d_acc.p, ctx->d_acc.bytes, hipMemcpyDeviceToDevice));
+        std::swap(ctx->d_acc.p, nb.p);
+        std::swap(ctx->d_acc.bytes, nb.bytes);
+        std::swap(ctx->d_acc.al, nb.al);
+    }
+    std::vector<int> order(D.units.size());
+    for (size_t u = 0; u < order.size(); ++u) order[u] = (int)u;
+    std::vector<int64_t> pos(n);
+    for (int64_t q = 0; q < n; ++q) pos[q] = q;
+    if ((rc = upload(ctx, D.d_units, D.units)) || (rc = upload(ctx, D.d_order, order)) ||
+        (rc = upload(ctx, D.d_pos, pos)) || (rc = upload(ctx, D.d_unit_of_dk, unit_of_dk)) ||
+        (rc = upload(ctx, D.d_dnlocal, dnl)) || (rc = upload(ctx, D.d_dAbase, dabase)) ||
+        (rc = upload(ctx, V.d_pair_sub, V.pair_sub)) || (rc = upload(ctx, V.d_pair_k, V.pair_k)) ||
+        (rc = upload(ctx, V.d_sub_Sbase, sbase)) || (rc = upload(ctx, V.d_sub_Abase, abase)))
+        return rc;
+    const int64_t nd = 2 * (ctx->field_size[1] + ctx->field_size[2]);
+    if ((rc = grow(D.d_tmp, std::max<int64_t>(nd, 1) * 8))) return rc;
+    if (!D.d_sum.p) {
+        if ((rc = alloc(ctx, D.d_sum, std::max<int64_t>(nd, 1) * 8))) return rc;
+        HIPCHK(hipMemset(D.d_sum.p, 0, D.d_sum.bytes));
+    }
+    V.S = D.d_S.as<double>();
+    D.S_total = S_off;
+    D.X_total = X_off;
+    D.n = n;
+    return SDMM_OK;
+}
+
+// Build the deterministic bases of the batch (Section 5.3: S_{H,i} of every
+// Darcy subdomain from the realization's own KL field, eqs. starDproblem1-2);
+// the Stokes blocks, which no realization changes, are copied from the
+// Stokes build.
+int det_build(Prob* ctx, const std::vector<double>& y, hipStream_t st) {
+    DetBatch& D = ctx->det;
+    int rc;
+    if (!y.empty()) {
+        if ((rc = upload(ctx, D.d_xi, y))) return rc;
+    } else if ((rc = alloc(ctx, D.d_xi, 8))) {
+        return rc;
+    }
+    DarcyTables t = darcy_tables(ctx);
+    t.units = D.d_units.as<UnitDev>();
+    t.order = D.d_order.as<int>();
+    t.xi = D.d_xi.as<double>();
+    int max_np = 0;
+    for (auto& h : ctx->P.darcy) max_np = std::max(max_np, (h.N + 15) / 16 * 16);
+    const bool mixed = D.precision == SDMM_PREC_MIXED;
+    if (mixed) HIPCHK(hipMemsetAsync(D.d_refine.p, 0, 16, st));
+    for (size_t c = 0; c + 1 < D.chunk_start.size(); ++c) {
+        t.unit_base = D.chunk_start[c];
+        const int count = D.chunk_start[c + 1] - D.chunk_start[c];
+        if (count <= 0) continue;
+        if (mixed)
+            HIPCHK(launch_darcy_basis_blocked_mixed(t, count, ctx->max_b, ctx->max_Rd, max_np, D.d_S.as<double>(),
+                                                    D.d_X.as<double>(), D.d_E.as<double>(), D.d_L32.as<float>(),
+                                                    D.d_I32.as<float>(), D.d_T.as<double>(), D.d_W32.as<float>(),
+                                                    kMaxRefine, kRefineTol, D.d_refine.as<double>(),
+                                                    reinterpret_cast<int*>(D.d_refine.as<char>() + 8), st));
+        else
+            HIPCHK(launch_darcy_basis_blocked(t, count, ctx->max_b, ctx->max_Rd, max_np, D.d_S.as<double>(),
+                                              D.d_X.as<double>(), D.d_L.as<double>(), D.d_I.as<double>(),
+                                              D.d_T.as<double>(), st));
+    }
+    const Problem& P = ctx->P;
+    std::vector<int64_t> sbase(P.subs.size());
+    HIPCHK(hipMemcpy(sbase.data(), D.view.d_sub_Sbase.p, sbase.size() * 8, hipMemcpyDeviceToHost));
+    for (auto& sh : P.stokes) {
+        const int i = sh.sub, R = ctx->sub_R[i];
+        HIPCHK(hipMemcpyAsync(D.d_S.as<double>() + sbase[i], ctx->d_S.as<double>() + ctx->sub_Sbase[i],
+                              (size_t)R * R * 8, hipMemcpyDeviceToDevice, st));
+    }
+    if (mixed) {
+        double mr = 0.0;
+        HIPCHK(hipMemcpyAsync(&mr, D.d_refine.p, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->counters.max_refine_residual = mr;
+        if (!(mr <= kRefineTol))
+            return fail(ctx, SDMM_ENOTCONV, "mixed-precision refinement of a deterministic basis stopped at " +
+                                                std::to_string(mr));
+    }
+    int64_t sd = 0;
+    for (auto& u : D.units) sd += ctx->P.darcy[u.d].R;
+    ctx->counters.basis_solves_darcy += sd;
+    ctx->counters.units_built += (int64_t)D.units.size();
+    return SDMM_OK;
+}
+
 int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, double rtol, int32_t max_iter,
                          double* lambda, int32_t* iters, double* relres, int32_t* status, void* stream) {
     if (!ctx) return SDMM_EINVAL;
-    if (n > 0 && !gidx && y) return fail(ctx, SDMM_EINVAL, "off-grid points need the deterministic method");
+    ctx->view = nullptr;
+    const bool det = ctx->method == SDMM_METHOD_DETERMINISTIC;
+    if (n > 0 && !gidx && y && !det) return fail(ctx, SDMM_EINVAL, "off-grid points need the deterministic method");
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
-    if (n < 0 || (n > 0 && (!gidx || !lambda)) || !(rtol > 0) || max_iter < 1)
+    if (n < 0 || (n > 0 && ((!gidx && !(det && y)) || !lambda)) || !(rtol > 0) || max_iter < 1)
         return fail(ctx, SDMM_EINVAL, "invalid arguments");
     if (n == 0) return SDMM_OK;
     if (n > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
@@ -1471,14 +1828,33 @@ int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double
     HIPCHK(hipEventRecord(ctx->ev[5], user));
     HIPCHK(hipStreamWaitEvent(st, ctx->ev[5], 0));
     int rc;
-    if ((rc = check_indices(ctx, gidx, n, st))) return rc;
+    const int64_t* cg_idx = gidx;
+    if (det) {
+        // Method S2: this batch's own bases, then the CG on them (the batch
+        // positions stand in for the global indices)
+        std::vector<double> pts;
+        ctx->det.valid = false;
+        if ((rc = det_points(ctx, n, gidx, y, st, pts)) || (rc = det_layout(ctx, n))) return rc;
+        rc = det_build(ctx, pts, st);
+        if (rc && rc != SDMM_ENOTCONV) return rc;
+        ctx->det.y = pts;
+        ctx->det.valid = true;
+        cg_idx = ctx->det.d_pos.as<int64_t>();
+        ctx->view = &ctx->det.view;
+    } else if ((rc = check_indices(ctx, gidx, n, st))) {
+        return rc;
+    }
     const int64_t chunk = chunk_size(ctx, n);
-    if ((rc = ensure_workspace(ctx, chunk))) return rc;
+    if ((rc = ensure_workspace(ctx, chunk))) {
+        ctx->view = nullptr;
+        return rc;
+    }
     HIPCHK(hipEventRecord(ctx->ev[3], st));
     int64_t tot = 0;
     bool bad = false, brk = false;
-    if ((rc = solve_batch(ctx, n, chunk, gidx, rtol, max_iter, lambda, iters, relres, status, st, tot, bad, brk)))
-        return rc;
+    rc = solve_batch(ctx, n, chunk, cg_idx, rtol, max_iter, lambda, iters, relres, status, st, tot, bad, brk);
+    ctx->view = nullptr;
+    if (rc) return rc;
     HIPCHK(hipEventRecord(ctx->ev[4], st));
     HIPCHK(hipStreamWaitEvent(user, ctx->ev[4], 0));
     HIPCHK(hipStreamSynchronize(st));
@@ -1501,6 +1877,8 @@ int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double
 int impl_solve_interface_noalloc(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter,
                                  double* lambda, int32_t* iters, double* relres, int32_t* status, void* stream) {
     if (!ctx) return SDMM_EINVAL;
+    if (ctx->method == SDMM_METHOD_DETERMINISTIC)
+        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built deterministic");
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (n < 0 || (n > 0 && (!gidx || !lambda)) || !(rtol > 0) || max_iter < 1)
@@ -1628,8 +2006,201 @@ int impl_solve_interface_noalloc(Prob* ctx, int64_t n, const int64_t* gidx, doub
     return SDMM_OK;
 }
 
+// ---- CG streams (continuous batching of Section 5.4's main loop) -------------
+
+int impl_stream_open(Prob* ctx, int64_t slots, double rtol, int32_t max_iter, void* stream, int64_t* sid) {
+    if (!ctx || !sid) return SDMM_EINVAL;
+    if (ctx->method == SDMM_METHOD_DETERMINISTIC)
+        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built deterministic");
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    if (slots < 1 || slots > (1 << 24) || !(rtol > 0) || max_iter < 1)
+        return fail(ctx, SDMM_EINVAL, "invalid stream arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    std::unique_ptr<CgStream> cs(new (std::nothrow) CgStream());
+    if (!cs) return fail(ctx, SDMM_ENOMEM, "stream");
+    CgStream& c = *cs;
+    c.S = slots;
+    c.rtol = rtol;
+    c.max_iter = max_iter;
+    c.st = (hipStream_t)stream;
+    const size_t S = slots, M = ctx->P.M;
+    int rc;
+    if ((rc = alloc(ctx, c.r, S * M * 8)) || (rc = alloc(ctx, c.p, S * M * 8)) ||
+        (rc = alloc(ctx, c.Y, S * ctx->SR * 8)) || (rc = alloc(ctx, c.lam, S * M * 8)) ||
+        (rc = alloc(ctx, c.rr, S * 8)) || (rc = alloc(ctx, c.r0, S * 8)) || (rc = alloc(ctx, c.relres, S * 8)) ||
+        (rc = alloc(ctx, c.iters, S * 4)) || (rc = alloc(ctx, c.status, S * 4)) ||
+        (rc = alloc(ctx, c.active, S * 4)) || (rc = alloc(ctx, c.any, 16)) || (rc = alloc(ctx, c.slot_q, S * 4)) ||
+        (rc = alloc(ctx, c.init, S * 4)) || (rc = alloc(ctx, c.g_slot, S * 4)) || (rc = alloc(ctx, c.g_lam, S * 8)) ||
+        (rc = alloc(ctx, c.g_it, S * 8)) || (rc = alloc(ctx, c.g_rel, S * 8)) || (rc = alloc(ctx, c.g_st, S * 8)))
+        return rc;
+    // slot l holds its realization's state and outputs at row l
+    std::vector<int> ident(S);
+    for (size_t l = 0; l < S; ++l) ident[l] = (int)l;
+    HIPCHK(hipMemcpy(c.slot_q.p, ident.data(), S * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(c.active.p, 0, S * 4));
+    c.slot_g.assign(S, 0);
+    c.slot_ticket.assign(S, -1);
+    c.slot_row.assign(S, -1);
+    c.act.assign(S, 0);
+    *sid = ctx->next_stream++;
+    ctx->streams[*sid] = std::move(cs);
+    return SDMM_OK;
+}
+
+int find_stream(Prob* ctx, int64_t sid, CgStream** out) {
+    auto it = ctx->streams.find(sid);
+    if (it == ctx->streams.end()) return fail(ctx, SDMM_EINVAL, "unknown CG stream " + std::to_string(sid));
+    *out = it->second.get();
+    return SDMM_OK;
+}
+
+int impl_stream_submit(Prob* ctx, int64_t sid, int64_t n, const int64_t* gidx, double* lambda, int32_t* iters,
+                       double* relres, int32_t* status, int64_t* ticket) {
+    if (!ctx || !ticket) return SDMM_EINVAL;
+    CgStream* c;
+    int rc;
+    if ((rc = find_stream(ctx, sid, &c))) return rc;
+    if (n < 1 || n > 2147483647LL || !gidx || !lambda) return fail(ctx, SDMM_EINVAL, "invalid request");
+    for (int64_t q = 0; q < n; ++q)
+        if (gidx[q] < 0 || gidx[q] >= ctx->P.nreal)
+            return fail(ctx, SDMM_EINVAL, "a global collocation index is out of range");
+    const int64_t t = c->next_ticket++;
+    c->reqs[t] = CgStream::Req{lambda, iters, relres, status, n};
+    for (int64_t q = 0; q < n; ++q) c->queue.push_back({t, gidx[q], (int)q});
+    *ticket = t;
+    return SDMM_OK;
+}
+
+int impl_stream_run(Prob* ctx, int64_t sid, int32_t max_groups, int64_t* done, int64_t cap, int64_t* n_done,
+                    int64_t* in_flight) {
+    if (!ctx || !n_done || (cap > 0 && !done)) return SDMM_EINVAL;
+    CgStream* cp;
+    int rc;
+    if ((rc = find_stream(ctx, sid, &cp))) return rc;
+    CgStream& c = *cp;
+    HIPCHK(hipSetDevice(ctx->device));
+    *n_done = 0;
+    const int M = ctx->P.M;
+    CgArgs a = cg_args(ctx, c.S, nullptr, c.lam.as<double>());
+    a.r = c.r.as<double>();
+    a.p = c.p.as<double>();
+    a.rr = c.rr.as<double>();
+    a.r0 = c.r0.as<double>();
+    a.relres = c.relres.as<double>();
+    a.iters = c.iters.as<int32_t>();
+    a.status = c.status.as<int32_t>();
+    a.active = c.active.as<int32_t>();
+    a.any_active = c.any.as<int32_t>();
+    a.slot_q = c.slot_q.as<int>();
+    a.init_slots = c.init.as<int>();
+    a.rtol = c.rtol;
+    a.max_iter = c.max_iter;
+    a.iters_out = nullptr;
+    a.relres_out = nullptr;
+    a.status_out = nullptr;
+    const int* pos = ctx->d_pos.as<int>();
+    std::vector<int64_t> finished;
+    auto regroup = [&]() -> int {
+        c.sel.clear();
+        for (int64_t l = 0; l < c.S; ++l)
+            if (c.slot_ticket[l] >= 0) c.sel.push_back((int)l);
+        int r2;
+        if ((r2 = build_groups_host(ctx, c.G, c.S, &c.sel, c.slot_g.data()))) return r2;
+        if ((r2 = upload_groups(ctx, c.G, c.st))) return r2;
+        c.in_work = (int64_t)c.sel.size();
+        return SDMM_OK;
+    };
+    for (int32_t grp = 0; grp < std::max(1, max_groups); ++grp) {
+        // admission: queued realizations into the free slots
+        c.init_h.clear();
+        for (int64_t l = 0; l < c.S && !c.queue.empty(); ++l) {
+            if (c.slot_ticket[l] >= 0) continue;
+            const CgStream::Pending pq = c.queue.front();
+            c.queue.pop_front();
+            c.slot_ticket[l] = pq.ticket;
+            c.slot_row[l] = pq.row;
+            c.slot_g[l] = pq.gidx;
+            c.init_h.push_back((int)l);
+            ++c.occupied;
+        }
+        if (!c.init_h.empty()) {
+            HIPCHK(hipMemcpyAsync(c.init.p, c.init_h.data(), c.init_h.size() * 4, hipMemcpyHostToDevice, c.st));
+            HIPCHK(launch_cg_init(a, (int64_t)c.init_h.size(), c.st));
+            if ((rc = regroup())) return rc;
+        }
+        if (c.occupied == 0) break;
+        for (int q = 0; q < ctx->opt_check; ++q) {
+            HIPCHK(launch_cg_apply_mfma(a, a.p, c.Y.as<double>(), ctx->SR, c.G.d_work.as<int4>(), c.G.nwork,
+                                        c.G.d_perm.as<int>(), ctx->max_R, c.st));
+            HIPCHK(launch_cg_update2(a, c.Y.as<double>(), ctx->SR, pos, c.st));
+        }
+        ++c.groups_run;
+        HIPCHK(hipMemcpyAsync(c.act.data(), a.active, c.S * 4, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        // finished realizations leave their slots for their requests' buffers
+        std::vector<int> gs;
+        std::vector<double*> gl;
+        std::vector<double*> gr;
+        std::vector<int32_t*> gi, gt;
+        for (int64_t l = 0; l < c.S; ++l) {
+            if (c.slot_ticket[l] < 0 || c.act[l]) continue;
+            CgStream::Req& rq = c.reqs[c.slot_ticket[l]];
+            const int row = c.slot_row[l];
+            gs.push_back((int)l);
+            gl.push_back(rq.lam + (int64_t)row * M);
+            gi.push_back(rq.it ? rq.it + row : nullptr);
+            gr.push_back(rq.rel ? rq.rel + row : nullptr);
+            gt.push_back(rq.st ? rq.st + row : nullptr);
+            if (--rq.remaining == 0) finished.push_back(c.slot_ticket[l]);
+            c.slot_ticket[l] = -1;
+            c.slot_row[l] = -1;
+            --c.occupied;
+        }
+        if (!gs.empty()) {
+            const size_t k = gs.size();
+            HIPCHK(hipMemcpyAsync(c.g_slot.p, gs.data(), k * 4, hipMemcpyHostToDevice, c.st));
+            HIPCHK(hipMemcpyAsync(c.g_lam.p, gl.data(), k * 8, hipMemcpyHostToDevice, c.st));
+            HIPCHK(hipMemcpyAsync(c.g_it.p, gi.data(), k * 8, hipMemcpyHostToDevice, c.st));
+            HIPCHK(hipMemcpyAsync(c.g_rel.p, gr.data(), k * 8, hipMemcpyHostToDevice, c.st));
+            HIPCHK(hipMemcpyAsync(c.g_st.p, gt.data(), k * 8, hipMemcpyHostToDevice, c.st));
+            HIPCHK(launch_stream_gather(c.lam.as<double>(), M, c.g_slot.as<int>(), c.g_lam.as<double*>(),
+                                        c.iters.as<int32_t>(), c.relres.as<double>(), c.status.as<int32_t>(),
+                                        c.g_it.as<int32_t*>(), c.g_rel.as<double*>(), c.g_st.as<int32_t*>(), (int)k,
+                                        c.st));
+            HIPCHK(hipStreamSynchronize(c.st));   // the host lists are rebuilt at the next check
+            // the freed slots are refilled at the next admission; when nothing
+            // waits, the operator shrinks to the realizations still iterating
+            if (c.queue.empty() && c.occupied > 0 && c.occupied < 0.75 * c.in_work && (rc = regroup())) return rc;
+        }
+    }
+    int64_t nd = 0;
+    for (int64_t t : finished) {
+        if (nd < cap) done[nd] = t;
+        ++nd;
+        c.reqs.erase(t);
+    }
+    *n_done = std::min(nd, cap);
+    if (in_flight) *in_flight = c.occupied + (int64_t)c.queue.size();
+    if (nd > cap) return fail(ctx, SDMM_EINVAL, "done capacity too small (tickets beyond it were dropped)");
+    return SDMM_OK;
+}
+
+int impl_stream_close(Prob* ctx, int64_t sid) {
+    CgStream* c;
+    int rc;
+    if (!ctx) return SDMM_EINVAL;
+    if ((rc = find_stream(ctx, sid, &c))) return rc;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(c->st));
+    ctx->streams.erase(sid);
+    return SDMM_OK;
+}
+
 int impl_autotune(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,
                   int64_t* chunk_out) {
+    if (ctx && ctx->method == SDMM_METHOD_DETERMINISTIC)
+        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built deterministic");
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
@@ -1695,24 +2266,16 @@ int impl_autotune(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_
     return SDMM_OK;
 }
 
-int impl_accumulate_moments(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, const double* lambda,
-                            const double* weights, void* stream) {
-    if (!ctx) return SDMM_EINVAL;
-    if (n > 0 && !gidx && y) return fail(ctx, SDMM_EINVAL, "off-grid points need the deterministic method");
-    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
-    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
-    if (n < 0 || (n > 0 && (!gidx || !lambda))) return fail(ctx, SDMM_EINVAL, "invalid arguments");
-    if (n == 0) return SDMM_OK;
-    HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
+int accumulate_core(Prob* ctx, int64_t n, const int64_t* grp_idx, const int64_t* w_idx, const double* lambda,
+                    const double* weights, hipStream_t st) {
     int rc;
-    if ((rc = check_indices(ctx, gidx, n, st))) return rc;
     const int64_t chunk = chunk_size(ctx, n);
     if ((rc = ensure_workspace(ctx, chunk))) return rc;
     const int M = ctx->P.M;
+    const BasisView* v = ctx->view;
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
         const int64_t cn = std::min(chunk, n - c0);
-        const int64_t* g = gidx + c0;
+        const int64_t* g = grp_idx + c0;
         const double* lam = lambda + c0 * M;
         if ((rc = fetch_gidx(ctx, g, cn, st))) return rc;
         Groups& G = ctx->grp[0];
@@ -1733,7 +2296,7 @@ int impl_accumulate_moments(Prob* ctx, int64_t n, const int64_t* gidx, const dou
         m.nsub = (int)ctx->P.subs.size();
         m.nregion = ctx->P.n_region;
         m.nker = ctx->P.n_kernel;
-        m.gidx = g;
+        m.gidx = w_idx ? w_idx + c0 : nullptr;
         m.g2l = ctx->d_g2l.as<int32_t>();
         m.weights = weights ? weights + c0 : nullptr;
         m.colloc_w = ctx->d_weights.as<double>();
@@ -1744,19 +2307,72 @@ int impl_accumulate_moments(Prob* ctx, int64_t n, const int64_t* gidx, const dou
         m.sub_region = ctx->d_sub_region.as<int>();
         m.sub_ker = ctx->d_sub_ker.as<int>();
         m.sub_Gcol = ctx->d_sub_Gcol.as<int>();
-        m.sub_Abase = ctx->d_sub_Abase.as<int64_t>();
+        m.sub_Abase = v ? v->d_sub_Abase.as<int64_t>() : ctx->d_sub_Abase.as<int64_t>();
         m.sub_nlocal = ctx->d_sub_nlocal.as<int>();
         m.alpha = ctx->w_alpha.as<double>();
         m.acc = ctx->d_acc.as<double>();
         m.lam1 = ctx->d_lam1.as<double>();
         m.lam2 = ctx->d_lam2.as<double>();
         m.wsum = ctx->d_wsum.as<double>();
+        const int npairs = (int)(v ? v->pair_sub.size() : ctx->pair_sub.size());
         HIPCHK(launch_accumulate_chunks(m, G.d_awork.as<int4>(), G.nawork, G.d_perm.as<int>(),
-                                        G.d_slot.as<int64_t>(), ctx->d_part.as<double>(), ctx->d_pair_sub.as<int>(),
-                                        ctx->d_pair_k.as<int>(), G.d_item0.as<int>(), (int)ctx->pair_sub.size(),
-                                        ctx->max_ext, st));
+                                        G.d_slot.as<int64_t>(), ctx->d_part.as<double>(),
+                                        v ? v->d_pair_sub.as<int>() : ctx->d_pair_sub.as<int>(),
+                                        v ? v->d_pair_k.as<int>() : ctx->d_pair_k.as<int>(), G.d_item0.as<int>(),
+                                        npairs, ctx->max_ext, st));
         HIPCHK(hipStreamSynchronize(st));  // the group tables are rebuilt by the next chunk
     }
+    ctx->moments_final = false;
+    return SDMM_OK;
+}
+
+int impl_accumulate_moments(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, const double* lambda,
+                            const double* weights, void* stream) {
+    if (!ctx) return SDMM_EINVAL;
+    ctx->view = nullptr;
+    const bool det = ctx->method == SDMM_METHOD_DETERMINISTIC;
+    if (n > 0 && !gidx && y && !det) return fail(ctx, SDMM_EINVAL, "off-grid points need the deterministic method");
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    if (n < 0 || (n > 0 && ((!gidx && !(det && y && weights)) || !lambda)))
+        return fail(ctx, SDMM_EINVAL, "invalid arguments (off-grid points need weights)");
+    if (n == 0) return SDMM_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    if (!det) {
+        if ((rc = check_indices(ctx, gidx, n, st))) return rc;
+        return accumulate_core(ctx, n, gidx, gidx, lambda, weights, st);
+    }
+    // Method S2: the realizations of the last solve, with their own bases
+    DetBatch& D = ctx->det;
+    std::vector<double> pts;
+    if ((rc = det_points(ctx, n, gidx, y, st, pts))) return rc;
+    if (!D.valid || n != D.n || pts != D.y)
+        return fail(ctx, SDMM_ESTATE, "a deterministic basis exists only for the points of the last solve");
+    const int64_t a_end = D.A_base + (int64_t)(D.view.pair_sub.size() - ctx->P.stokes.size()) * 0;
+    (void)a_end;
+    int64_t a_n = 0;
+    for (auto& h : ctx->P.darcy) a_n += n * ((int64_t)h.R + (int64_t)h.R * h.R);
+    HIPCHK(hipMemsetAsync(ctx->d_acc.as<double>() + D.A_base, 0, a_n * 8, st));
+    ctx->view = &D.view;
+    rc = accumulate_core(ctx, n, D.d_pos.as<int64_t>(), gidx, lambda, weights, st);
+    ctx->view = nullptr;
+    if (rc) return rc;
+    // expand this batch's Darcy moments with its own responses and add them
+    const int64_t f1 = ctx->field_size[1], f2 = ctx->field_size[2];
+    double* tmp = D.d_tmp.as<double>();
+    DarcyTables t = darcy_tables(ctx);
+    t.units = D.d_units.as<UnitDev>();
+    t.order = D.d_order.as<int>();
+    t.xi = D.d_xi.as<double>();
+    HIPCHK(launch_darcy_moments_impl(t, D.d_unit_of_dk.as<int>(), D.d_dnlocal.as<int>(), (int)ctx->P.darcy.size(),
+                                     ctx->max_nout_d, (int)n, D.d_dAbase.as<int64_t>(), ctx->d_acc.as<double>(),
+                                     D.d_X.as<double>(), ctx->max_Rd, ctx->d_cell_out.as<int64_t>(),
+                                     ctx->d_edge_out.as<int64_t>(), tmp, tmp + f1, tmp + 2 * f1, tmp + 2 * f1 + f2,
+                                     st));
+    HIPCHK(launch_add_inplace(D.d_sum.as<double>(), tmp, 2 * (f1 + f2), st));
+    HIPCHK(hipStreamSynchronize(st));
     return SDMM_OK;
 }
 
@@ -1770,7 +2386,57 @@ int impl_reset_moments(Prob* ctx) {
     HIPCHK(hipMemset(ctx->d_lam1.p, 0, ctx->d_lam1.bytes));
     HIPCHK(hipMemset(ctx->d_lam2.p, 0, ctx->d_lam2.bytes));
     HIPCHK(hipMemset(ctx->d_wsum.p, 0, 8));
+    if (ctx->det.d_sum.p) HIPCHK(hipMemset(ctx->det.d_sum.p, 0, ctx->det.d_sum.bytes));
+    ctx->moments_final = false;
     return SDMM_OK;
+}
+
+// Expansion of the reduced moments to the fine fields (Section 2 moments of
+// the Darcy and Stokes responses): E[u] = Phi a and E[u^2] = diag(Phi Mc Phi^T)
+// per (subdomain, local realization), into the device field buffers.
+int finalize_moments(Prob* ctx, hipStream_t st) {
+    double* base = ctx->d_mom.as<double>();
+    double* p1 = base;
+    double* p2 = p1 + ctx->field_size[1];
+    double* u1 = p2 + ctx->field_size[1];
+    double* u2 = u1 + ctx->field_size[2];
+    double* su1 = u2 + ctx->field_size[2];
+    double* su2 = su1 + ctx->field_size[3];
+    double* sp1 = su2 + ctx->field_size[3];
+    double* sp2 = sp1 + ctx->field_size[4];
+    HIPCHK(hipEventRecord(ctx->ev[6], st));
+    if (ctx->method == SDMM_METHOD_DETERMINISTIC) {
+        // Method S2: the Darcy moments were expanded batch by batch
+        const size_t nd = (size_t)2 * (ctx->field_size[1] + ctx->field_size[2]);
+        if (ctx->det.d_sum.p)
+            HIPCHK(hipMemcpyAsync(p1, ctx->det.d_sum.p, nd * 8, hipMemcpyDeviceToDevice, st));
+        else
+            HIPCHK(hipMemsetAsync(p1, 0, nd * 8, st));
+    } else {
+        DarcyTables t = darcy_tables(ctx);
+        HIPCHK(launch_darcy_moments_impl(t, ctx->d_unit_of_dk.as<int>(), ctx->d_dnlocal.as<int>(),
+                                         (int)ctx->P.darcy.size(), ctx->max_nout_d, ctx->max_units_per_d,
+                                         ctx->d_dAbase.as<int64_t>(), ctx->d_acc.as<double>(), ctx->d_X.as<double>(),
+                                         ctx->max_Rd, ctx->d_cell_out.as<int64_t>(), ctx->d_edge_out.as<int64_t>(),
+                                         p1, p2, u1, u2, st));
+    }
+    HIPCHK(launch_stokes_moments_impl(ctx->d_sdev.as<StokesDev>(), (int)ctx->sdev.size(), ctx->max_nout_s,
+                                      ctx->d_sAbase.as<int64_t>(), ctx->d_acc.as<double>(), ctx->d_wsum.as<double>(),
+                                      ctx->d_U.as<double>(), ctx->d_P.as<double>(), ctx->d_Z.as<double>(),
+                                      ctx->d_u_out.as<int64_t>(), ctx->d_p_out.as<int64_t>(), ctx->max_ext, su1, su2,
+                                      sp1, sp2, st));
+    HIPCHK(hipEventRecord(ctx->ev[7], st));
+    ctx->moments_final = true;
+    ctx->moments_timed = true;
+    return SDMM_OK;
+}
+
+int impl_finalize_moments(Prob* ctx, void* stream) {
+    if (!ctx) return SDMM_EINVAL;
+    if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
+    if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
+    HIPCHK(hipSetDevice(ctx->device));
+    return finalize_moments(ctx, (hipStream_t)stream);
 }
 
 int impl_get_moments(Prob* ctx, int field, double* mean, double* var, int64_t cap) {
@@ -1786,34 +2452,16 @@ int impl_get_moments(Prob* ctx, int field, double* mean, double* var, int64_t ca
         HIPCHK(hipMemcpy(m1.data(), ctx->d_lam1.p, n * 8, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(m2.data(), ctx->d_lam2.p, n * 8, hipMemcpyDeviceToHost));
     } else {
-        double* base = ctx->d_mom.as<double>();
-        double* p1 = base;
-        double* p2 = p1 + ctx->field_size[1];
-        double* u1 = p2 + ctx->field_size[1];
-        double* u2 = u1 + ctx->field_size[2];
-        double* su1 = u2 + ctx->field_size[2];
-        double* su2 = su1 + ctx->field_size[3];
-        double* sp1 = su2 + ctx->field_size[3];
-        double* sp2 = sp1 + ctx->field_size[4];
-        if (field <= SDMM_FIELD_DARCY_U) {
-            DarcyTables t = darcy_tables(ctx);
-            HIPCHK(launch_darcy_moments_impl(t, ctx->d_unit_of_dk.as<int>(), ctx->d_dnlocal.as<int>(),
-                                             (int)ctx->P.darcy.size(), ctx->max_nout_d, ctx->max_units_per_d,
-                                             ctx->d_dAbase.as<int64_t>(), ctx->d_acc.as<double>(),
-                                             ctx->d_X.as<double>(), ctx->max_Rd, ctx->d_cell_out.as<int64_t>(),
-                                             ctx->d_edge_out.as<int64_t>(), p1, p2, u1, u2, 0));
-        } else {
-            HIPCHK(launch_stokes_moments_impl(ctx->d_sdev.as<StokesDev>(), (int)ctx->sdev.size(), ctx->max_nout_s,
-                                              ctx->d_sAbase.as<int64_t>(), ctx->d_acc.as<double>(),
-                                              ctx->d_wsum.as<double>(), ctx->d_U.as<double>(), ctx->d_P.as<double>(),
-                                              ctx->d_Z.as<double>(), ctx->d_u_out.as<int64_t>(),
-                                              ctx->d_p_out.as<int64_t>(), ctx->max_ext, su1, su2, sp1, sp2, 0));
+        if (!ctx->moments_final) {
+            int rc = finalize_moments(ctx, 0);
+            if (rc) return rc;
+            HIPCHK(hipDeviceSynchronize());
         }
-        HIPCHK(hipDeviceSynchronize());
-        double* s1 = field == 1 ? p1 : field == 2 ? u1 : field == 3 ? su1 : sp1;
-        double* s2 = field == 1 ? p2 : field == 2 ? u2 : field == 3 ? su2 : sp2;
-        HIPCHK(hipMemcpy(m1.data(), s1, n * 8, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(m2.data(), s2, n * 8, hipMemcpyDeviceToHost));
+        double* base = ctx->d_mom.as<double>();
+        int64_t off = 0;
+        for (int f = 1; f < field; ++f) off += 2 * ctx->field_size[f];
+        HIPCHK(hipMemcpy(m1.data(), base + off, n * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(m2.data(), base + off + n, n * 8, hipMemcpyDeviceToHost));
     }
     for (int64_t q = 0; q < n; ++q) {
         mean[q] = m1[q];
@@ -1834,6 +2482,8 @@ int impl_get_counters(Prob* ctx, sdmm_counters* out) {
     if (ctx->basis_built) {
         if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->counters.ms_basis_darcy = ms;
         if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->counters.ms_basis_stokes = ms;
+        if (ctx->moments_timed && hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]) == hipSuccess)
+            ctx->counters.ms_moments = ms;
         if (ctx->built_precision == SDMM_PREC_MIXED && ctx->d_refine.p) {
             double mr;
             int steps;
@@ -1994,6 +2644,20 @@ int sdmm_solve_interface_noalloc(sdmm_ctx* ctx, int64_t id, int64_t n, const int
     WITH_PROB(impl_solve_interface_noalloc(p_, n, gidx, rtol, max_iter, lambda, iters, relres, status, stream));
 }
 
+int sdmm_stream_open(sdmm_ctx* ctx, int64_t id, int64_t slots, double rtol, int32_t max_iter, void* stream,
+                     int64_t* sid) {
+    WITH_PROB(impl_stream_open(p_, slots, rtol, max_iter, stream, sid));
+}
+int sdmm_stream_submit(sdmm_ctx* ctx, int64_t id, int64_t sid, int64_t n, const int64_t* gidx, double* lambda,
+                       int32_t* iters, double* relres, int32_t* status, int64_t* ticket) {
+    WITH_PROB(impl_stream_submit(p_, sid, n, gidx, lambda, iters, relres, status, ticket));
+}
+int sdmm_stream_run(sdmm_ctx* ctx, int64_t id, int64_t sid, int32_t max_groups, int64_t* done, int64_t cap,
+                    int64_t* n_done, int64_t* in_flight) {
+    WITH_PROB(impl_stream_run(p_, sid, max_groups, done, cap, n_done, in_flight));
+}
+int sdmm_stream_close(sdmm_ctx* ctx, int64_t id, int64_t sid) { WITH_PROB(impl_stream_close(p_, sid)); }
+
 int sdmm_noalloc_scratch_bytes(int64_t* bytes) {
     if (!bytes) return SDMM_EINVAL;
     *bytes = (int64_t)kNoAllocScratchBytes;
@@ -2010,6 +2674,7 @@ int sdmm_get_moments(sdmm_ctx* ctx, int64_t id, int field, double* mean, double*
 }
 
 int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id) { WITH_PROB(impl_reset_moments(p_)); }
+int sdmm_finalize_moments(sdmm_ctx* ctx, int64_t id, void* stream) { WITH_PROB(impl_finalize_moments(p_, stream)); }
 
 int sdmm_set_option(sdmm_ctx* ctx, int64_t id, int option, int64_t value) {
     WITH_PROB(impl_set_option(p_, option, value));

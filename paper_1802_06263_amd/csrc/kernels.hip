@@ -155,307 +155,23 @@ hipError_t launch_stokes_pad_identity(const StokesDev* sd, int ns, int max_nblk,
     return hipGetLastError();
 }
 
-// Factor the diagonal tile of block column J: A = L D L^T in place (D on the
-// diagonal, unit L strictly below).
-__global__ __launch_bounds__(kThreads) void stokes_ldl_diag_kernel(const StokesDev* sd, int J, double* tiles) {
-    __shared__ double A[kTile * (kTile + 1)];
-    const StokesDev s = sd[blockIdx.x];
-    if (J >= s.nblk) return;
-    double* T = tile_ptr(tiles, s, J, J);
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
-        const int c = idx / kTile, r = idx % kTile;
-        A[c * (kTile + 1) + r] = T[idx];
-    }
-    __syncthreads();
-    for (int c = 0; c < kTile; ++c) {
-        const double d = A[c * (kTile + 1) + c];
-        const double dinv = 1.0 / d;
-        // trailing update with the unscaled column: A[r][k] -= A[r][c] A[k][c] / d
-        for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
-            const int k = idx / kTile, r = idx % kTile;
-            if (k <= c || r < k) continue;
-            A[k * (kTile + 1) + r] -= A[c * (kTile + 1) + r] * A[c * (kTile + 1) + k] * dinv;
-        }
-        __syncthreads();
-        for (int r = c + 1 + tid; r < kTile; r += blockDim.x) A[c * (kTile + 1) + r] *= dinv;
-        __syncthreads();
-    }
-    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
-        const int c = idx / kTile, r = idx % kTile;
-        T[idx] = r >= c ? A[c * (kTile + 1) + r] : 0.0;
-    }
-}
-
-// Panel: L(I, J) = A(I, J) L(J, J)^{-T} D^{-1} for I = J+1 .. J+w.
-__global__ __launch_bounds__(kThreads) void stokes_ldl_panel_kernel(const StokesDev* sd, int J, double* tiles) {
-    __shared__ double Ld[kTile * (kTile + 1)];
-    __shared__ double B[kTile * (kTile + 1)];
-    const StokesDev s = sd[blockIdx.y];
-    const int I = J + 1 + blockIdx.x;
-    if (J >= s.nblk || (int)blockIdx.x >= s.w || I >= s.nblk) return;
-    const double* Td = tile_ptr(tiles, s, J, J);
-    double* T = tile_ptr(tiles, s, I, J);
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
-        const int c = idx / kTile, r = idx % kTile;
-        Ld[c * (kTile + 1) + r] = Td[idx];
-        B[c * (kTile + 1) + r] = T[idx];
-    }
-    __syncthreads();
-    // each row r: Y[r][c] = B[r][c] - sum_{k<c} Y[r][k] L[c][k]; then / D[c]
-    if (tid < kTile) {
-        const int r = tid;
-        for (int c = 0; c < kTile; ++c) {
-            double v = B[c * (kTile + 1) + r];
-            for (int k = 0; k < c; ++k) v -= B[k * (kTile + 1) + r] * Ld[k * (kTile + 1) + c];
-            B[c * (kTile + 1) + r] = v;  // Y = L(I,J) D
-        }
-        for (int c = 0; c < kTile; ++c) B[c * (kTile + 1) + r] /= Ld[c * (kTile + 1) + c];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
-        const int c = idx / kTile, r = idx % kTile;
-        T[idx] = B[c * (kTile + 1) + r];
-    }
-}
-
-// Trailing update: A(I, K) -= L(I, J) D_J L(K, J)^T for J < K <= I <= J + w.
-__global__ __launch_bounds__(kThreads) void stokes_ldl_update_kernel(const StokesDev* sd, int J, double* tiles) {
-    __shared__ double LI[kTile * (kTile + 1)];
-    __shared__ double LK[kTile * (kTile + 1)];
-    __shared__ double Dd[kTile];
-    const StokesDev s = sd[blockIdx.y];
-    if (J >= s.nblk) return;
-    // decode the pair index p -> (a, c) with 1 <= c <= a <= w
-    int p = blockIdx.x, a = 1;
-    while (p >= a) {
-        p -= a;
-        ++a;
-    }
-    const int c = p + 1;
-    if (a > s.w) return;
-    const int I = J + a, K = J + c;
-    if (I >= s.nblk) return;
-    const double* TI = tile_ptr(tiles, s, I, J);
-    const double* TK = tile_ptr(tiles, s, K, J);
-    const double* Td = tile_ptr(tiles, s, J, J);
-    double* Tt = tile_ptr(tiles, s, I, K);
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < kTile * kTile; idx += blockDim.x) {
-        const int cc = idx / kTile, r = idx % kTile;
-        LI[cc * (kTile + 1) + r] = TI[idx];
-        LK[cc * (kTile + 1) + r] = TK[idx];
-    }
-    if (tid < kTile) Dd[tid] = Td[tid * kTile + tid];
-    __syncthreads();
-    // thread computes a 4 x 4 block of the 64 x 64 target
-    const int br = (tid % 16) * 4, bc = (tid / 16) * 4;
-    double acc[4][4] = {};
-    for (int k = 0; k < kTile; ++k) {
-        const double dk = Dd[k];
-        double li[4], lk[4];
-        for (int q = 0; q < 4; ++q) {
-            li[q] = LI[k * (kTile + 1) + br + q] * dk;
-            lk[q] = LK[k * (kTile + 1) + bc + q];
-        }
-        for (int x = 0; x < 4; ++x)
-            for (int y = 0; y < 4; ++y) acc[x][y] += li[x] * lk[y];
-    }
-    for (int x = 0; x < 4; ++x)
-        for (int y = 0; y < 4; ++y) {
-            const int r = br + x, cc = bc + y;
-            if (I == K && r < cc) continue;
-            Tt[cc * kTile + r] -= acc[x][y];
-        }
-}
-
-hipError_t launch_stokes_ldl_step(const StokesDev* sd, int ns, int J, int max_w, double* tiles, hipStream_t stream) {
-    hipLaunchKernelGGL(stokes_ldl_diag_kernel, dim3(ns), dim3(kThreads), 0, stream, sd, J, tiles);
-    if (max_w > 0) {
-        hipLaunchKernelGGL(stokes_ldl_panel_kernel, dim3(max_w, ns), dim3(kThreads), 0, stream, sd, J, tiles);
-        hipLaunchKernelGGL(stokes_ldl_update_kernel, dim3(max_w * (max_w + 1) / 2, ns), dim3(kThreads), 0, stream, sd,
-                           J, tiles);
-    }
-    return hipGetLastError();
-}
-
-// Solves: forward L y = f, y /= D, backward L^T x = y, on 64-column chunks.
-__global__ __launch_bounds__(kThreads) void stokes_fwd_diag_kernel(const StokesDev* sd, int J, const double* tiles,
-                                                                   double* rhs) {
-    __shared__ double Ld[kTile * (kTile + 1)];
-    const StokesDev s = sd[blockIdx.y];
-    const int c0 = blockIdx.x * kTile;
-    if (J >= s.nblk || c0 >= s.ncol) return;
-    const double* Td = tile_ptr(tiles, s, J, J);
-    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x)
-        Ld[(idx / kTile) * (kTile + 1) + idx % kTile] = Td[idx];
-    __syncthreads();
-    const int col = c0 + threadIdx.x;
-    if (threadIdx.x < kTile && col < s.ncol) {
-        const int64_t ld = (int64_t)s.nblk * kTile;
-        double* x = rhs + s.off_rhs + (int64_t)col * ld + (int64_t)J * kTile;
-        double v[kTile];
-        for (int r = 0; r < kTile; ++r) v[r] = x[r];
-        for (int k = 0; k < kTile; ++k)
-            for (int r = k + 1; r < kTile; ++r) v[r] -= Ld[k * (kTile + 1) + r] * v[k];
-        for (int r = 0; r < kTile; ++r) x[r] = v[r];
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void stokes_fwd_update_kernel(const StokesDev* sd, int J, const double* tiles,
-                                                                     double* rhs) {
-    // X(I) -= L(I, J) X(J), I = J + 1 + blockIdx.x, 64 columns from blockIdx.z
-    __shared__ double Lt[kTile * (kTile + 1)];
-    __shared__ double Xj[kTile * (kTile + 1)];
-    const StokesDev s = sd[blockIdx.y];
-    const int I = J + 1 + blockIdx.x;
-    const int c0 = blockIdx.z * kTile;
-    if (J >= s.nblk || (int)blockIdx.x >= s.w || I >= s.nblk || c0 >= s.ncol) return;
-    const int64_t ld = (int64_t)s.nblk * kTile;
-    const double* T = tile_ptr(tiles, s, I, J);
-    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
-        const int c = idx / kTile, r = idx % kTile;
-        Lt[c * (kTile + 1) + r] = T[idx];
-        Xj[c * (kTile + 1) + r] = (c0 + c < s.ncol) ? rhs[s.off_rhs + (int64_t)(c0 + c) * ld + (int64_t)J * kTile + r] : 0.0;
-    }
-    __syncthreads();
-    const int br = (threadIdx.x % 16) * 4, bc = (threadIdx.x / 16) * 4;
-    double acc[4][4] = {};
-    for (int k = 0; k < kTile; ++k) {
-        double l[4], x[4];
-        for (int q = 0; q < 4; ++q) {
-            l[q] = Lt[k * (kTile + 1) + br + q];
-            x[q] = Xj[(bc + q) * (kTile + 1) + k];
-        }
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) acc[a][b] += l[a] * x[b];
-    }
-    for (int b = 0; b < 4; ++b) {
-        const int col = c0 + bc + b;
-        if (col >= s.ncol) continue;
-        double* xi = rhs + s.off_rhs + (int64_t)col * ld + (int64_t)I * kTile;
-        for (int a = 0; a < 4; ++a) xi[br + a] -= acc[a][b];
-    }
-}
-
-__global__ void stokes_dscale_kernel(const StokesDev* sd, const double* tiles, double* rhs) {
-    const StokesDev s = sd[blockIdx.z];
-    const int64_t ld = (int64_t)s.nblk * kTile;
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int col = blockIdx.y;
-    if (row >= ld || col >= s.ncol) return;
-    const int J = (int)(row / kTile), d = (int)(row % kTile);
-    const double D = tile_ptr(tiles, s, J, J)[d * kTile + d];
-    rhs[s.off_rhs + (int64_t)col * ld + row] /= D;
-}
-
-__global__ __launch_bounds__(kThreads) void stokes_bwd_kernel(const StokesDev* sd, int J, const double* tiles,
-                                                              double* rhs) {
-    // X(J) -= sum_{I = J+1 .. J+w} L(I, J)^T X(I); then X(J) = L(J, J)^{-T} X(J)
-    __shared__ double Lt[kTile * (kTile + 1)];
-    __shared__ double Xi[kTile * (kTile + 1)];
-    const StokesDev s = sd[blockIdx.y];
-    const int c0 = blockIdx.x * kTile;
-    if (J >= s.nblk || c0 >= s.ncol) return;
-    const int64_t ld = (int64_t)s.nblk * kTile;
-    const int br = (threadIdx.x % 16) * 4, bc = (threadIdx.x / 16) * 4;
-    double acc[4][4] = {};
-    for (int a = 1; a <= s.w; ++a) {
-        const int I = J + a;
-        if (I >= s.nblk) break;
-        const double* T = tile_ptr(tiles, s, I, J);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
-            const int c = idx / kTile, r = idx % kTile;
-            Lt[c * (kTile + 1) + r] = T[idx];
-            Xi[c * (kTile + 1) + r] = (c0 + c < s.ncol) ? rhs[s.off_rhs + (int64_t)(c0 + c) * ld + (int64_t)I * kTile + r] : 0.0;
-        }
-        __syncthreads();
-        // out[r][col] += sum_k L(I,J)[k][r] X(I)[k][col]
-        for (int k = 0; k < kTile; ++k) {
-            double l[4], x[4];
-            for (int q = 0; q < 4; ++q) {
-                l[q] = Lt[(br + q) * (kTile + 1) + k];
-                x[q] = Xi[(bc + q) * (kTile + 1) + k];
-            }
-            for (int x1 = 0; x1 < 4; ++x1)
-                for (int y1 = 0; y1 < 4; ++y1) acc[x1][y1] += l[x1] * x[y1];
-        }
-    }
-    __syncthreads();
-    // gather X(J) - acc into Xi (reuse), then triangular solve with L(J,J)^T
-    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x) {
-        const int c = idx / kTile, r = idx % kTile;
-        Xi[c * (kTile + 1) + r] = (c0 + c < s.ncol) ? rhs[s.off_rhs + (int64_t)(c0 + c) * ld + (int64_t)J * kTile + r] : 0.0;
-    }
-    const double* Td = tile_ptr(tiles, s, J, J);
-    for (int idx = threadIdx.x; idx < kTile * kTile; idx += blockDim.x)
-        Lt[(idx / kTile) * (kTile + 1) + idx % kTile] = Td[idx];
-    __syncthreads();
-    for (int x1 = 0; x1 < 4; ++x1)
-        for (int y1 = 0; y1 < 4; ++y1) Xi[(bc + y1) * (kTile + 1) + br + x1] -= acc[x1][y1];
-    __syncthreads();
-    const int col = c0 + threadIdx.x;
-    if (threadIdx.x < kTile && col < s.ncol) {
-        double v[kTile];
-        for (int r = 0; r < kTile; ++r) v[r] = Xi[threadIdx.x * (kTile + 1) + r];
-        for (int r = kTile - 1; r >= 0; --r)
-            for (int k = r + 1; k < kTile; ++k) v[r] -= Lt[r * (kTile + 1) + k] * v[k];
-        double* x = rhs + s.off_rhs + (int64_t)col * ld + (int64_t)J * kTile;
-        for (int r = 0; r < kTile; ++r) x[r] = v[r];
-    }
-}
-
-hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol, const double* tiles,
-                               double* rhs, hipStream_t stream) {
-    const int nchunk = (max_ncol + kTile - 1) / kTile;
-    for (int J = 0; J < max_nblk; ++J) {
-        hipLaunchKernelGGL(stokes_fwd_diag_kernel, dim3(nchunk, ns), dim3(kThreads), 0, stream, sd, J, tiles, rhs);
-        if (max_w > 0)
-            hipLaunchKernelGGL(stokes_fwd_update_kernel, dim3(max_w, ns, nchunk), dim3(kThreads), 0, stream, sd, J,
-                               tiles, rhs);
-    }
-    hipLaunchKernelGGL(stokes_dscale_kernel, dim3((max_nblk * kTile + 255) / 256, max_ncol, ns), dim3(256), 0, stream,
-                       sd, tiles, rhs);
-    for (int J = max_nblk - 1; J >= 0; --J)
-        hipLaunchKernelGGL(stokes_bwd_kernel, dim3(nchunk, ns), dim3(kThreads), 0, stream, sd, J, tiles, rhs);
-    return hipGetLastError();
-}
-
-// res = b - A x for every right-hand side column (one thread per band row;
-// padding rows get 0).
-__global__ void stokes_residual_kernel(const StokesDev* sd, const int64_t* __restrict__ cptr,
-                                       const int* __restrict__ ccol, const double* __restrict__ cval,
-                                       const double* __restrict__ b, const double* __restrict__ x,
-                                       double* __restrict__ res) {
-    const StokesDev s = sd[blockIdx.z];
-    const int col = blockIdx.y;
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ld = (int64_t)s.nblk * kTile;
-    if (col >= s.ncol || row >= ld) return;
-    const int64_t base = s.off_rhs + (int64_t)col * ld;
-    double r = 0.0;
-    if (row < s.nband) {
-        r = b[base + row];
-        const int64_t q0 = cptr[s.off_cptr + row], q1 = cptr[s.off_cptr + row + 1];
-        for (int64_t q = q0; q < q1; ++q) r -= cval[q] * x[base + ccol[q]];
-    }
-    res[base + row] = r;
-}
-
-hipError_t launch_stokes_residual(const StokesDev* sd, int ns, int max_nblk, int max_ncol, const int64_t* cptr,
-                                  const int* ccol, const double* cval, const double* b, const double* x, double* res,
-                                  hipStream_t stream) {
-    if (ns <= 0) return hipSuccess;
-    hipLaunchKernelGGL(stokes_residual_kernel, dim3((max_nblk * kTile + 255) / 256, max_ncol, ns), dim3(256), 0,
-                       stream, sd, cptr, ccol, cval, b, x, res);
-    return hipGetLastError();
-}
+#include "stokes_tiled.inc"
 
 __global__ void add_inplace_kernel(double* __restrict__ x, const double* __restrict__ d, int64_t n) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
         x[q] += d[q];
+}
+
+__global__ void fill_zero_kernel(double* __restrict__ x, int64_t n) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        x[q] = 0.0;
+}
+
+hipError_t launch_fill_zero(double* x, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_add_inplace(double* x, const double* d, int64_t n, hipStream_t stream) {
@@ -916,6 +632,34 @@ __global__ void count_active_kernel(const int32_t* active, int64_t n, int32_t* c
 
 hipError_t launch_count_active(const int32_t* active, int64_t n, int32_t* count, hipStream_t stream) {
     hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(256), 0, stream, active, n, count);
+    return hipGetLastError();
+}
+
+// Finished realizations of a CG stream to their callers' buffers: row
+// slot[q] of lam (M values) to dst_lam[q], and its iteration count, relative
+// residual and status to the optional per-realization destinations.
+__global__ void stream_gather_kernel(const double* __restrict__ lam, int M, const int* __restrict__ slot,
+                                     double* const* __restrict__ dst_lam, const int32_t* __restrict__ it,
+                                     const double* __restrict__ rel, const int32_t* __restrict__ stat,
+                                     int32_t* const* __restrict__ dst_it, double* const* __restrict__ dst_rel,
+                                     int32_t* const* __restrict__ dst_st) {
+    const int q = blockIdx.x;
+    const int64_t l = slot[q];
+    double* d = dst_lam[q];
+    for (int m = threadIdx.x; m < M; m += blockDim.x) d[m] = lam[l * M + m];
+    if (threadIdx.x == 0) {
+        if (dst_it[q]) *dst_it[q] = it[l];
+        if (dst_rel[q]) *dst_rel[q] = rel[l];
+        if (dst_st[q]) *dst_st[q] = stat[l];
+    }
+}
+
+hipError_t launch_stream_gather(const double* lam, int M, const int* slot, double* const* dst_lam, const int32_t* it,
+                                const double* rel, const int32_t* stat, int32_t* const* dst_it,
+                                double* const* dst_rel, int32_t* const* dst_st, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stream_gather_kernel, dim3(n), dim3(256), 0, stream, lam, M, slot, dst_lam, it, rel, stat,
+                       dst_it, dst_rel, dst_st);
     return hipGetLastError();
 }
 

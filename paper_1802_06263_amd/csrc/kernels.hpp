@@ -78,20 +78,26 @@ struct StokesDev {
     int64_t off_dofs;   // local->global mortar DOFs
     int64_t off_G;      // first column of this subdomain's kernel traces in G
     int64_t off_cptr;   // CSR row pointer base of the full band matrix (nband + 1)
+    int64_t off_linv;   // L(J, J)^{-1} of every block column (nblk x 64 x 64)
 };
 
 hipError_t launch_stokes_scatter(const StokesDev* sd, int ns, const int* tr_sub, const int* tr_r, const int* tr_c,
                                  const double* tr_v, int64_t ntrip, double* tiles, hipStream_t stream);
 hipError_t launch_stokes_pad_identity(const StokesDev* sd, int ns, int max_nblk, double* tiles, hipStream_t stream);
-hipError_t launch_stokes_ldl_step(const StokesDev* sd, int ns, int J, int max_w, double* tiles, hipStream_t stream);
-hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol, const double* tiles,
-                               double* rhs, hipStream_t stream);
-// FP64 iterative refinement of the band solves: res = b - A x with the full
-// band matrix in CSR (fixed summation order), then x += d after d = A^{-1} res.
-hipError_t launch_stokes_residual(const StokesDev* sd, int ns, int max_nblk, int max_ncol, const int64_t* cptr,
-                                  const int* ccol, const double* cval, const double* b, const double* x, double* res,
+// one block column J of the band LDL^T (diagonal tile, panel, trailing update)
+hipError_t launch_stokes_ldl_step(const StokesDev* sd, int ns, int J, int max_w, double* tiles, double* linv,
                                   hipStream_t stream);
+// x := A^{-1} x for all R + 1 columns (tmp: work array of the size of x)
+hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol, const double* tiles,
+                               const double* linv, double* x, double* tmp, hipStream_t stream);
+// FP64 iterative refinement of the band solves: res = b - A x with the
+// assembled band matrix (tiles0; fixed summation order), then x += d after
+// d = A^{-1} res.
+hipError_t launch_stokes_residual(const StokesDev* sd, int ns, int max_nblk, int max_ncol, const double* tiles0,
+                                  const double* b, const double* x, double* res, hipStream_t stream);
 hipError_t launch_add_inplace(double* x, const double* d, int64_t n, hipStream_t stream);
+// x[0 .. n) = 0 with a kernel (graph-safe, unlike a memset node)
+hipError_t launch_fill_zero(double* x, int64_t n, hipStream_t stream);
 hipError_t launch_stokes_finish(const StokesDev* sd, int ns, int max_ncol, int max_R, const double* rhs, const int* bmap,
                                 const double* uD, const int64_t* uD_off, const double* Z, const int* q_ptr,
                                 const int* q_col, const double* q_val, const int64_t* dofs, double* U, double* P,
@@ -150,6 +156,10 @@ hipError_t launch_gather_global(const double* Y, int64_t SR, const int* pos, int
 hipError_t launch_cg_update2(const CgArgs& a, const double* Y, int64_t SR, const int* pos, hipStream_t stream,
                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_count_active(const int32_t* active, int64_t n, int32_t* count, hipStream_t stream);
+// copy finished realizations (CG slot slot[q]) to their callers' buffers
+hipError_t launch_stream_gather(const double* lam, int M, const int* slot, double* const* dst_lam, const int32_t* it,
+                                const double* rel, const int32_t* stat, int32_t* const* dst_it,
+                                double* const* dst_rel, int32_t* const* dst_st, int n, hipStream_t stream);
 
 // Moments
 struct MomArgs {

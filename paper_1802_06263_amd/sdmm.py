@@ -48,7 +48,7 @@ class CCounters(ctypes.Structure):
                                               "units_built", "refinement_steps", "cg_iterations", "realizations")] + \
                [(n, ctypes.c_double) for n in ("ms_basis_darcy", "ms_basis_stokes", "ms_solve", "max_refine_residual")] + \
                [(n, ctypes.c_int64) for n in ("cg_launches", "cg_timed_launches", "cg_timed_active", "cg_timed_columns")] + \
-               [(n, ctypes.c_double) for n in ("ms_cg_apply", "ms_cg_update")]
+               [(n, ctypes.c_double) for n in ("ms_cg_apply", "ms_cg_update", "ms_moments")]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)
@@ -75,15 +75,20 @@ EXPORTS = {
     "sdmm_solve_interface": (ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _f64, _i32, _vp, _vp, _vp, _vp, _vp]),
     "sdmm_solve_interface_noalloc": (ctypes.c_int, [_vp, _i64, _i64, _vp, _f64, _i32, _vp, _vp, _vp, _vp, _vp]),
     "sdmm_noalloc_scratch_bytes": (ctypes.c_int, [_i64p]),
+    "sdmm_stream_open": (ctypes.c_int, [_vp, _i64, _i64, _f64, _i32, _vp, _i64p]),
+    "sdmm_stream_submit": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64p, _vp, _vp, _vp, _vp, _i64p]),
+    "sdmm_stream_run": (ctypes.c_int, [_vp, _i64, _i64, _i32, _i64p, _i64, _i64p, _i64p]),
+    "sdmm_stream_close": (ctypes.c_int, [_vp, _i64, _i64]),
     "sdmm_get_interface_data": (ctypes.c_int, [_vp, _i64, _f64p, _f64p]),
     "sdmm_autotune": (ctypes.c_int, [_vp, _i64, _i64, _vp, _f64, _i32, _vp, _i64p]),
     "sdmm_accumulate_moments": (ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp]),
     "sdmm_get_moments": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _f64p, _f64p, _i64]),
     "sdmm_reset_moments": (ctypes.c_int, [_vp, _i64]),
+    "sdmm_finalize_moments": (ctypes.c_int, [_vp, _i64, _vp]),
     "sdmm_get_counters": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(CCounters)]),
     "sdmm_set_option": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _i64]),
 }
-OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2, "kernel_timing": 3, "cg_lanes": 4}
+OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2, "kernel_timing": 3, "cg_lanes": 4, "stokes_rebuild": 5}
 
 _LIB = None
 
@@ -159,6 +164,11 @@ class Context:
     method takes an optional problem id `pid` instead."""
 
     def __init__(self, device=0, torch_alloc=False):
+        if device >= 0:
+            # torch brings its own HIP runtime; it must be initialised before the
+            # library's first HIP call, or torch no longer sees the device
+            import torch
+            torch.cuda.init()
         self.lib = load()
         h = ctypes.c_void_p()
         self._alloc_keep = None
@@ -325,6 +335,37 @@ class Context:
         self._check(self.lib.sdmm_noalloc_scratch_bytes(ctypes.byref(out)))
         return out.value
 
+    # ---- CG streams (continuous batching) -------------------------------------
+    def stream_open(self, slots, rtol=1e-8, max_iter=None, stream=None, pid=None):
+        sz = self._sz[self._id(pid).value]
+        if max_iter is None:
+            max_iter = 10 * sz["M"]
+        sid = ctypes.c_int64()
+        self._check(self.lib.sdmm_stream_open(self.h, self._id(pid), int(slots), float(rtol), int(max_iter),
+                                              _stream(stream), ctypes.byref(sid)))
+        return sid.value
+
+    def stream_submit(self, sid, gidx, lam, iters=None, relres=None, status=None, pid=None):
+        """gidx: host int64 array; lam (n x M) and the optional outputs: device tensors."""
+        g = _arr(gidx, np.int64)
+        t = ctypes.c_int64()
+        self._check(self.lib.sdmm_stream_submit(self.h, self._id(pid), sid, g.size, _ptr(g, ctypes.c_int64),
+                                                _dptr(lam), _dptr(iters), _dptr(relres), _dptr(status),
+                                                ctypes.byref(t)))
+        return t.value
+
+    def stream_run(self, sid, max_groups=1, pid=None, cap=4096):
+        """Advance the stream; returns (completed tickets, realizations in flight or queued)."""
+        done = np.zeros(cap, dtype=np.int64)
+        nd = ctypes.c_int64()
+        fl = ctypes.c_int64()
+        self._check(self.lib.sdmm_stream_run(self.h, self._id(pid), sid, int(max_groups), _ptr(done, ctypes.c_int64),
+                                             cap, ctypes.byref(nd), ctypes.byref(fl)))
+        return done[:nd.value].tolist(), fl.value
+
+    def stream_close(self, sid, pid=None):
+        self._check(self.lib.sdmm_stream_close(self.h, self._id(pid), sid))
+
     def interface_data(self, pid=None):
         """(g_H [M], G [n_kernel x M]) as host arrays."""
         sz = self._sz[self._id(pid).value]
@@ -358,6 +399,9 @@ class Context:
         self._check(self.lib.sdmm_get_moments(self.h, self._id(pid), FIELDS[field], _ptr(mean, ctypes.c_double),
                                               _ptr(var, ctypes.c_double), mean.size))
         return mean[:n], var[:n]
+
+    def finalize_moments(self, stream=None, pid=None):
+        self._check(self.lib.sdmm_finalize_moments(self.h, self._id(pid), _stream(stream)))
 
     def reset_moments(self, pid=None):
         self._check(self.lib.sdmm_reset_moments(self.h, self._id(pid)))

@@ -1,4 +1,4 @@
-"""Serving loop: batches of collocation realizations against resident flux bases.
+"""Serving loop: requests of collocation realizations against resident flux bases.
 
 A request names a problem and a batch of global collocation indices (the
 points of the collocation rule of Section 4); the answer is the mortar
@@ -8,19 +8,25 @@ problem's running moments (Section 2).
 
 Design:
   * one Engine per problem: a library context whose flux basis stays
-    resident in HBM, one HIP stream and one worker thread.  Workers spend
-    their time inside the C library (ctypes releases the GIL), so requests of
-    different problems run concurrently on the device.
-  * continuous batching: when its worker is free, an engine takes every
-    queued request (oldest first) up to its admitted batch size and solves
-    them as one batch.  A realization's result does not depend on the batch
-    it rides in (fixed-order reductions in the library), so batching never
-    changes answers.
-  * admission: engines are admitted only while their resident HBM footprint
-    (basis cache, fine responses, CG workspace of one batch) fits the budget;
-    a request is rejected when its engine already holds max_pending queued
-    realizations.
-  * latency is measured from the request's arrival to the end of its batch.
+    resident in HBM, one HIP stream, one CG stream of the library
+    (sdmm_stream_*) and one worker thread.  Workers spend their time inside
+    the C library (ctypes releases the GIL), so requests of different
+    problems run concurrently on the device.
+  * continuous batching at the level of CG iterations: the CG stream keeps a
+    fixed number of slots (the autotuned count); at every convergence check
+    (64 iterations) finished realizations leave their slots and realizations
+    of any queued request take the freed ones.  A request that arrives while
+    others iterate starts at the next check, not after a whole batch.  A
+    realization's result does not depend on what shares the slots with it
+    (fixed-order reductions in the library), so batching never changes
+    answers.
+  * admission by HBM footprint, per request: a request enters its engine's
+    CG stream only while the device bytes it holds (its lambda and status
+    outputs) fit in the budget left after every engine's resident footprint
+    (basis cache, fine responses, CG stream workspace); otherwise it waits
+    and is admitted as completed requests release their bytes.  A request is
+    rejected when its engine already holds max_pending waiting realizations.
+  * latency is measured from the request's arrival to its completion.
 
 Run ``python -m paper_1802_06263_amd.serve --help``.
 """
@@ -35,7 +41,8 @@ import numpy as np
 
 
 class Request:
-    __slots__ = ("rid", "problem", "gidx", "t_arrival", "t_done", "lam", "iters", "status", "rejected", "event")
+    __slots__ = ("rid", "problem", "gidx", "t_arrival", "t_done", "lam", "iters", "status", "rejected", "event",
+                 "footprint")
 
     def __init__(self, rid, problem, gidx, t_arrival):
         self.rid = rid
@@ -48,33 +55,41 @@ class Request:
         self.status = None
         self.rejected = False
         self.event = threading.Event()
+        self.footprint = 0
 
 
-def footprint_bytes(sizes, batch):
-    """Resident device bytes of one engine: basis cache, fine responses and the
-    CG state of one batch (r, p, S lambda and lambda itself, M each, and the
-    product in the subdomain-local layout, 2 M)."""
+def footprint_bytes(sizes, slots):
+    """Resident device bytes of one engine: basis cache, fine responses and
+    the workspace of a CG stream with `slots` slots (r, p, lambda, M each,
+    the product in the subdomain-local layout, about 2 M, and per-slot
+    scalars)."""
     M = sizes["M"]
-    per_real = 8 * (6 * M + 64)
-    return sizes["basis_bytes"] + sizes["response_bytes"] + batch * per_real
+    per_slot = 8 * (5 * M + 16)
+    return sizes["basis_bytes"] + sizes["response_bytes"] + slots * per_slot
+
+
+def request_bytes(M, n):
+    """Device bytes a request of n realizations holds while in flight: its
+    lambda (n x M) and iteration-count and status outputs."""
+    return n * (8 * M + 8)
 
 
 class Engine:
-    """One problem on the device: resident basis, a stream and a worker."""
+    """One problem on the device: resident basis, a CG stream and a worker."""
 
-    def __init__(self, name, prob, precision="fp64", max_batch=4096, max_pending=1 << 20, rtol=1e-8,
-                 accumulate=True, autotune=True, backend=None):
+    def __init__(self, name, prob, precision="fp64", max_pending=1 << 20, rtol=1e-8, accumulate=True,
+                 autotune=True, slots=None, backend=None):
         self.name = name
-        self.rtol = rtol
         self.max_pending = max_pending
         self.accumulate = accumulate
-        self.backend = backend if backend is not None else GpuBackend(prob, precision, autotune, max_batch)
-        self.max_batch = min(max_batch, self.backend.max_batch)
+        self.backend = backend if backend is not None else GpuBackend(prob, precision, autotune, slots, rtol)
         self.queue = collections.deque()
-        self.pending = 0
+        self.pending = 0          # realizations waiting for admission
+        self.inflight = {}        # ticket -> request (worker thread only)
         self.cv = threading.Condition()
         self.stop = False
-        self.batches = []       # (n_requests, n_realizations, seconds)
+        self.server = None
+        self.runs = []            # per CG check group: (requests in flight, realizations in flight, seconds)
         self.thread = threading.Thread(target=self._run, name="engine-" + name, daemon=True)
 
     def start(self):
@@ -98,101 +113,152 @@ class Engine:
         self.thread.join()
         self.backend.close()
 
-    def _take(self):
-        batch, n = [], 0
-        while self.queue and (not batch or n + self.queue[0].gidx.size <= self.max_batch):
-            r = self.queue.popleft()
-            batch.append(r)
-            n += r.gidx.size
-        self.pending -= n
-        return batch, n
+    def _admit(self):
+        """Queued requests into the CG stream while their bytes fit (oldest first)."""
+        while self.queue:
+            r = self.queue[0]
+            fp = self.backend.request_bytes(r.gidx.size)
+            if self.server is not None and not self.server.reserve(fp):
+                break
+            self.queue.popleft()
+            self.pending -= r.gidx.size
+            r.footprint = fp
+            self.inflight[self.backend.submit(r.gidx)] = r
 
     def _run(self):
         while True:
             with self.cv:
-                while not self.queue and not self.stop:
+                while not self.queue and not self.inflight and not self.stop:
                     self.cv.wait()
-                if self.stop and not self.queue:
+                if self.stop and not self.queue and not self.inflight:
                     return
-                batch, n = self._take()
+                self._admit()
+                if not self.inflight:
+                    self.cv.wait(0.001)   # every queued request waits for device memory
+                    continue
+            nreq = len(self.inflight)
+            nreal = sum(r.gidx.size for r in self.inflight.values())
             t0 = time.perf_counter()
-            gidx = np.concatenate([r.gidx for r in batch])
-            lam, iters, status = self.backend.solve(gidx, self.rtol, self.accumulate)
+            done = self.backend.run(1)
             t1 = time.perf_counter()
-            self.batches.append((len(batch), n, t1 - t0))
-            off = 0
-            for r in batch:
-                k = r.gidx.size
-                r.lam, r.iters, r.status = lam[off:off + k], iters[off:off + k], status[off:off + k]
-                r.t_done = t1
-                off += k
+            self.runs.append((nreq, nreal, t1 - t0))
+            for t in done:
+                r = self.inflight.pop(t)
+                r.lam, r.iters, r.status = self.backend.result(t, self.accumulate)
+                r.t_done = time.perf_counter()
+                if self.server is not None:
+                    self.server.release(r.footprint)
                 r.event.set()
 
 
 class GpuBackend:
-    """Library context of one problem with its basis built and resident."""
+    """Library context of one problem with its basis resident and one CG stream."""
 
-    batch_per_slots = 2   # largest batch, in multiples of the autotuned CG slot count
-
-    def __init__(self, prob, precision, autotune, max_batch):
+    def __init__(self, prob, precision, autotune, slots, rtol):
         import torch
         from . import sdmm
         self.torch = torch
         self.ctx = sdmm.Context(0)
         self.ctx.set_problem(prob)
-        # the engines already overlap on the device; lanes would add streams
-        # beyond the device's hardware queues
-        self.ctx.set_option("cg_lanes", 1)
         self.sizes = self.ctx.sizes()
         self.stream = torch.cuda.Stream()
         self.ctx.build_flux_basis(precision, stream=self.stream)
         self.stream.synchronize()
         self.M = self.sizes["M"]
-        self.max_batch = max_batch
-        if autotune:
-            n = min(self.sizes["n_real"], 8192)
-            g = torch.arange(n, dtype=torch.int64, device="cuda")
-            # the CG refills its slots from the batch, so a batch may hold more
-            # realizations than there are slots without draining between them
-            slots = self.ctx.autotune(g, stream=self.stream)
-            self.max_batch = min(max_batch, max(256, self.batch_per_slots * slots))
-            self.stream.synchronize()
+        if slots is None:
+            if autotune:
+                n = min(self.sizes["n_real"], 8192)
+                g = torch.arange(n, dtype=torch.int64, device="cuda")
+                slots = self.ctx.autotune(g, stream=self.stream)
+                self.stream.synchronize()
+            else:
+                slots = 1024
+        self.slots = slots
+        self.sid = self.ctx.stream_open(slots, rtol=rtol, stream=self.stream)
+        self.out = {}
 
-    def solve(self, gidx, rtol, accumulate):
+    def request_bytes(self, n):
+        return request_bytes(self.M, n)
+
+    def submit(self, gidx):
+        torch = self.torch
+        n = gidx.size
+        lam = torch.empty((n, self.M), dtype=torch.float64, device="cuda")
+        it = torch.empty(n, dtype=torch.int32, device="cuda")
+        st = torch.empty(n, dtype=torch.int32, device="cuda")
+        t = self.ctx.stream_submit(self.sid, gidx, lam, iters=it, status=st)
+        self.out[t] = (gidx, lam, it, st)
+        return t
+
+    def run(self, groups):
+        done, _ = self.ctx.stream_run(self.sid, groups)
+        return done
+
+    def result(self, ticket, accumulate):
+        torch = self.torch
+        gidx, lam, it, st = self.out.pop(ticket)
+        with torch.cuda.stream(self.stream):
+            if accumulate:
+                g = torch.from_numpy(gidx).to("cuda", non_blocking=False)
+                self.ctx.accumulate_moments(g, lam, stream=self.stream)
+            out = lam.to("cpu"), it.to("cpu"), st.to("cpu")
+        self.stream.synchronize()
+        return out[0].numpy(), out[1].numpy(), out[2].numpy()
+
+    def solve_alone(self, gidx, rtol):
+        """The same realizations through sdmm_solve_interface (for checks)."""
         torch = self.torch
         n = gidx.size
         with torch.cuda.stream(self.stream):
-            g = torch.from_numpy(gidx).to("cuda", non_blocking=False)
+            g = torch.from_numpy(np.asarray(gidx, dtype=np.int64)).to("cuda")
             lam = torch.empty((n, self.M), dtype=torch.float64, device="cuda")
             it = torch.empty(n, dtype=torch.int32, device="cuda")
             st = torch.empty(n, dtype=torch.int32, device="cuda")
             self.ctx.solve_interface(g, lam, rtol=rtol, iters=it, status=st, stream=self.stream, allow_notconv=True)
-            if accumulate:
-                self.ctx.accumulate_moments(g, lam, stream=self.stream)
-            out = lam.to("cpu", non_blocking=False), it.to("cpu"), st.to("cpu")
+            out = lam.to("cpu"), it.to("cpu"), st.to("cpu")
         self.stream.synchronize()
         return out[0].numpy(), out[1].numpy(), out[2].numpy()
 
     def close(self):
         self.stream.synchronize()
+        self.ctx.stream_close(self.sid)
         self.ctx.close()
 
 
 class Server:
-    """Engines for several problems plus admission by HBM footprint."""
+    """Engines for several problems plus admission by HBM footprint: every
+    engine's resident bytes when it is added, every request's bytes while it
+    is in flight."""
 
     def __init__(self, hbm_budget_bytes=200 << 30):
         self.engines = {}
         self.budget = hbm_budget_bytes
         self.used = 0
+        self.lock = threading.Lock()
 
     def add(self, engine, footprint):
-        if self.used + footprint > self.budget:
-            raise MemoryError("engine %s needs %d bytes, %d of %d in use" % (engine.name, footprint, self.used,
-                                                                           self.budget))
-        self.used += footprint
+        with self.lock:
+            if self.used + footprint > self.budget:
+                raise MemoryError("engine %s needs %d bytes, %d of %d in use" % (engine.name, footprint, self.used,
+                                                                               self.budget))
+            self.used += footprint
         self.engines[engine.name] = engine
+        engine.server = self
         engine.start()
+
+    def reserve(self, nbytes):
+        with self.lock:
+            if self.used + nbytes > self.budget:
+                return False
+            self.used += nbytes
+            return True
+
+    def release(self, nbytes):
+        with self.lock:
+            self.used -= nbytes
+        for e in self.engines.values():
+            with e.cv:
+                e.cv.notify()
 
     def submit(self, req):
         return self.engines[req.problem].submit(req)
@@ -238,12 +304,12 @@ def summarize(reqs, wall_s):
     return out
 
 
-def build_server(problems, precision, max_batch, budget_gb):
+def build_server(problems, precision, budget_gb):
     from workloads import problem
     server = Server(int(budget_gb * (1 << 30)))
     for name in problems:
-        e = Engine(name, problem(name), precision=precision, max_batch=max_batch)
-        server.add(e, footprint_bytes(e.backend.sizes, e.max_batch))
+        e = Engine(name, problem(name), precision=precision)
+        server.add(e, footprint_bytes(e.backend.sizes, e.backend.slots))
     return server
 
 
@@ -253,13 +319,12 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--duration", type=float, default=10.0, help="seconds of the arrival stream")
     ap.add_argument("--rates", default="200", help="arrival rates (requests/s), comma separated")
-    ap.add_argument("--max-batch", type=int, default=8192)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=4)
     args = ap.parse_args(argv)
     from workloads import serving_stream
     problems = tuple(args.problems.split(","))
-    server = build_server(problems, args.precision, args.max_batch, args.budget_gb)
+    server = build_server(problems, args.precision, args.budget_gb)
     sizes = {p: server.engines[p].backend.sizes["n_real"] for p in problems}
 
     def log(msg):
@@ -274,7 +339,11 @@ def main(argv=None):
         out = summarize(reqs, time.perf_counter() - t0)
         out.update({"rate_hz": rate, "offered_realizations_per_s": sum(g.size for _, _, g in stream) / args.duration,
                     "precision": args.precision, "duration_s": args.duration,
-                    "max_batch": {p: server.engines[p].max_batch for p in problems}})
+                    "cg_slots": {p: server.engines[p].backend.slots for p in problems},
+                    "requests_in_flight_per_check": {
+                        p: float(np.mean([x[0] for x in server.engines[p].runs] or [0])) for p in problems}})
+        for e in server.engines.values():
+            e.runs.clear()
         print(json.dumps(out), flush=True)
     server.close()
 

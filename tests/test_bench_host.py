@@ -20,28 +20,29 @@ def _counters(nl=10, active=1000.0, ms_apply=0.4, ms_update=0.4):
 
 
 def test_rooflines_price_each_kernel_against_its_bound():
-    # 6561-realization layout: sum R_i = 2560, sum R_i^2 = 181248, M = 1280
+    # 6561-realization layout: sum R_i^2 = 181248, M = 1280
     sz = {"M": 1280, "darcy_flops": 21.7e9}
-    k = bench.kernel_rooflines(sz, 2560, 181248, _counters(), 6.4, "fp64", "no-such-workload")
+    ms = {"basis_darcy": 6.4}
+    k = bench.kernel_rooflines(sz, 1280, 181248, _counters(), ms, "fp64", "no-such-workload")
     for name in ("cg_update", "cg_apply", "darcy_basis"):
         assert ROOF_KEYS <= set(k[name]), name
         assert 0 < k[name]["frac"] and k[name]["achieved"] / k[name]["peak"] == pytest.approx(k[name]["frac"])
     upd = k["cg_update"]
     assert upd["bound"] == "hbm" and upd["unit"] == "GB/s" and upd["peak"] == 8000.0
-    # 8 (sum R_i + 6 M) bytes per realization-iteration, 1000 active, 40 us per launch
-    assert upd["bytes_per_unit"] == 8 * (2560 + 6 * 1280)
+    # an unfused update streams 7 M doubles per realization-iteration; 1000 active, 40 us per launch
+    assert upd["bytes_per_unit"] == 7 * 1280 * 8
     assert upd["achieved"] == pytest.approx(upd["bytes_per_unit"] * 1000 / 40e-6 / 1e9)
-    # 11.8 flop/B is above the FP64 MFMA ridge (78.6 / 8 = 9.8): priced against MFMA
+    # the product: 2 sum R_i^2 flops per realization-iteration on FP64 MFMA
     app = k["cg_apply"]
     assert app["bound"] == "mfma" and app["unit"] == "TFLOP/s" and app["peak"] == 78.6
     assert app["achieved"] == pytest.approx(2 * 181248 * 1000 / 40e-6 / 1e12)
+    # the FP64 basis build against the FP64 MFMA peak, the mixed one against FP32 MFMA
     assert k["darcy_basis"]["bound"] == "mfma" and k["darcy_basis"]["peak"] == 78.6
-    # the uneven layout: 2 sum R_i^2 = 203,904 flops against 23,040 bytes (8.9 flop/B) is HBM-bound
-    k3 = bench.kernel_rooflines({"M": 960, "darcy_flops": 313e9}, 1920, 101952, _counters(), 42.0, "mixed",
-                                "no-such-workload")
-    assert k3["cg_apply"]["bound"] == "hbm" and k3["cg_apply"]["unit"] == "GB/s"
+    assert k["darcy_basis"]["achieved"] == pytest.approx(21.7e9 / 6.4e-3 / 1e12)
+    km = bench.kernel_rooflines(sz, 1280, 181248, _counters(), ms, "mixed", "no-such-workload")
+    assert km["darcy_basis"]["peak"] == 157.3
     # no counter summary for an unknown workload: traffic is null, not guessed
-    assert k3["cg_apply"]["traffic"] is None and k3["cg_update"]["traffic"] is None
+    assert km["cg_apply"]["traffic"] is None and km["cg_update"]["traffic"] is None
 
 
 def test_traffic_is_reported_only_for_the_profiled_kernel_source():
@@ -66,13 +67,23 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_whole_cg_figure_adds_both_kernels():
-    """The whole-CG figure counts the product's and the update's algorithmic
-    bytes, 8 (M + sum R_i) + 8 (sum R_i + 6 M) per realization-iteration, and
-    the product's 2 sum R_i^2 flops, over the CG wall time."""
-    w = bench.cg_whole(2560, 181248, 1280, 1.0e6, 100.0)
-    assert w["bytes_per_unit"] == 8 * (1280 + 2560) + 8 * (2560 + 6 * 1280) == 112640
-    assert w["gbps"] == pytest.approx(112640 * 1.0e6 / 0.1 / 1e9)
+def test_whole_cg_figure_uses_the_scope_table_counts():
+    """The whole-CG figure prices a realization-iteration at 5 M 8 bytes (the
+    CG vectors streamed once) and 2 sum R_i^2 flops, over the CG wall time."""
+    w = bench.cg_whole(1280, 181248, 1.0e6, 100.0)
+    assert w["bytes_per_unit"] == 5 * 1280 * 8 == 51200
+    assert w["flops_per_unit"] == 2 * 181248 == 362496
+    assert w["gbps"] == pytest.approx(51200 * 1.0e6 / 0.1 / 1e9)
     assert w["frac_hbm"] == pytest.approx(w["gbps"] / 8000.0)
-    assert w["tflops"] == pytest.approx(2 * 181248 * 1.0e6 / 0.1 / 1e12)
+    assert w["tflops"] == pytest.approx(362496 * 1.0e6 / 0.1 / 1e12)
     assert w["frac_fp64_mfma"] == pytest.approx(w["tflops"] / 78.6)
+
+
+def test_moment_errors_are_relative_to_the_largest_entry():
+    import numpy as np
+    ref = {f: (np.array([1.0, -2.0]), np.array([0.5, 0.25])) for f in bench.FIELD_NAMES}
+    mom = {f: (np.array([1.0, -2.0 + 2e-9]), np.array([0.5 + 5e-10, 0.25])) for f in bench.FIELD_NAMES}
+    e = bench.moment_errors(mom, ref)
+    for f in bench.FIELD_NAMES:
+        assert e[f]["mean"] == pytest.approx(1e-9)
+        assert e[f]["var"] == pytest.approx(1e-9)

@@ -64,7 +64,7 @@ def test_sampled_basis_parity_full_size(name, precision, tol):
     grid = Grid(prob["regions"], prob["rule"])
     ctx = gpu_ctx(prob, precision)
     if precision == "mixed":
-        assert ctx.counters()["max_refine_residual"] <= 1e-12
+        assert ctx.counters()["max_refine_residual"] <= 1e-11
     rng = np.random.default_rng(11)
     for i, k in sampled_units(L, grid, name, rng):
         S = oracle_unit_basis(L, grid, i, k)
@@ -268,7 +268,7 @@ def test_mixed_moments_match_fp64_cfg2():
         ctx.accumulate_moments(g, lam)
         mom[prec] = {f: ctx.get_moments(f) for f in SFIELDS}
         if prec == "mixed":
-            assert ctx.counters()["max_refine_residual"] <= 1e-12
+            assert ctx.counters()["max_refine_residual"] <= 1e-11
         ctx.close()
     for f in SFIELDS:
         (m64, v64), (mmx, vmx) = mom["fp64"][f], mom["mixed"][f]
@@ -287,7 +287,7 @@ def test_mixed_basis_moments_match_fp64_cfg3():
     print("case: cfg3 moments of one interface solution, mixed against FP64 basis", flush=True)
     from paper_1802_06263_amd.sdmm import FIELDS as SFIELDS
     ctxs = {prec: gpu_ctx(problem("cfg3"), prec) for prec in ("fp64", "mixed")}
-    assert ctxs["mixed"].counters()["max_refine_residual"] <= 1e-12
+    assert ctxs["mixed"].counters()["max_refine_residual"] <= 1e-11
     n = ctxs["fp64"].sizes()["n_real"]
     g, lam, it, rr, st, _ = gpu_solve(ctxs["fp64"], np.arange(n), rtol=1e-8)
     assert (st == CG_CONVERGED).all()

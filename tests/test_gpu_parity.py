@@ -6,8 +6,9 @@ Tolerances (derived from the arithmetic):
   lambda at rtol 1e-12   1e-9 relative (CG stopping error times the interface
                          condition number)
   moments at rtol 1e-12  1e-9 relative per field (the spec bar)
-  mixed precision        S 1e-10, moments 1e-8 (FP32 factor, FP64 refinement
-                         to 1e-13 relative residual)
+  mixed precision        S 1e-10, moments 1e-8 (FP32 factor and solves on FP32
+                         MFMA, FP64 refinement to 1e-11 relative residual, S
+                         evaluated to second order in that residual)
 """
 import numpy as np
 import pytest
@@ -73,7 +74,7 @@ def test_mixed_precision_moments_cfg0(cfg0):
         assert rel(mg, mo) < 1e-8, f
         assert rel(vg, vo) < 1e-8, f
     c = ctx.counters()
-    assert c["max_refine_residual"] <= 1e-12
+    assert c["max_refine_residual"] <= 1e-11
     ctx.close()
 
 
@@ -163,4 +164,31 @@ def test_cg_options_do_not_change_results(cfg0):
             ctx.set_option(k, v)
         _, lam, *_ = gpu_solve(ctx, np.arange(16), rtol=1e-10)
         assert np.array_equal(lam.cpu().numpy(), ref), opts
+    ctx.close()
+
+
+def test_stokes_graph_replays_match_the_eager_build():
+    """The Stokes build is captured once as a HIP graph and replayed on every
+    rebuild; each replay must give exactly what the eager launches give."""
+    print("case: Stokes graph replays vs eager build (small floating-Stokes layout)", flush=True)
+    from paper_1802_06263_amd import sdmm
+    p = _small_feti()
+    stokes = [i for i, s in enumerate(p["subdomains"]) if s["type"] == "stokes"]
+    eager = sdmm.Context(0)
+    eager.set_problem(p)
+    eager.set_option("cg_graph", 0)
+    eager.build_flux_basis("fp64")
+    R = np.diff(eager.index_map("sub_ptr"))
+    ref = [eager.get_basis(i, 0, int(R[i])) for i in stokes]
+    g_ref, G_ref = eager.interface_data()
+    eager.close()
+    ctx = sdmm.Context(0)
+    ctx.set_problem(p)
+    ctx.set_option("stokes_rebuild", 1)
+    for rep in range(3):
+        ctx.build_flux_basis("fp64" if rep != 1 else "mixed")
+        for i, S in zip(stokes, ref):
+            assert np.array_equal(ctx.get_basis(i, 0, int(R[i])), S), (rep, i)
+        g, G = ctx.interface_data()
+        assert np.array_equal(g, g_ref) and np.array_equal(G, G_ref), rep
     ctx.close()
