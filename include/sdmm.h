@@ -351,6 +351,8 @@ int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
  *   SDMM_OPT_STOKES_REBUILD 1 = every sdmm_build_flux_basis rebuilds the
  *                      Stokes basis too (0, the default: built once, since
  *                      it does not depend on the realization)
+ *   SDMM_OPT_STOKES_REFINE FP64 refinement steps after the band LDL^T solves
+ *                      of the Stokes subdomains (0 .. 8, default 1)
  * Results do not depend on any of them. */
 #define SDMM_OPT_CG_CHUNK 0
 #define SDMM_OPT_CG_CHECK 1
@@ -358,6 +360,7 @@ int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
 #define SDMM_OPT_KERNEL_TIMING 3
 #define SDMM_OPT_CG_LANES 4
 #define SDMM_OPT_STOKES_REBUILD 5
+#define SDMM_OPT_STOKES_REFINE 6
 int sdmm_set_option(sdmm_ctx* ctx, int64_t id, int option, int64_t value);
 /* Autotuner of the batched CG: runs the first min(n, 16384) realizations of
  * gidx (device int64, n) through the whole CG (rtol, max_iter as in

@@ -186,6 +186,7 @@ struct Prob {
     int opt_graph = 1;       // capture the iteration group in a HIP graph
     int opt_ktime = 0;       // 0: no kernel timing; n: time one iteration of every n-th check group
     int opt_stokes_rebuild = 0;   // rebuild the Stokes basis on every build_flux_basis
+    int opt_stokes_refine = 1;    // FP64 refinement steps of the Stokes solves
     bool moments_final = false;   // the field moments in d_mom match the accumulators
     std::vector<hipEvent_t> kev;   // event pool of the kernel timing
     hipStream_t cap_stream = nullptr;
@@ -682,9 +683,9 @@ int stokes_device_work(Prob* ctx, hipStream_t st) {
                                    ctx->d_stmp.as<double>(), st);
     };
     HIPCHK(solve(x));
-    // two steps of FP64 iterative refinement: the LDL^T without pivoting of
-    // the saddle matrix loses digits that the refined solution recovers
-    for (int step = 0; step < 2; ++step) {
+    // FP64 iterative refinement: the LDL^T without pivoting of the saddle
+    // matrix loses digits that the refined solution recovers
+    for (int step = 0; step < ctx->opt_stokes_refine; ++step) {
         HIPCHK(launch_stokes_residual(sd, ns, ctx->max_nblk, ctx->max_ncol, ctx->d_tiles0.as<double>(),
                                       ctx->d_rhs0.as<double>(), x, res, st));
         HIPCHK(solve(res));
@@ -1302,6 +1303,17 @@ int impl_set_option(Prob* ctx, int option, int64_t value) {
             return SDMM_OK;
         case SDMM_OPT_STOKES_REBUILD:
             ctx->opt_stokes_rebuild = value ? 1 : 0;
+            return SDMM_OK;
+        case SDMM_OPT_STOKES_REFINE:
+            if (value < 0 || value > 8) return fail(ctx, SDMM_EINVAL, "Stokes refinement steps must be in 0..8");
+            if (value != ctx->opt_stokes_refine) {
+                // the captured Stokes build holds the old step count
+                if (ctx->stokes_exec) (void)hipGraphExecDestroy(ctx->stokes_exec);
+                if (ctx->stokes_graph) (void)hipGraphDestroy(ctx->stokes_graph);
+                ctx->stokes_exec = nullptr;
+                ctx->stokes_graph = nullptr;
+            }
+            ctx->opt_stokes_refine = (int)value;
             return SDMM_OK;
         case SDMM_OPT_CG_LANES:
             if (value < 1 || value > kMaxLanes) return fail(ctx, SDMM_EINVAL, "cg_lanes must be 1 or 2");

@@ -934,15 +934,113 @@ __global__ __launch_bounds__(kThreads) void darcy_moments_kernel(DarcyTables t, 
     }
 }
 
+// The same expansion with the quadratic form on FP64 MFMA (R <= 64): per
+// local realization k, G = F Mc for the workgroup's 64 outputs (F: their
+// response rows, 64 x R; Mc: R x R), then E[u^2] += sum_a F[o][a] G[o][a]
+// and E[u] += F a.  Every thread keeps its part of the row sums across k;
+// the parts are added in a fixed order at the end.
+__global__ __launch_bounds__(kThreads) void darcy_moments_mfma_kernel(DarcyTables t, const int* unit_of_dk,
+                                                                      const int* d_nlocal, const int64_t* d_Abase,
+                                                                      const double* acc, const double* X,
+                                                                      const int64_t* cell_out_off,
+                                                                      const int64_t* edge_out_off, double* p1,
+                                                                      double* p2, double* u1, double* u2,
+                                                                      int max_units_per_d) {
+    __shared__ double Fs[kTile * kLd];    // Fs[a kLd + o] = F[o][a]
+    __shared__ double Ms[kTile * kLd];    // Ms[a kLd + b] = Mc[b][a]
+    __shared__ double red[kTile * 33];    // row-sum parts: 16 lanes x 2 waves per row
+    __shared__ double lin[kTile];
+    __shared__ double Fr[kTile * kLd];    // Fr[o kLd + a] = F[o][a] as the response rows are built
+    const int d = blockIdx.y;
+    const DarcyDev D = t.dar[d];
+    const int R = D.R;
+    const int nout = D.N + (D.nx + 1) * D.ny + D.nx * (D.ny + 1);
+    const int o0 = blockIdx.x * 64;
+    if (o0 >= nout) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, g = lane >> 4;
+    const int rb = (wave & 1) * 32, cb = (wave >> 1) * 32;
+    double s2[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    double s1 = 0.0;
+    for (int k = 0; k < d_nlocal[d]; ++k) {
+        const int u = unit_of_dk[d * max_units_per_d + k];
+        const UnitDev U = t.units[u];
+        const double* xi = t.xi + U.off_xi;
+        const double* Xu = X + U.off_X;
+        const double* av = acc + d_Abase[d] + (int64_t)k * (R + R * R);
+        const double* Mc = av + R;
+        __syncthreads();
+        if (wave == 0) {
+            const int o = o0 + lane;
+            double* fr = Fr + lane * kLd;
+            const bool has = o < nout && darcy_response_row(t, D, xi, Xu, o, fr);
+            double l = 0.0;
+            for (int a = 0; a < kTile; ++a) {
+                if (!has || a >= R) fr[a] = 0.0;
+                if (a < R) l += fr[a] * av[a];
+            }
+            s1 += l;
+        }
+        for (int idx = tid; idx < kTile * kTile; idx += kThreads) {
+            const int a = idx >> 6, b = idx & 63;
+            Ms[a * kLd + b] = (a < R && b < R) ? Mc[(int64_t)b * R + a] : 0.0;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < kTile * kTile; idx += kThreads) {
+            const int a = idx >> 6, o = idx & 63;
+            Fs[a * kLd + o] = Fr[o * kLd + a];
+        }
+        __syncthreads();
+        TileAcc G;
+        tile_acc_zero(G);
+        tile_mma<false, false>(Fs, Ms, G);
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q2 = 0; q2 < 2; ++q2)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = rb + 16 * p + 4 * q + g, c = cb + 16 * q2 + li;
+                    s2[p][q] += G.c[p][q2][q] * Fs[c * kLd + r];
+                }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[(rb + 16 * p + 4 * q + g) * 33 + (wave >> 1) * 16 + li] = s2[p][q];
+    if (wave == 0) lin[lane] = s1;
+    __syncthreads();
+    if (tid < 64) {
+        const int o = o0 + tid;
+        double m2 = 0.0;
+        for (int j = 0; j < 32; ++j) m2 += red[tid * 33 + j];
+        const double m1 = lin[tid];
+        if (o < nout) {
+            if (o < D.N) {
+                p1[cell_out_off[d] + o] = m1;
+                p2[cell_out_off[d] + o] = m2;
+            } else {
+                u1[edge_out_off[d] + o - D.N] = m1;
+                u2[edge_out_off[d] + o - D.N] = m2;
+            }
+        }
+    }
+}
+
 hipError_t launch_darcy_moments_impl(const DarcyTables& t, const int* unit_of_dk, const int* d_nlocal, int n_darcy,
                                      int max_nout, int max_units_per_d, const int64_t* d_Abase, const double* acc,
                                      const double* X, int max_R, const int64_t* cell_out_off,
                                      const int64_t* edge_out_off, double* p1, double* p2, double* u1, double* u2,
                                      hipStream_t stream) {
     if (n_darcy <= 0) return hipSuccess;
-    hipLaunchKernelGGL(darcy_moments_kernel, dim3((max_nout + 63) / 64, n_darcy), dim3(kThreads),
-                       64 * max_R * sizeof(double), stream, t, unit_of_dk, d_nlocal, d_Abase, acc, X, cell_out_off,
-                       edge_out_off, p1, p2, u1, u2, max_units_per_d);
+    if (max_R <= kTile)
+        hipLaunchKernelGGL(darcy_moments_mfma_kernel, dim3((max_nout + 63) / 64, n_darcy), dim3(kThreads), 0, stream,
+                           t, unit_of_dk, d_nlocal, d_Abase, acc, X, cell_out_off, edge_out_off, p1, p2, u1, u2,
+                           max_units_per_d);
+    else
+        hipLaunchKernelGGL(darcy_moments_kernel, dim3((max_nout + 63) / 64, n_darcy), dim3(kThreads),
+                           64 * max_R * sizeof(double), stream, t, unit_of_dk, d_nlocal, d_Abase, acc, X, cell_out_off,
+                           edge_out_off, p1, p2, u1, u2, max_units_per_d);
     return hipGetLastError();
 }
 
