@@ -352,7 +352,7 @@ int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
  *                      Stokes basis too (0, the default: built once, since
  *                      it does not depend on the realization)
  *   SDMM_OPT_STOKES_REFINE FP64 refinement steps after the band LDL^T solves
- *                      of the Stokes subdomains (0 .. 8, default 1)
+ *                      of the Stokes subdomains (0 .. 8, default 0)
  * Results do not depend on any of them. */
 #define SDMM_OPT_CG_CHUNK 0
 #define SDMM_OPT_CG_CHECK 1

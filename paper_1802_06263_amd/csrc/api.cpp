@@ -158,7 +158,7 @@ struct Prob {
         d_xi, d_supp_ptr, d_supp_e, d_supp_v, d_me_cell;
     DevBuf d_S, d_X, d_L, d_T, d_L32, d_W32, d_E, d_refine, d_I, d_I32;
     DevBuf d_sdev, d_tiles, d_rhs, d_U, d_P, d_bmap, d_Z, d_q_ptr, d_q_col, d_q_val, d_uD, d_uD_off, d_tr_sub, d_tr_r,
-        d_tr_c, d_tr_v, d_rhs0, d_res, d_tiles0, d_linv, d_stmp;
+        d_tr_c, d_tr_v, d_rhs0, d_res, d_tiles0, d_tilesN, d_linv, d_stmp;
     DevBuf d_g, d_G, d_GtGinv, d_Grow, d_Gval;
     int nGrow = 0;
     DevBuf d_sub_R, d_sub_dof_ptr, d_sub_dofs, d_sub_region, d_sub_Sbase, d_g2l, d_weights;
@@ -186,11 +186,13 @@ struct Prob {
     int opt_graph = 1;       // capture the iteration group in a HIP graph
     int opt_ktime = 0;       // 0: no kernel timing; n: time one iteration of every n-th check group
     int opt_stokes_rebuild = 0;   // rebuild the Stokes basis on every build_flux_basis
-    int opt_stokes_refine = 1;    // FP64 refinement steps of the Stokes solves
+    int opt_stokes_refine = 0;    // FP64 refinement steps of the Stokes solves
     bool moments_final = false;   // the field moments in d_mom match the accumulators
     std::vector<hipEvent_t> kev;   // event pool of the kernel timing
     hipStream_t cap_stream = nullptr;
     hipStream_t stokes_cap = nullptr;        // capture stream of the Stokes graph
+    hipStream_t stokes_side = nullptr;       // second stream of the Stokes factor (the rest updates)
+    hipEvent_t stokes_ev[5] = {};            // panel done, and the rest updates of four columns
     hipGraph_t stokes_graph = nullptr;
     hipGraphExec_t stokes_exec = nullptr;
     hipStream_t lane_stream = nullptr;   // the second CG lane
@@ -615,6 +617,7 @@ int setup_device(Prob* ctx) {
     if ((rc = alloc(ctx, ctx->d_T, ctx->T_total * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_tiles, tiles_off * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_tiles0, tiles_off * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->d_tilesN, tiles_off * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_linv, linv_off * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_stmp, rhs_off * 8))) return rc;
     if ((rc = alloc(ctx, ctx->d_rhs, rhs_off * 8))) return rc;
@@ -654,9 +657,10 @@ int setup_device(Prob* ctx) {
 
 // The device part of the Stokes build (Section 5.1, eqs. starSproblem1-2 and
 // barSproblem1-2 for every Stokes subdomain): assembly into tiles, the band
-// LDL^T, the solves for all R + 1 right-hand sides with two FP64 refinement
-// steps, and the traces that give S, g_H and G.  Only kernels and device
-// copies, so the whole sequence can be captured as one graph.
+// LDL^T (on st and a second stream), the sweep tiles, the solves for all
+// R + 1 right-hand sides with the optional FP64 refinement steps, and the
+// traces that give S, g_H and G.  Only kernels, device copies and event
+// waits, so the whole sequence can be captured as one graph.
 int stokes_device_work(Prob* ctx, hipStream_t st) {
     Problem& P = ctx->P;
     const int ns = (int)ctx->sdev.size();
@@ -676,15 +680,31 @@ int stokes_device_work(Prob* ctx, hipStream_t st) {
     HIPCHK(launch_stokes_pad_identity(sd, ns, ctx->max_nblk, tiles, st));
     // the assembled matrix, kept for the refinement residuals
     HIPCHK(hipMemcpyAsync(ctx->d_tiles0.p, ctx->d_tiles.p, ctx->d_tiles.bytes, hipMemcpyDeviceToDevice, st));
-    for (int J = 0; J < ctx->max_nblk; ++J)
-        HIPCHK(launch_stokes_ldl_step(sd, ns, J, ctx->max_w, tiles, ctx->d_linv.as<double>(), st));
+    // the factor, block column by block column: diag and panel of column J on
+    // st; the rest updates of column J on the side stream, which the diag
+    // launch of column J + 2 waits for (every tile still receives its updates
+    // in increasing J)
+    hipStream_t side = ctx->stokes_side;
+    hipEvent_t* ev = ctx->stokes_ev;
+    for (int J = 0; J < ctx->max_nblk; ++J) {
+        if (J >= 2) HIPCHK(hipStreamWaitEvent(st, ev[1 + (J - 2) % 4], 0));
+        HIPCHK(launch_stokes_ldl_diag(sd, ns, J, tiles, ctx->d_linv.as<double>(), st));
+        HIPCHK(launch_stokes_ldl_panel(sd, ns, J, ctx->max_w, tiles, linv, st));
+        HIPCHK(hipEventRecord(ev[0], st));
+        HIPCHK(hipStreamWaitEvent(side, ev[0], 0));
+        HIPCHK(launch_stokes_ldl_rest(sd, ns, J, ctx->max_w, tiles, side));
+        HIPCHK(hipEventRecord(ev[1 + J % 4], side));
+    }
+    // join the side stream (the last columns' rest updates) before the sweeps
+    for (int J = std::max(0, ctx->max_nblk - 2); J < ctx->max_nblk; ++J)
+        HIPCHK(hipStreamWaitEvent(st, ev[1 + J % 4], 0));
+    HIPCHK(launch_stokes_sweep_tiles(sd, ns, ctx->max_nblk, ctx->max_w, tiles, ctx->d_tilesN.as<double>(), linv, st));
     auto solve = [&](double* b) {
-        return launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, linv, b,
-                                   ctx->d_stmp.as<double>(), st);
+        return launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, ctx->d_tilesN.as<double>(),
+                                   linv, b, ctx->d_stmp.as<double>(), st);
     };
     HIPCHK(solve(x));
-    // FP64 iterative refinement: the LDL^T without pivoting of the saddle
-    // matrix loses digits that the refined solution recovers
+    // optional FP64 iterative refinement against the assembled matrix
     for (int step = 0; step < ctx->opt_stokes_refine; ++step) {
         HIPCHK(launch_stokes_residual(sd, ns, ctx->max_nblk, ctx->max_ncol, ctx->d_tiles0.as<double>(),
                                       ctx->d_rhs0.as<double>(), x, res, st));
@@ -701,12 +721,23 @@ int stokes_device_work(Prob* ctx, hipStream_t st) {
 
 int build_stokes(Prob* ctx, hipStream_t st) {
     Problem& P = ctx->P;
+    if (!ctx->stokes_side) {
+        if (hipStreamCreateWithFlags(&ctx->stokes_side, hipStreamNonBlocking) != hipSuccess) {
+            ctx->stokes_side = nullptr;
+            return fail(ctx, SDMM_EDEVICE, "second stream of the Stokes factor");
+        }
+        for (hipEvent_t& e : ctx->stokes_ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                e = nullptr;
+                return fail(ctx, SDMM_EDEVICE, "events of the Stokes factor");
+            }
+    }
     if (!ctx->opt_graph) {
         int rc = stokes_device_work(ctx, st);
         if (rc) return rc;
     } else {
-        // about 7,000 small launches per build: captured once as a graph and
-        // replayed on every later build of this problem
+        // about 3,000 small launches on two streams per build: captured once
+        // as a graph and replayed on every later build of this problem
         if (!ctx->stokes_exec) {
             if (!ctx->stokes_cap && hipStreamCreateWithFlags(&ctx->stokes_cap, hipStreamNonBlocking) != hipSuccess) {
                 ctx->stokes_cap = nullptr;
@@ -1049,6 +1080,9 @@ int impl_destroy(Prob* ctx) {
     if (ctx->stokes_exec) (void)hipGraphExecDestroy(ctx->stokes_exec);
     if (ctx->stokes_graph) (void)hipGraphDestroy(ctx->stokes_graph);
     if (ctx->stokes_cap) (void)hipStreamDestroy(ctx->stokes_cap);
+    if (ctx->stokes_side) (void)hipStreamDestroy(ctx->stokes_side);
+    for (hipEvent_t e : ctx->stokes_ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->lane_stream) (void)hipStreamDestroy(ctx->lane_stream);
     if (ctx->h_count) (void)hipHostFree(ctx->h_count);
     if (ctx->lane_ev) (void)hipEventDestroy(ctx->lane_ev);

@@ -84,12 +84,22 @@ struct StokesDev {
 hipError_t launch_stokes_scatter(const StokesDev* sd, int ns, const int* tr_sub, const int* tr_r, const int* tr_c,
                                  const double* tr_v, int64_t ntrip, double* tiles, hipStream_t stream);
 hipError_t launch_stokes_pad_identity(const StokesDev* sd, int ns, int max_nblk, double* tiles, hipStream_t stream);
-// one block column J of the band LDL^T (diagonal tile, panel, trailing update)
-hipError_t launch_stokes_ldl_step(const StokesDev* sd, int ns, int J, int max_w, double* tiles, double* linv,
+// one block column J of the band LDL^T: diag (the last update of tile
+// (J, J), its LDL^T and L(J, J)^{-1}), panel (the last update of the tiles
+// below it, then L(I, J)) and rest (the updates of block column J to the
+// tiles of columns J + 2 ..); rest of column J must finish before the diag
+// launch of column J + 2
+hipError_t launch_stokes_ldl_diag(const StokesDev* sd, int ns, int J, double* tiles, double* linv,
                                   hipStream_t stream);
+hipError_t launch_stokes_ldl_panel(const StokesDev* sd, int ns, int J, int max_w, double* tiles, const double* linv,
+                                   hipStream_t stream);
+hipError_t launch_stokes_ldl_rest(const StokesDev* sd, int ns, int J, int max_w, double* tiles, hipStream_t stream);
+// after the factor: the sweep tiles M (in place of L) and N (into tilesN)
+hipError_t launch_stokes_sweep_tiles(const StokesDev* sd, int ns, int max_nblk, int max_w, double* tiles,
+                                     double* tilesN, const double* linv, hipStream_t stream);
 // x := A^{-1} x for all R + 1 columns (tmp: work array of the size of x)
 hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol, const double* tiles,
-                               const double* linv, double* x, double* tmp, hipStream_t stream);
+                               const double* tilesN, const double* linv, double* x, double* tmp, hipStream_t stream);
 // FP64 iterative refinement of the band solves: res = b - A x with the
 // assembled band matrix (tiles0; fixed summation order), then x += d after
 // d = A^{-1} res.

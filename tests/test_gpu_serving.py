@@ -34,3 +34,29 @@ def test_mixed_stream_answers_match_alone():
         lam, it, st = server.engines[r.problem].backend.solve_alone(r.gidx, 1e-8)
         assert np.array_equal(lam, r.lam) and np.array_equal(it, r.iters) and np.array_equal(st, r.status)
     server.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_layouts_in_the_mix_match_alone(precision):
+    """The two large serving layouts (4x2 Stokes over 8x4 Darcy 64x64, and the
+    uneven P2 layout) served together: every answer equals the same request
+    solved alone, in both precisions."""
+    print("case: serving stream on the full cfg2 + cfg3 layouts,", precision, flush=True)
+    from paper_1802_06263_amd.serve import Engine, Server, footprint_bytes, replay, summarize
+    names = ("cfg2", "cfg3")
+    server = Server()
+    for name in names:
+        e = Engine(name, problem(name), precision=precision, slots=1024)
+        server.add(e, footprint_bytes(e.backend.sizes, e.backend.slots))
+    sizes = {p: server.engines[p].backend.sizes["n_real"] for p in names}
+    stream = serving_stream(seed=5, duration_s=0.25, rate_hz=48.0, max_batch=96, grid_sizes=sizes, problems=names)
+    reqs = replay(server, stream, speed=1.0)
+    out = summarize(reqs, 1.0)
+    assert out["answered"] == len(stream) and out["not_converged"] == 0
+    shared = max(max((x[0] for x in server.engines[p].runs), default=0) for p in names)
+    print("  %d requests; most sharing one CG stream at a check: %d" % (len(stream), shared), flush=True)
+    assert shared >= 2
+    for r in reqs:
+        lam, it, st = server.engines[r.problem].backend.solve_alone(r.gidx, 1e-8)
+        assert np.array_equal(lam, r.lam) and np.array_equal(it, r.iters) and np.array_equal(st, r.status)
+    server.close()
