@@ -413,9 +413,11 @@ int setup_device(Prob* ctx) {
         edge_tot += (int64_t)(h.nx + 1) * h.ny + (int64_t)h.nx * (h.ny + 1);
     }
     ctx->n_units = (int64_t)ctx->units.size();
-    if (darcy_factor_lds((ctx->max_b + 15) / 16 * 16, 8) > 150 * 1024 ||
+    // the block kernels hold a band block of 16 (bp + 1) <= 8 x 256 values in
+    // registers and index band columns below 128: bp <= 112
+    if ((ctx->max_b + 15) / 16 * 16 > kMaxDarcyBand || darcy_factor_lds((ctx->max_b + 15) / 16 * 16, 8) > 150 * 1024 ||
         darcy_solve_lds((ctx->max_b + 15) / 16 * 16, ctx->max_Rd, 8) > 150 * 1024)
-        return fail(ctx, SDMM_EINVAL, "a Darcy subdomain's band window does not fit in LDS (shorter side too long)");
+        return fail(ctx, SDMM_EINVAL, "a Darcy subdomain's band window does not fit (shorter side above 112 cells)");
     {
         // shape classes, most expensive unit shape first
         std::map<std::pair<int, int>, std::vector<int>> cls;

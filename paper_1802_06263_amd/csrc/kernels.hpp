@@ -52,6 +52,7 @@ struct DarcyTables {
 
 // Launchers (all enqueue on `stream`).
 
+constexpr int kMaxDarcyBand = 112;   // largest padded half-bandwidth of a Darcy unit
 size_t darcy_factor_lds(int bp, size_t elem);
 size_t darcy_solve_lds(int bp, int R, size_t elem);
 // max_np: largest padded cell count of the launch's units
