@@ -367,36 +367,49 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
     const int cb = (wave >> 1) * 32, rb = (wave & 1) * 32;   // realizations x S-rows quadrant
     const int li = lane & 15, lk = lane >> 4;
     dbl4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
-    // every coefficient load of a thread is for local DOF k0 + (tid % KC); its
-    // global index is fetched one chunk ahead
+    // Software pipeline over 16-wide k-chunks: the S and coefficient values of
+    // chunk k0 + KC are loaded into registers while the MFMAs of chunk k0 run.
+    // The loads are unconditional, at addresses clamped into S, the DOF list
+    // and the first realization's vector, and the out-of-range values are
+    // zeroed when they are staged in LDS: a masked load would need its
+    // destination zeroed first, which waits for every load in flight.  Every
+    // coefficient load of a thread is for local DOF k0 + (tid % KC), whose
+    // global index is fetched one chunk before its coefficients.
+    constexpr int NL = KC * 64 / kThreads;
     const int jt = tid % KC;
-    int64_t gnext = jt < R ? dofs[jt] : 0;
-    for (int k0 = 0; k0 < R; k0 += KC) {
-        const int64_t gj = gnext;
-        if (k0 + KC + jt < R) gnext = dofs[k0 + KC + jt];
-        __syncthreads();
-        // KC / 4 independent loads per thread for each operand
-        constexpr int NL = KC * 64 / kThreads;
-        double sv[NL], xv[NL];
+    auto dof_at = [&](int k0) { return dofs[min(k0 + jt, R - 1)]; };
+    double sv[NL], xv[NL];
+    auto load_chunk = [&](int k0, int64_t gj, int64_t xo0) {
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             const int idx = tid + q * kThreads;
             const int j = idx >> 6, r = idx & 63;
-            sv[q] = (k0 + j < R && r < nrow) ? S[(int64_t)(k0 + j) * R + row0 + r] : 0.0;
+            sv[q] = S[(int64_t)min(k0 + j, R - 1) * R + row0 + min(r, nrow - 1)];
         }
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
-            const int c = (tid + q * kThreads) / KC;
-            const int64_t xo = xoff[c];
-            xv[q] = (xo >= 0 && k0 + jt < R) ? x[xo + gj] : 0.0;
+            const int64_t xo = xoff[(tid + q * kThreads) / KC];
+            xv[q] = x[(xo >= 0 ? xo : xo0) + gj];
         }
+    };
+    int64_t gnext = dof_at(KC);
+    __syncthreads();   // rowoff / xoff
+    const int64_t xo0 = xoff[0];   // count >= 1
+    load_chunk(0, dof_at(0), xo0);
+    for (int k0 = 0; k0 < R; k0 += KC) {
+        __syncthreads();   // the previous chunk's MFMAs are done with St / Xs
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             const int idx = tid + q * kThreads;
-            St[idx] = sv[q];
-            Xs[jt * 65 + idx / KC] = xv[q];
+            const int j = idx >> 6, r = idx & 63, c = idx / KC;
+            St[idx] = (k0 + j < R && r < nrow) ? sv[q] : 0.0;
+            Xs[jt * 65 + c] = (xoff[c] >= 0 && k0 + jt < R) ? xv[q] : 0.0;
         }
         __syncthreads();
+        if (k0 + KC < R) {
+            load_chunk(k0 + KC, gnext, xo0);
+            gnext = dof_at(k0 + 2 * KC);
+        }
         // transposed product Y^T = X^T S^T: tile rows are realizations, columns
         // are rows of S, so the 16 lanes of a group store 16 consecutive doubles
 #pragma unroll
