@@ -59,6 +59,9 @@ extern "C" {
 #define SDMM_METHOD_DETERMINISTIC 1 /* Method S2 (Section 5.3): a basis for every  */
                                     /* global realization, built per batch inside */
                                     /* sdmm_solve_interface                        */
+#define SDMM_METHOD_PER_ITERATION 2 /* Method S1 (Section 5.2): no Darcy basis;    */
+                                    /* every CG iteration solves the local Darcy  */
+                                    /* problems of each realization                */
 
 /* status values written per realization by sdmm_solve_interface */
 #define SDMM_CG_CONVERGED 0
@@ -223,6 +226,12 @@ int sdmm_get_kl(sdmm_ctx* ctx, int64_t id, int region, double* lam, int32_t* mod
  * Stokes part is built here; every sdmm_solve_interface call then builds
  * S_{H,i} for each Darcy subdomain and each realization of its batch from
  * that realization's own KL field, and solves with it.
+ * method SDMM_METHOD_PER_ITERATION, Method S1 (Section 5.2): only the Stokes
+ * part is built here; every sdmm_solve_interface call factors the local
+ * Darcy problem of each (subdomain, realization) of its batch once (FP64,
+ * whatever the precision) and solves it for every application of S_H in the
+ * CG (one local solve per Darcy subdomain per iteration); the Stokes
+ * problems, which no realization changes, enter through their responses.
  * precision: SDMM_PREC_FP64 or SDMM_PREC_MIXED (FP32 factor and multi-RHS
  * solves with FP32 accumulation, FP64 refinement of every response).
  * Returns ENOTCONV (the basis is still stored) when the mixed refinement of
@@ -230,7 +239,9 @@ int sdmm_get_kl(sdmm_ctx* ctx, int64_t id, int region, double* lam, int32_t* mod
 int sdmm_build_flux_basis(sdmm_ctx* ctx, int64_t id, int method, int precision, void* stream);
 /* Copy S_{H,i}^{(k)} (R_i x R_i, column-major with leading dimension ld,
  * host) of subdomain `sub` and local realization k (k = 0 for Stokes) of a
- * stochastic basis.  The signs of Stokes-Stokes mortar DOFs are included. */
+ * stochastic basis (Method S2: k is the batch position of the last solve;
+ * Method S1 has no Darcy basis: ESTATE).  The signs of Stokes-Stokes mortar
+ * DOFs are included. */
 int sdmm_get_basis(sdmm_ctx* ctx, int64_t id, int sub, int k, double* S, int64_t ld);
 
 /* The interface right-hand side g_H (host, M values; Section 5.1, the
@@ -246,8 +257,11 @@ int sdmm_get_interface_data(sdmm_ctx* ctx, int64_t id, double* g, double* G);
  *   gidx (device int64, n): global collocation indices; or NULL, and then
  *   y (device double, n x n_term, row-major) gives each realization's
  *   point in the stochastic space directly (an off-grid request; needs
- *   SDMM_METHOD_DETERMINISTIC, since a stochastic basis exists only for
- *   the collocation points of the local grids).
+ *   SDMM_METHOD_DETERMINISTIC or SDMM_METHOD_PER_ITERATION, since a
+ *   stochastic basis exists only for the collocation points of the local
+ *   grids).  Under Method S1 all n realizations iterate together and their
+ *   local factors stay resident (about n x sum over Darcy subdomains of
+ *   16 N_i (b_i + R_i) bytes).
  * lambda_0 = 0; a realization stops when ||r_k|| <= rtol ||r_0||.  Outputs
  * (device): lambda (n x M, row-major), iters (int32 n), relres (double n),
  * status (int32 n, SDMM_CG_*); iters/relres/status may be NULL.  Returns
@@ -316,7 +330,10 @@ int sdmm_stream_close(sdmm_ctx* ctx, int64_t id, int64_t sid);
  * Method S3): gidx (device int64 n) or, for off-grid requests, NULL and y
  * (device n x n_term) as in sdmm_solve_interface; lambda (device n x M from
  * sdmm_solve_interface); weights (device double n, or NULL for the
- * collocation weights of the points; required with y). */
+ * collocation weights of the points; required with y).  Under Methods S2
+ * and S1 the realizations must be those of the last sdmm_solve_interface
+ * call (ESTATE otherwise); Method S1 recovers each realization's Darcy
+ * fields with one more local solve per subdomain. */
 int sdmm_accumulate_moments(sdmm_ctx* ctx, int64_t id, int64_t n, const int64_t* gidx, const double* y,
                             const double* lambda, const double* weights, void* stream);
 /* Mean and variance (host arrays of cap >= field_size[field] entries) of one

@@ -112,6 +112,8 @@ struct DetBatch {
     std::vector<int> chunk_start;        // unit ranges built per launch (scratch reused)
     DevBuf d_units, d_order, d_xi, d_pos, d_S, d_X, d_E, d_W32, d_L, d_L32, d_I, d_I32, d_T, d_refine;
     DevBuf d_unit_of_dk, d_dnlocal, d_dAbase, d_sum, d_tmp;
+    DevBuf d_z, d_F, d_s1work, d_s1perm;   // Method S1: local solutions, fields, Stokes work list
+    int s1_nwork = 0;
     int64_t S_total = 0, X_total = 0, L_chunk = 0, T_chunk = 0, I_chunk = 0, A_base = 0;
     int precision = SDMM_PREC_FP64;
     bool valid = false;
@@ -1220,7 +1222,7 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->have_problem) return fail(ctx, SDMM_ESTATE, "no problem set");
     if (precision != SDMM_PREC_FP64 && precision != SDMM_PREC_MIXED) return fail(ctx, SDMM_EINVAL, "bad precision");
-    if (method != SDMM_METHOD_STOCHASTIC && method != SDMM_METHOD_DETERMINISTIC)
+    if (method != SDMM_METHOD_STOCHASTIC && method != SDMM_METHOD_DETERMINISTIC && method != SDMM_METHOD_PER_ITERATION)
         return fail(ctx, SDMM_EINVAL, "bad method");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
@@ -1228,8 +1230,9 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     ctx->method = method;
     ctx->det.valid = false;
     ctx->det.precision = precision;
-    if (method == SDMM_METHOD_DETERMINISTIC) {
-        // Method S2: the Darcy bases are built per batch inside solve_interface
+    if (method != SDMM_METHOD_STOCHASTIC) {
+        // Methods S2 and S1: the Darcy bases (S2) or factors (S1) are built per
+        // batch inside solve_interface
     } else if (precision == SDMM_PREC_FP64) {
         HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, int np, hipStream_t q) {
             return launch_darcy_basis_blocked(tc, count, bp, Rs, np, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
@@ -1268,7 +1271,7 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     ctx->counters.basis_solves_darcy += sd;
     ctx->counters.basis_solves_stokes = ss;
     ctx->counters.complementary_solves = (int64_t)ctx->P.stokes.size();
-    if (method == SDMM_METHOD_DETERMINISTIC) return SDMM_OK;
+    if (method != SDMM_METHOD_STOCHASTIC) return SDMM_OK;
     ctx->counters.units_built += ctx->n_units;
     if (precision == SDMM_PREC_MIXED) {
         // every right-hand-side group must have reached the refinement tolerance
@@ -1288,6 +1291,8 @@ int impl_get_basis(Prob* ctx, int sub, int k, double* S, int64_t ld) {
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (sub < 0 || sub >= (int)ctx->P.subs.size()) return fail(ctx, SDMM_EINVAL, "bad subdomain");
     const int R = ctx->sub_R[sub];
+    if (ctx->method == SDMM_METHOD_PER_ITERATION && ctx->sub_region[sub] >= 0)
+        return fail(ctx, SDMM_ESTATE, "Method S1 builds no Darcy basis");
     const bool det = ctx->method == SDMM_METHOD_DETERMINISTIC && ctx->sub_region[sub] >= 0;
     // Method S2: k is the batch position of the last solve
     const int64_t nk = det ? (ctx->det.valid ? ctx->det.n : 0) : ctx->sub_nlocal[sub];
@@ -1679,8 +1684,11 @@ int det_points(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, hipSt
     return SDMM_OK;
 }
 
-// Units, offsets, device tables and the basis view of a batch of n realizations.
-int det_layout(Prob* ctx, int64_t n) {
+// Units, offsets, device tables and the basis view of a batch of n
+// realizations.  resident: every unit keeps its own factor scratch (Method
+// S1 solves with the factors in every CG iteration); otherwise the scratch
+// is reused chunk by chunk.
+int det_layout(Prob* ctx, int64_t n, bool resident = false) {
     Problem& P = ctx->P;
     DetBatch& D = ctx->det;
     BasisView& V = D.view;
@@ -1740,7 +1748,7 @@ int det_layout(Prob* ctx, int64_t n) {
             D.units.push_back(u);
             V.pair_sub.push_back(i);
             V.pair_k.push_back((int)q);
-            if (++in_chunk == kDetChunkUnits) in_chunk = 0;
+            if (++in_chunk == kDetChunkUnits && !resident) in_chunk = 0;
         }
     }
     D.chunk_start.push_back((int)D.units.size());
@@ -1858,15 +1866,206 @@ int det_build(Prob* ctx, const std::vector<double>& y, hipStream_t st) {
     return SDMM_OK;
 }
 
+// ---- Method S1 (Section 5.2) ------------------------------------------------
+
+int accumulate_core(Prob* ctx, int64_t n, const int64_t* grp_idx, const int64_t* w_idx, const double* lambda,
+                    const double* weights, hipStream_t st, int64_t chunk_override = 0, bool alpha_ready = false);
+
+// Factors of every (Darcy subdomain, realization) unit of the batch (each
+// realization's own KL field, eqs. KLapprox and starDproblem1-2), kept
+// resident for the local solves of every CG iteration, the local-solution
+// scratch, and the work list of the Stokes products (their responses do not
+// depend on the realization, R2).
+int s1_prepare(Prob* ctx, int64_t n, const std::vector<double>& pts, hipStream_t st) {
+    DetBatch& D = ctx->det;
+    const Problem& P = ctx->P;
+    int rc;
+    for (auto& h : P.darcy)
+        if (h.R > kS1MaxR || h.n_medge > kS1MaxMedge)
+            return fail(ctx, SDMM_EINVAL, "Method S1 handles at most 256 mortar DOFs and 512 mortar edges per Darcy subdomain");
+    D.precision = SDMM_PREC_FP64;
+    if ((rc = det_layout(ctx, n, true))) return rc;
+    if (!pts.empty()) {
+        if ((rc = upload(ctx, D.d_xi, pts))) return rc;
+    } else if ((rc = alloc(ctx, D.d_xi, 8))) {
+        return rc;
+    }
+    int max_np = 0;
+    for (auto& h : P.darcy) max_np = std::max(max_np, (h.N + 15) / 16 * 16);
+    const int64_t zn = n * (int64_t)P.darcy.size() * max_np;
+    if (D.d_z.bytes < (size_t)std::max<int64_t>(zn, 1) * 8 && (rc = alloc(ctx, D.d_z, std::max<int64_t>(zn, 1) * 8)))
+        return rc;
+    DarcyTables t = darcy_tables(ctx);
+    t.units = D.d_units.as<UnitDev>();
+    t.order = D.d_order.as<int>();
+    t.xi = D.d_xi.as<double>();
+    t.unit_base = 0;
+    HIPCHK(launch_darcy_factor_only(t, (int)D.units.size(), ctx->max_b, max_np, D.d_X.as<double>(),
+                                    D.d_L.as<double>(), D.d_I.as<double>(), D.d_T.as<double>(), st));
+    std::vector<int4> work;
+    for (auto& sh : P.stokes) {
+        const int i = sh.sub, R = ctx->sub_R[i];
+        for (int64_t c0 = 0; c0 < n; c0 += 64) {
+            const int cnt = (int)std::min<int64_t>(64, n - c0);
+            for (int row0 = 0; row0 < R; row0 += 64) work.push_back(make_int4(i, 0, row0 | (cnt << 16), (int)c0));
+        }
+    }
+    std::vector<int> perm(n);
+    for (int64_t q = 0; q < n; ++q) perm[q] = (int)q;
+    D.s1_nwork = (int)work.size();
+    if (work.empty()) work.push_back(make_int4(0, 0, 0, 0));
+    if ((rc = upload(ctx, D.d_s1work, work)) || (rc = upload(ctx, D.d_s1perm, perm))) return rc;
+    return SDMM_OK;
+}
+
+// S_H x for the n vectors of x (global layout) into Y (subdomain-local
+// layout): local Darcy solves with the batch's factors and the Stokes
+// responses; vectors with active == 0 are skipped on the Darcy side.
+hipError_t s1_apply(Prob* ctx, const CgArgs& a, int64_t n, const int32_t* active, const double* x, double* Y,
+                    hipStream_t st) {
+    DetBatch& D = ctx->det;
+    const Problem& P = ctx->P;
+    DarcyTables t = darcy_tables(ctx);
+    t.units = D.d_units.as<UnitDev>();
+    t.order = D.d_order.as<int>();
+    t.xi = D.d_xi.as<double>();
+    int max_np = 0;
+    for (auto& h : P.darcy) max_np = std::max(max_np, (h.N + 15) / 16 * 16);
+    hipError_t e = launch_darcy_s1_apply(t, D.d_unit_of_dk.as<int>(), (int)n, (int)n, nullptr, active, x, P.M,
+                                         ctx->d_sub_dof_ptr.as<int64_t>(), ctx->d_sub_dofs.as<int64_t>(),
+                                         D.d_L.as<double>(), D.d_I.as<double>(), D.d_T.as<double>(),
+                                         D.d_X.as<double>(), D.d_z.as<double>(), (int)P.darcy.size(), max_np,
+                                         ctx->max_b, Y, ctx->SR, st);
+    if (e != hipSuccess) return e;
+    return launch_cg_apply_mfma(a, x, Y, ctx->SR, D.d_s1work.as<int4>(), D.s1_nwork, D.d_s1perm.as<int>(),
+                                ctx->max_R, st);
+}
+
+// Method S1: CG for the whole batch at once (every realization holds a slot
+// until it stops), S_H applied through local solves in every iteration.
+int s1_solve(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, double rtol, int32_t max_iter,
+             double* lambda, int32_t* iters, double* relres, int32_t* status, hipStream_t st) {
+    DetBatch& D = ctx->det;
+    const Problem& P = ctx->P;
+    int rc;
+    std::vector<double> pts;
+    D.valid = false;
+    if ((rc = det_points(ctx, n, gidx, y, st, pts)) || (rc = s1_prepare(ctx, n, pts, st))) return rc;
+    if ((rc = ensure_workspace(ctx, n))) return rc;
+    CgArgs a = cg_args(ctx, n, D.d_pos.as<int64_t>(), lambda);
+    std::vector<int> ident(n);
+    for (int64_t q = 0; q < n; ++q) ident[q] = (int)q;
+    HIPCHK(hipMemcpyAsync(ctx->w_slot_q.p, ident.data(), n * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->w_init.p, ident.data(), n * 4, hipMemcpyHostToDevice, st));
+    a.slot_q = ctx->w_slot_q.as<int>();
+    a.init_slots = ctx->w_init.as<int>();
+    a.rtol = rtol;
+    a.max_iter = max_iter;
+    a.iters_out = iters;
+    a.relres_out = relres;
+    a.status_out = status;
+    HIPCHK(hipEventRecord(ctx->ev[3], st));
+    HIPCHK(launch_cg_init(a, n, st));
+    double* Y = ctx->w_Y.as<double>();
+    const int* pos = ctx->d_pos.as<int>();
+    const int group = ctx->opt_check;
+    const int64_t max_groups = (int64_t)max_iter / group + 2;
+    for (int64_t grp = 0;; ++grp) {
+        if (grp > max_groups) return fail(ctx, SDMM_EDEVICE, "the CG driver did not finish");
+        for (int q = 0; q < group; ++q) {
+            HIPCHK(s1_apply(ctx, a, n, a.active, a.p, Y, st));
+            HIPCHK(launch_cg_update2(a, Y, ctx->SR, pos, st));
+        }
+        HIPCHK(launch_count_active(a.active, n, a.any_active, st));
+        int32_t count = 0;
+        HIPCHK(hipMemcpyAsync(&count, a.any_active, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (count == 0) break;
+    }
+    HIPCHK(hipEventRecord(ctx->ev[4], st));
+    std::vector<int32_t> itv(2 * n);
+    HIPCHK(hipMemcpyAsync(itv.data(), a.iters, n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(itv.data() + n, a.status, n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t tot = 0;
+    bool bad = false, brk = false;
+    for (int64_t l = 0; l < n; ++l) {
+        tot += itv[l];
+        bad |= itv[n + l] != SDMM_CG_CONVERGED;
+        brk |= itv[n + l] == SDMM_CG_BREAKDOWN;
+    }
+    ctx->counters.cg_iterations += tot;
+    ctx->counters.realizations += n;
+    // one local solve per Darcy subdomain in every iteration (eq. S1-cost)
+    ctx->counters.basis_solves_darcy += tot * (int64_t)P.darcy.size();
+    ctx->counters.units_built += (int64_t)D.units.size();
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, ctx->ev[3], ctx->ev[4]) == hipSuccess) ctx->counters.ms_solve = ms;
+    D.y = pts;
+    D.valid = true;
+    if (brk) return fail(ctx, SDMM_EBREAKDOWN, "CG breakdown in some realization");
+    if (bad) return fail(ctx, SDMM_ENOTCONV, "some realization reached max_iter");
+    return SDMM_OK;
+}
+
+// Method S1 moments: lambda and the Stokes fields through the reduced form
+// (as for every method), the Darcy fields of each realization from one
+// recovery solve per subdomain with its final lambda, summed with the
+// weights into the batch sums.
+int s1_accumulate(Prob* ctx, int64_t n, const int64_t* gidx, const double* lambda, const double* weights,
+                  hipStream_t st) {
+    DetBatch& D = ctx->det;
+    const Problem& P = ctx->P;
+    int rc;
+    if ((rc = ensure_workspace(ctx, n))) return rc;
+    CgArgs a = cg_args(ctx, n, D.d_pos.as<int64_t>(), const_cast<double*>(lambda));
+    // S_H lambda (its Darcy solves leave z = P^{-1} E lambda_i in the scratch)
+    HIPCHK(s1_apply(ctx, a, n, nullptr, lambda, ctx->w_Y.as<double>(), st));
+    if (P.n_kernel > 0) {
+        HIPCHK(launch_gather_global(ctx->w_Y.as<double>(), ctx->SR, ctx->d_pos.as<int>(), P.M, n,
+                                    ctx->w_Slam.as<double>(), st));
+        HIPCHK(launch_alpha(a, ctx->w_Slam.as<double>(), ctx->w_alpha.as<double>(), st));
+    }
+    int64_t a_n = 0;
+    for (auto& h : P.darcy) a_n += n * ((int64_t)h.R + (int64_t)h.R * h.R);
+    HIPCHK(hipMemsetAsync(ctx->d_acc.as<double>() + D.A_base, 0, a_n * 8, st));
+    ctx->view = &D.view;
+    rc = accumulate_core(ctx, n, D.d_pos.as<int64_t>(), gidx, lambda, weights, st, n, true);
+    ctx->view = nullptr;
+    if (rc) return rc;
+    const int64_t f1 = ctx->field_size[1], f2 = ctx->field_size[2];
+    if (D.d_F.bytes < (size_t)std::max<int64_t>(n * (f1 + f2), 1) * 8 &&
+        (rc = alloc(ctx, D.d_F, std::max<int64_t>(n * (f1 + f2), 1) * 8)))
+        return rc;
+    DarcyTables t = darcy_tables(ctx);
+    t.units = D.d_units.as<UnitDev>();
+    t.order = D.d_order.as<int>();
+    t.xi = D.d_xi.as<double>();
+    int max_np = 0;
+    for (auto& h : P.darcy) max_np = std::max(max_np, (h.N + 15) / 16 * 16);
+    HIPCHK(launch_darcy_s1_moments(t, D.d_unit_of_dk.as<int>(), (int)n, lambda, P.M, ctx->d_sub_dof_ptr.as<int64_t>(),
+                                   ctx->d_sub_dofs.as<int64_t>(), D.d_z.as<double>(), (int)P.darcy.size(), max_np,
+                                   ctx->d_cell_out.as<int64_t>(), ctx->d_edge_out.as<int64_t>(), f1, f2,
+                                   D.d_F.as<double>(), weights, gidx, ctx->d_weights.as<double>(),
+                                   D.d_sum.as<double>(), st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->counters.basis_solves_darcy += n * (int64_t)P.darcy.size();   // the recovery solves
+    ctx->moments_final = false;
+    return SDMM_OK;
+}
+
 int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, double rtol, int32_t max_iter,
                          double* lambda, int32_t* iters, double* relres, int32_t* status, void* stream) {
     if (!ctx) return SDMM_EINVAL;
     ctx->view = nullptr;
     const bool det = ctx->method == SDMM_METHOD_DETERMINISTIC;
-    if (n > 0 && !gidx && y && !det) return fail(ctx, SDMM_EINVAL, "off-grid points need the deterministic method");
+    const bool s1 = ctx->method == SDMM_METHOD_PER_ITERATION;
+    const bool offgrid_ok = det || s1;
+    if (n > 0 && !gidx && y && !offgrid_ok)
+        return fail(ctx, SDMM_EINVAL, "off-grid points need Method S2 or S1 (a stochastic basis exists only on the grid)");
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
-    if (n < 0 || (n > 0 && ((!gidx && !(det && y)) || !lambda)) || !(rtol > 0) || max_iter < 1)
+    if (n < 0 || (n > 0 && ((!gidx && !(offgrid_ok && y)) || !lambda)) || !(rtol > 0) || max_iter < 1)
         return fail(ctx, SDMM_EINVAL, "invalid arguments");
     if (n == 0) return SDMM_OK;
     if (n > 2147483647LL) return fail(ctx, SDMM_EINVAL, "batch too large");
@@ -1876,6 +2075,12 @@ int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double
     HIPCHK(hipEventRecord(ctx->ev[5], user));
     HIPCHK(hipStreamWaitEvent(st, ctx->ev[5], 0));
     int rc;
+    if (s1) {
+        rc = s1_solve(ctx, n, gidx, y, rtol, max_iter, lambda, iters, relres, status, st);
+        HIPCHK(hipEventRecord(ctx->ev[4], st));
+        HIPCHK(hipStreamWaitEvent(user, ctx->ev[4], 0));
+        return rc;
+    }
     const int64_t* cg_idx = gidx;
     if (det) {
         // Method S2: this batch's own bases, then the CG on them (the batch
@@ -1925,8 +2130,8 @@ int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double
 int impl_solve_interface_noalloc(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter,
                                  double* lambda, int32_t* iters, double* relres, int32_t* status, void* stream) {
     if (!ctx) return SDMM_EINVAL;
-    if (ctx->method == SDMM_METHOD_DETERMINISTIC)
-        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built deterministic");
+    if (ctx->method != SDMM_METHOD_STOCHASTIC)
+        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built for Method S1 or S2");
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (n < 0 || (n > 0 && (!gidx || !lambda)) || !(rtol > 0) || max_iter < 1)
@@ -2058,8 +2263,8 @@ int impl_solve_interface_noalloc(Prob* ctx, int64_t n, const int64_t* gidx, doub
 
 int impl_stream_open(Prob* ctx, int64_t slots, double rtol, int32_t max_iter, void* stream, int64_t* sid) {
     if (!ctx || !sid) return SDMM_EINVAL;
-    if (ctx->method == SDMM_METHOD_DETERMINISTIC)
-        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built deterministic");
+    if (ctx->method != SDMM_METHOD_STOCHASTIC)
+        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built for Method S1 or S2");
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
     if (slots < 1 || slots > (1 << 24) || !(rtol > 0) || max_iter < 1)
@@ -2247,8 +2452,8 @@ int impl_stream_close(Prob* ctx, int64_t sid) {
 
 int impl_autotune(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_t max_iter, void* stream,
                   int64_t* chunk_out) {
-    if (ctx && ctx->method == SDMM_METHOD_DETERMINISTIC)
-        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built deterministic");
+    if (ctx && ctx->method != SDMM_METHOD_STOCHASTIC)
+        return fail(ctx, SDMM_ESTATE, "needs a stochastic basis (Method S3); this problem was built for Method S1 or S2");
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
@@ -2314,10 +2519,12 @@ int impl_autotune(Prob* ctx, int64_t n, const int64_t* gidx, double rtol, int32_
     return SDMM_OK;
 }
 
+// chunk_override > 0: that many realizations per pass; alpha_ready: the
+// FETI coefficients of the (single) pass are already in w_alpha
 int accumulate_core(Prob* ctx, int64_t n, const int64_t* grp_idx, const int64_t* w_idx, const double* lambda,
-                    const double* weights, hipStream_t st) {
+                    const double* weights, hipStream_t st, int64_t chunk_override, bool alpha_ready) {
     int rc;
-    const int64_t chunk = chunk_size(ctx, n);
+    const int64_t chunk = chunk_override > 0 ? chunk_override : chunk_size(ctx, n);
     if ((rc = ensure_workspace(ctx, chunk))) return rc;
     const int M = ctx->P.M;
     const BasisView* v = ctx->view;
@@ -2329,7 +2536,7 @@ int accumulate_core(Prob* ctx, int64_t n, const int64_t* grp_idx, const int64_t*
         Groups& G = ctx->grp[0];
         if ((rc = build_groups(ctx, G, cn, nullptr, ctx->h_gidx.data(), st))) return rc;
         CgArgs a = cg_args(ctx, cn, g, const_cast<double*>(lam));
-        if (ctx->P.n_kernel > 0) {
+        if (ctx->P.n_kernel > 0 && !alpha_ready) {
             HIPCHK(launch_cg_apply_mfma(a, lam, ctx->w_Y.as<double>(), ctx->SR,
                                         G.d_work.as<int4>(), G.nwork, G.d_perm.as<int>(), ctx->max_R, st));
             HIPCHK(launch_gather_global(ctx->w_Y.as<double>(), ctx->SR, ctx->d_pos.as<int>(), M, cn,
@@ -2379,25 +2586,29 @@ int impl_accumulate_moments(Prob* ctx, int64_t n, const int64_t* gidx, const dou
     if (!ctx) return SDMM_EINVAL;
     ctx->view = nullptr;
     const bool det = ctx->method == SDMM_METHOD_DETERMINISTIC;
-    if (n > 0 && !gidx && y && !det) return fail(ctx, SDMM_EINVAL, "off-grid points need the deterministic method");
+    const bool s1 = ctx->method == SDMM_METHOD_PER_ITERATION;
+    if (n > 0 && !gidx && y && !det && !s1)
+        return fail(ctx, SDMM_EINVAL, "off-grid points need Method S2 or S1 (a stochastic basis exists only on the grid)");
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
     if (!ctx->basis_built) return fail(ctx, SDMM_ESTATE, "basis not built");
-    if (n < 0 || (n > 0 && ((!gidx && !(det && y && weights)) || !lambda)))
+    if (n < 0 || (n > 0 && ((!gidx && !((det || s1) && y && weights)) || !lambda)))
         return fail(ctx, SDMM_EINVAL, "invalid arguments (off-grid points need weights)");
     if (n == 0) return SDMM_OK;
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     int rc;
-    if (!det) {
+    if (!det && !s1) {
         if ((rc = check_indices(ctx, gidx, n, st))) return rc;
         return accumulate_core(ctx, n, gidx, gidx, lambda, weights, st);
     }
-    // Method S2: the realizations of the last solve, with their own bases
+    // Methods S2 and S1: the realizations of the last solve, with their own
+    // bases (S2) or factors (S1)
     DetBatch& D = ctx->det;
     std::vector<double> pts;
     if ((rc = det_points(ctx, n, gidx, y, st, pts))) return rc;
     if (!D.valid || n != D.n || pts != D.y)
-        return fail(ctx, SDMM_ESTATE, "a deterministic basis exists only for the points of the last solve");
+        return fail(ctx, SDMM_ESTATE, "the local problems exist only for the points of the last solve");
+    if (s1) return s1_accumulate(ctx, n, gidx, lambda, weights, st);
     const int64_t a_end = D.A_base + (int64_t)(D.view.pair_sub.size() - ctx->P.stokes.size()) * 0;
     (void)a_end;
     int64_t a_n = 0;
@@ -2453,8 +2664,8 @@ int finalize_moments(Prob* ctx, hipStream_t st) {
     double* sp1 = su2 + ctx->field_size[3];
     double* sp2 = sp1 + ctx->field_size[4];
     HIPCHK(hipEventRecord(ctx->ev[6], st));
-    if (ctx->method == SDMM_METHOD_DETERMINISTIC) {
-        // Method S2: the Darcy moments were expanded batch by batch
+    if (ctx->method != SDMM_METHOD_STOCHASTIC) {
+        // Methods S2 and S1: the Darcy moments were expanded batch by batch
         const size_t nd = (size_t)2 * (ctx->field_size[1] + ctx->field_size[2]);
         if (ctx->det.d_sum.p)
             HIPCHK(hipMemcpyAsync(p1, ctx->det.d_sum.p, nd * 8, hipMemcpyDeviceToDevice, st));

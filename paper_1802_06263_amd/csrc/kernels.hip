@@ -884,6 +884,8 @@ __device__ inline int darcy_response_row(const DarcyTables& t, const DarcyDev& D
     return 1;
 }
 
+#include "darcy_s1.inc"
+
 __global__ __launch_bounds__(kThreads) void darcy_moments_kernel(DarcyTables t, const int* unit_of_dk, const int* d_nlocal,
                                                                  const int64_t* d_Abase, const double* acc,
                                                                  const double* X, const int64_t* cell_out_off,

@@ -59,6 +59,30 @@ size_t darcy_solve_lds(int bp, int R, size_t elem);
 hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np,
                                       double* S_cache, double* X, double* Lscr, double* Iscr, double* Tscr,
                                       hipStream_t stream);
+// Method S1: the band factors of the units only (mortar loads E, factor L,
+// block inverses I, transmissibilities T), for per-iteration local solves
+hipError_t launch_darcy_factor_only(const DarcyTables& t, int n_units, int max_b, int max_np, double* E, double* L,
+                                    double* I, double* T, hipStream_t stream);
+// Method S1: Y = the Darcy part of S_H x for nvec vectors x (rows of M values)
+// through one local solve per (vector, Darcy subdomain); unit_of_dq[di nq + q]
+// is the unit of subdomain di for realization q = slot_q[s] (slot_q may be
+// null: q = s); the solutions z stay in zbuf (nvec x ndarcy x max_np); Y
+// may be null (solves only)
+hipError_t launch_darcy_s1_apply(const DarcyTables& t, const int* unit_of_dq, int nq, int nvec, const int* slot_q,
+                                 const int32_t* active, const double* x, int M, const int64_t* sub_dof_ptr,
+                                 const int64_t* sub_dofs, const double* L, const double* I, const double* T,
+                                 const double* E, double* zbuf, int ndarcy, int max_np, int max_b, double* Y,
+                                 int64_t SR, hipStream_t stream);
+// Method S1 moments: the fine Darcy fields of the nq realizations from zbuf
+// (after launch_darcy_s1_apply with x = lambda) into F (nq x (f1 + f2)), and
+// their weighted sums added to sum (E[p], E[p^2], E[u], E[u^2])
+hipError_t launch_darcy_s1_moments(const DarcyTables& t, const int* unit_of_dq, int nq, const double* lam, int M,
+                                   const int64_t* sub_dof_ptr, const int64_t* sub_dofs, const double* zbuf,
+                                   int ndarcy, int max_np, const int64_t* cell_out_off, const int64_t* edge_out_off,
+                                   int64_t f1, int64_t f2, double* F, const double* weights, const int64_t* gidx,
+                                   const double* colloc_w, double* sum, hipStream_t stream);
+constexpr int kS1MaxR = 256;       // Method S1: mortar DOFs of one Darcy subdomain
+constexpr int kS1MaxMedge = 512;   // Method S1: mortar edges of one Darcy subdomain
 hipError_t launch_darcy_basis_blocked_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np,
                                             double* S_cache, double* X, double* E, float* L32, float* I32,
                                             double* Tscr, float* W32, int max_refine, double refine_tol,

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libsdmm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, ESTATE, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 PREC = {"fp64": 0, "mixed": 1}
-METHOD = {"stochastic": 0, "deterministic": 1}
+METHOD = {"stochastic": 0, "deterministic": 1, "per_iteration": 2}
 FIELDS = {"lambda": 0, "darcy_p": 1, "darcy_u": 2, "stokes_u": 3, "stokes_p": 4}
 MAPS = {"interfaces": 0, "sub_ptr": 1, "sub_dofs": 2, "sub_sign": 3, "g2l": 4, "nlocal": 5, "node_ids": 6}
 
