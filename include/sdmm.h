@@ -176,6 +176,9 @@ typedef struct {
     double ms_cg_apply;           /* summed duration of the sampled products     */
     double ms_cg_update;          /* summed duration of the sampled updates      */
     double ms_moments;            /* last expansion of the moments to the fields */
+    double ms_basis_build;        /* last build, wall time: the Darcy units and the
+                                     Stokes subdomains run side by side, so this is
+                                     about the larger of the two times above    */
 } sdmm_counters;
 
 /* Create a context on HIP device `device`.  Ownership of *out passes to the

@@ -48,7 +48,7 @@ class CCounters(ctypes.Structure):
                                               "units_built", "refinement_steps", "cg_iterations", "realizations")] + \
                [(n, ctypes.c_double) for n in ("ms_basis_darcy", "ms_basis_stokes", "ms_solve", "max_refine_residual")] + \
                [(n, ctypes.c_int64) for n in ("cg_launches", "cg_timed_launches", "cg_timed_active", "cg_timed_columns")] + \
-               [(n, ctypes.c_double) for n in ("ms_cg_apply", "ms_cg_update", "ms_moments")]
+               [(n, ctypes.c_double) for n in ("ms_cg_apply", "ms_cg_update", "ms_moments", "ms_basis_build")]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)

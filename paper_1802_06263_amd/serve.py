@@ -167,8 +167,9 @@ class GpuBackend:
         self.M = self.sizes["M"]
         if slots is None:
             if autotune:
-                n = min(self.sizes["n_real"], 8192)
-                g = torch.arange(n, dtype=torch.int64, device="cuda")
+                # requests repeat points, so the sample is 8192 realizations even
+                # when the grid has fewer points (the slots then fill with repeats)
+                g = torch.arange(8192, dtype=torch.int64, device="cuda") % self.sizes["n_real"]
                 slots = self.ctx.autotune(g, stream=self.stream)
                 self.stream.synchronize()
             else:
