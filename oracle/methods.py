@@ -24,7 +24,7 @@ import numpy as np
 
 from . import interface as itf
 from .collocation import Grid
-from .darcy import DarcyLocal
+from .darcy import make_darcy_local
 from .geometry import Layout
 from .kl import cell_centres, region_field
 from .stokes import StokesLocal
@@ -96,7 +96,7 @@ class Oracle:
 
     def darcy_local(self, i, y_global):
         r = self.L.subs[i]["region"]
-        return DarcyLocal(self.L, i, self.darcy_K(i, self.region_point(y_global, r)))
+        return make_darcy_local(self.L, i, self.darcy_K(i, self.region_point(y_global, r)))
 
     def g_vector(self, darcy_locals):
         g = self.g_stokes.copy()
@@ -211,7 +211,7 @@ class Oracle:
             r = L.subs[i]["region"]
             ylocs = self.grid.local_points(r)
             for k in range(ylocs.shape[0]):
-                dl = DarcyLocal(L, i, self.darcy_K(i, ylocs[k]))
+                dl = make_darcy_local(L, i, self.darcy_K(i, ylocs[k]))
                 table[(i, k)] = dl.basis()
             self._count(i, L.sub_dofs[i].size * ylocs.shape[0])
         for i, S in self.stokes_basis().items():

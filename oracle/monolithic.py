@@ -7,9 +7,11 @@ system built from the forms of Section 3.2,
   b~(u, w) = -(q_d, w)
   b~_Lambda(u, mu) = 0,
 solved by sparse LU.  The Darcy part is kept in its mixed RT0-Q0 form
-(velocities on edges with the trapezoidal mass), so this path shares no
-cell-centred elimination with the domain-decomposition solvers; agreement
-of the two pins the interface reduction of Section 5.1.  Floating Stokes
+(velocities on edges with the trapezoidal mass, or with the exactly
+integrated mass that couples the two opposite faces of a cell), so this
+path shares neither the cell-centred nor the hybridized elimination of the
+domain-decomposition solvers; agreement of the two pins the interface
+reduction of Section 5.1.  Floating Stokes
 subdomains need no special treatment here.
 """
 import numpy as np
@@ -19,8 +21,17 @@ import scipy.sparse.linalg as spla
 from .stokes import StokesLocal
 
 
+def rt0_pair_mass(exact):
+    """Velocity mass of the two opposite faces of a unit cell with K = nu = 1,
+    in +x / +y oriented normal velocities: int phi_a phi_b for the linear
+    shape functions (1 - s) and s, or its trapezoidal (vertex) rule."""
+    if exact:
+        return np.array([[1.0 / 3.0, 1.0 / 6.0], [1.0 / 6.0, 1.0 / 3.0]])
+    return np.array([[0.5, 0.0], [0.0, 0.5]])
+
+
 def darcy_mixed(layout, i, K):
-    """RT0-Q0 blocks of Darcy subdomain i: (mass diag, B, Q, rhs_u, kept edges)."""
+    """RT0-Q0 blocks of Darcy subdomain i: (mass, B, Q, rhs_u, kept edges)."""
     s = layout.subs[i]
     nx, ny = s["n"]
     hx, hy = s["h"]
@@ -29,7 +40,18 @@ def darcy_mixed(layout, i, K):
     nv = (nx + 1) * ny
     ne = nv + nx * (ny + 1)
     N = nx * ny
-    mass = np.zeros(ne)
+    pm = rt0_pair_mass(layout.prob.get("discretization", {}).get("darcy", "trapezoidal") == "exact")
+    mr, mc, mv = [], [], []
+    for iy in range(ny):
+        for ix in range(nx):
+            c = iy * nx + ix
+            for pair in ((iy * (nx + 1) + ix, iy * (nx + 1) + ix + 1), (nv + iy * nx + ix, nv + (iy + 1) * nx + ix)):
+                for a in range(2):
+                    for b in range(2):
+                        mr.append(pair[a])
+                        mc.append(pair[b])
+                        mv.append(nu * area / K[c] * pm[a, b])
+    mass = sp.coo_matrix((mv, (mr, mc)), shape=(ne, ne)).tocsr()
     B = sp.lil_matrix((N, ne))
     for iy in range(ny):
         for ix in range(nx + 1):
@@ -37,7 +59,6 @@ def darcy_mixed(layout, i, K):
             for cx, sgn in ((ix - 1, -1.0), (ix, 1.0)):
                 if 0 <= cx < nx:
                     c = iy * nx + cx
-                    mass[e] += nu * area / (2.0 * K[c])
                     # cell on the left sees outward +x: -(div phi, 1_c) = -|e|
                     B[c, e] = sgn * hy
     for iy in range(ny + 1):
@@ -46,7 +67,6 @@ def darcy_mixed(layout, i, K):
             for cy, sgn in ((iy - 1, -1.0), (iy, 1.0)):
                 if 0 <= cy < ny:
                     c = cy * nx + ix
-                    mass[e] += nu * area / (2.0 * K[c])
                     B[c, e] = sgn * hx
     R = layout.sub_dofs[i].size
     Q = np.zeros((R, ne))
@@ -102,16 +122,16 @@ def system(layout, darcy_K, stokes=None):
         else:
             K = darcy_K[i]
             mass, B, Q, ru, keep = darcy_mixed(L, i, K)
-            Mk = sp.diags(mass[keep])
+            Mk = mass[keep][:, keep]
             Bk = B[:, keep]
             blk = sp.bmat([[Mk, Bk.T], [Bk, None]], format="csr")
-            Qfull = np.zeros((M, mass.size))
+            Qfull = np.zeros((M, mass.shape[0]))
             Qfull[L.sub_dofs[i]] = Q
             Qblk = sp.hstack([sp.csr_matrix(Qfull[:, keep]), sp.csr_matrix((M, B.shape[0]))])
             blocks_diag.append(blk)
             coup.append(Qblk)
             rhs_parts.append(np.concatenate([ru[keep], np.zeros(B.shape[0])]))
-            info.append(("darcy", i, keep, mass.size, B.shape[0]))
+            info.append(("darcy", i, keep, mass.shape[0], B.shape[0]))
     Bd = sp.block_diag(blocks_diag, format="csr")
     Qall = sp.hstack(coup, format="csr")
     rhs = np.concatenate(rhs_parts + [lam_rhs])

@@ -10,8 +10,17 @@ projected onto the compatible loads and the solution is taken orthogonal
 (in the Euclidean coefficient inner product) to the kernel Z_i of rigid
 motions that the BJS term leaves free.
 
-Readings: Q2-Q1 on rectangles (the numerical cases of the paper use the
-triangular pair); 3x3 Gauss per element; the velocity (inflow, optionally
+Readings: Q2-Q1 on rectangles by default; 3x3 Gauss per element.  The
+triangular Taylor-Hood pair P2-P1 of the paper's numerical cases (Section 6)
+is the alternative element: every rectangle is cut into two right triangles
+along a diagonal, which puts the P2 nodes on the same (2nx+1) x (2ny+1) node
+grid as Q2 (the diagonal midpoint is the rectangle centre) and the P1
+pressures on the Q1 vertices, so both pairs share every index map.  The
+diagonal runs from the lower-left to the upper-right corner except in the
+lower-right and upper-left corner rectangles of a subdomain, which take the
+other diagonal, so that no triangle has two edges on the subdomain boundary.
+P2-P1 integrals use the edge-midpoint rule, exact for the degree-2
+integrands of both forms.  The velocity (inflow, optionally
 with a linear shear profile in y) is imposed on the whole Stokes outer
 boundary; the BJS coefficient uses the deterministic
 permeability k_bjs, so every Stokes operator is deterministic.
@@ -81,8 +90,76 @@ def element_matrices(hx, hy, nu):
     return A, B
 
 
+# triangles of one rectangle, as (a, b) corners on its 3x3 node grid (node
+# 3*b + a at (a hx/2, b hy/2)); "/" cuts along (0,0)-(2,2), "\\" along (2,0)-(0,2)
+_TRIANGLES = {"/": (((0, 0), (2, 0), (2, 2)), ((0, 0), (2, 2), (0, 2))),
+              "\\": (((0, 0), (2, 0), (0, 2)), ((2, 0), (2, 2), (0, 2)))}
+# edge-midpoint rule on a triangle: barycentric points, weights times |T|
+_TRI_RULE = (np.array([[0.5, 0.5, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5]]), np.full(3, 1.0 / 3.0))
+
+
+def diagonal(ex, ey, nx, ny):
+    """Cut of element (ex, ey) of an nx x ny subdomain for the P2-P1 pair."""
+    corner = (ex == nx - 1 and ey == 0) or (ex == 0 and ey == ny - 1)
+    return "\\" if corner else "/"
+
+
+def _pressure_node(a, b):
+    """Q1/P1 pressure node of the rectangle corner at (a, b) on its node grid."""
+    return 2 * (b // 2) + a // 2
+
+
+def element_matrices_p2p1(hx, hy, nu, diag):
+    """P2-P1 blocks of one rectangle cut into two triangles, in the layout of
+    element_matrices: 18x18 velocity block and 4x18 divergence block.
+
+    On a triangle with barycentric coordinates l_0, l_1, l_2 the P2 basis is
+    l_i (2 l_i - 1) at vertex i and 4 l_i l_j at the midpoint of edge ij;
+    the P1 pressure basis is l_i."""
+    A = np.zeros((18, 18))
+    B = np.zeros((4, 18))
+    pts, wts = _TRI_RULE
+    for tri in _TRIANGLES[diag]:
+        xy = np.array([[a * hx / 2.0, b * hy / 2.0] for a, b in tri])
+        # gradients of the barycentric coordinates: rows of the inverse of
+        # [[1, 1, 1], [x_0, x_1, x_2], [y_0, y_1, y_2]] (first column dropped)
+        T = np.vstack([np.ones(3), xy.T])
+        G = np.linalg.inv(T)[:, 1:]          # G[i] = grad l_i
+        area = 0.5 * abs(np.linalg.det(T))
+        vnode = [3 * b + a for a, b in tri]
+        enode = {(i, j): 3 * ((tri[i][1] + tri[j][1]) // 2) + (tri[i][0] + tri[j][0]) // 2
+                 for i, j in ((0, 1), (1, 2), (0, 2))}
+        pnode = [_pressure_node(a, b) for a, b in tri]
+        for lam, w in zip(pts, wts * area):
+            nodes, grads = [], []
+            for i in range(3):
+                nodes.append(vnode[i])
+                grads.append((4.0 * lam[i] - 1.0) * G[i])
+            for (i, j), nd in enode.items():
+                nodes.append(nd)
+                grads.append(4.0 * (lam[i] * G[j] + lam[j] * G[i]))
+            for m, gm in zip(nodes, grads):
+                for n, gn in zip(nodes, grads):
+                    A[2 * m, 2 * n] += w * nu * (2 * gn[0] * gm[0] + gn[1] * gm[1])
+                    A[2 * m + 1, 2 * n + 1] += w * nu * (2 * gn[1] * gm[1] + gn[0] * gm[0])
+                    A[2 * m + 1, 2 * n] += w * nu * gn[1] * gm[0]
+                    A[2 * m, 2 * n + 1] += w * nu * gn[0] * gm[1]
+                for i in range(3):
+                    B[pnode[i], 2 * m] -= w * gm[0] * lam[i]
+                    B[pnode[i], 2 * m + 1] -= w * gm[1] * lam[i]
+    return A, B
+
+
+def stokes_element(layout):
+    """'q2q1' (rectangles) or 'p2p1' (triangles) from the problem's discretization."""
+    el = layout.prob.get("discretization", {}).get("stokes", "q2q1")
+    if el not in ("q2q1", "p2p1"):
+        raise ValueError("unknown Stokes element %r" % el)
+    return el
+
+
 class StokesLocal:
-    """Local Q2-Q1 operator of one Stokes subdomain."""
+    """Local Q2-Q1 or P2-P1 operator of one Stokes subdomain."""
 
     def __init__(self, layout, i):
         self.layout, self.i = layout, i
@@ -96,10 +173,15 @@ class StokesLocal:
         self.nnx, self.nny = 2 * nx + 1, 2 * ny + 1
         self.nvel = 2 * self.nnx * self.nny
         self.npre = (nx + 1) * (ny + 1)
-        Ae, Be = element_matrices(hx, hy, nu)
+        self.element = stokes_element(layout)
+        if self.element == "q2q1":
+            blocks = dict.fromkeys(("/", "\\"), element_matrices(hx, hy, nu))
+        else:
+            blocks = {d: element_matrices_p2p1(hx, hy, nu, d) for d in ("/", "\\")}
         rows, cols, vals, brow, bcol, bval = [], [], [], [], [], []
         for ey in range(ny):
             for ex in range(nx):
+                Ae, Be = blocks[diagonal(ex, ey, nx, ny)]
                 nodes = [(2 * ey + b) * self.nnx + 2 * ex + a for b in range(3) for a in range(3)]
                 dofs = np.array([[2 * n, 2 * n + 1] for n in nodes]).ravel()
                 pn = np.array([(ey + b) * (nx + 1) + ex + a for b in range(2) for a in range(2)])

@@ -75,8 +75,11 @@ def _couette_error(o, f):
     return err
 
 
-def test_couette_over_bjs_interface_all_methods_and_monolithic():
-    o = Oracle(_couette("cfg0"))
+@pytest.mark.parametrize("element", ["q2q1", "p2p1"])
+def test_couette_over_bjs_interface_all_methods_and_monolithic(element):
+    p = _couette("cfg0")
+    p["discretization"] = {"stokes": element}
+    o = Oracle(p)
     for meth in ("S1", "S2", "S3"):
         f, it, rel, ok = getattr(o, "realization_" + meth)(5, rtol=1e-13)
         assert ok
@@ -87,10 +90,13 @@ def test_couette_over_bjs_interface_all_methods_and_monolithic():
     assert _couette_error(o, m) < 1e-10
 
 
-def test_couette_with_floating_subdomains_and_stokes_stokes_mortars():
+@pytest.mark.parametrize("element", ["q2q1", "p2p1"])
+def test_couette_with_floating_subdomains_and_stokes_stokes_mortars(element):
     """4 x 2 Stokes subdomains (two floating, FETI) over 8 x 4 Darcy: the
-    Stokes-Stokes mortars carry the constant shear stress vector."""
+    Stokes-Stokes mortars carry the constant shear stress vector.  The
+    Couette field lies in both the rectangular and the triangular spaces."""
     p = _couette("cfg2", stokes_mesh=(8, 8), darcy_mesh=(4, 4), mortar={"degree": 1, "elements": 2})
+    p["discretization"] = {"stokes": element}
     o = Oracle(p)
     assert o.G.shape[1] == 4
     for l in (0, 3000):

@@ -15,6 +15,11 @@ A problem is a plain dict (JSON-serialisable):
   regions     list of KL regions {rect, nterm, sigma2, eta: [e1, e2],
               mean_logk}; each is an exact union of Darcy subdomains.
   rule        {kind: "tensor", m} or {kind: "sparse", level, growth}
+  discretization  optional {stokes: "q2q1"|"p2p1", darcy: "trapezoidal"|"exact"}:
+              the Stokes pair (Q2-Q1 on rectangles, or triangular
+              Taylor-Hood P2-P1 with two triangles per rectangle) and the
+              integration of the RT0 velocity mass; the default is
+              Q2-Q1 with the trapezoidal mass.
 
 Every random draw is seeded; the layouts are the coupled Stokes-over-Darcy
 geometries of the paper's numerical section (Section 6), scaled to the
