@@ -137,6 +137,14 @@ typedef struct {
     int32_t rule_m;      /* tensor: points per dimension                       */
     int32_t rule_level;  /* sparse: l_max                                      */
     int32_t rule_growth; /* sparse: 0 -> 2^(p+1)-1 points at level p, 1 -> p+1 */
+    /* Stokes element: 0 Q2-Q1 on the rectangles, 1 triangular Taylor-Hood
+     * P2-P1 (Section 6), each rectangle cut into two triangles on the same
+     * node grid (the diagonal runs lower-left to upper-right, except in a
+     * subdomain's lower-right and upper-left corner rectangles)           */
+    int32_t stokes_element;
+    /* RT0 velocity mass of the Darcy subdomains: 0 trapezoidal (diagonal,
+     * the cell-centred 5-point system), 1 exact integration (Section 6)   */
+    int32_t darcy_mass;
 } sdmm_problem;
 
 typedef struct {

@@ -275,6 +275,13 @@ DarcyTables darcy_tables(Prob* c) {
     return t;
 }
 
+// T scratch of one unit: K, the transmissibilities and the mortar-edge
+// terms (5-point operator), or K and the five band diagonals of the padded
+// face-pressure system (exact mass)
+static int64_t darcy_tscr(const DarcyHost& h) {
+    return h.exact ? (int64_t)h.N + 5LL * ((h.Ns + 15) / 16 * 16) : 4LL * h.N + h.n_medge;
+}
+
 int setup_device(Prob* ctx) {
     Problem& P = ctx->P;
     const int nsub = (int)P.subs.size();
@@ -320,6 +327,9 @@ int setup_device(Prob* ctx) {
         d.N = h.N;
         d.swap = h.swap;
         d.b = h.b;
+        d.exact = h.exact;
+        d.Ns = h.Ns;
+        d.bs = h.bs;
         d.R = h.R;
         d.nterm = h.nterm;
         d.n_medge = h.n_medge;
@@ -394,18 +404,18 @@ int setup_device(Prob* ctx) {
             u.off_T = T_off;
             u.off_I = I_off;
             // the blocked factor pads rows to a multiple of 16 and the band to bp
-            const int64_t Np = (h.N + 15) / 16 * 16, bp = (h.b + 15) / 16 * 16;
+            const int64_t Np = (h.Ns + 15) / 16 * 16, bp = (h.bs + 15) / 16 * 16;
             S_off += (int64_t)h.R * h.R;
             X_off += Np * h.R;
             L_off += Np * (bp + 1);
             I_off += Np * 16;
-            T_off += (int64_t)4 * h.N + h.n_medge;
+            T_off += darcy_tscr(h);
             A_off += (int64_t)h.R + (int64_t)h.R * h.R;
             ctx->units.push_back(u);
             ctx->pair_sub.push_back(i);
             ctx->pair_k.push_back(k);
         }
-        ctx->max_b = std::max(ctx->max_b, h.b);
+        ctx->max_b = std::max(ctx->max_b, h.bs);
         ctx->max_R = std::max(ctx->max_R, h.R);
         ctx->max_Rd = std::max(ctx->max_Rd, h.R);
         int nout = h.N + (h.nx + 1) * h.ny + h.nx * (h.ny + 1);
@@ -426,12 +436,12 @@ int setup_device(Prob* ctx) {
         std::map<std::pair<int, int>, std::vector<int>> cls;
         for (size_t u = 0; u < ctx->units.size(); ++u) {
             const DarcyHost& h = P.darcy[ctx->units[u].d];
-            cls[{(h.b + 15) / 16 * 16, (h.R + 3) & ~3}].push_back((int)u);
+            cls[{(h.bs + 15) / 16 * 16, (h.R + 3) & ~3}].push_back((int)u);
         }
         std::vector<std::pair<double, std::pair<int, int>>> rank;
         for (auto& kv : cls) {
             const DarcyHost& h = P.darcy[ctx->units[kv.second[0]].d];
-            const double cost = (double)h.N * kv.first.first * (kv.first.first + kv.first.second);
+            const double cost = (double)h.Ns * kv.first.first * (kv.first.first + kv.first.second);
             rank.push_back({-cost, kv.first});
         }
         std::sort(rank.begin(), rank.end());
@@ -440,7 +450,7 @@ int setup_device(Prob* ctx) {
         for (auto& rk : rank) {
             const auto& ids = cls[rk.second];
             int np = 0;
-            for (int u : ids) np = std::max(np, (P.darcy[ctx->units[u].d].N + 15) / 16 * 16);
+            for (int u : ids) np = std::max(np, (P.darcy[ctx->units[u].d].Ns + 15) / 16 * 16);
             ctx->classes.push_back({(int)ctx->h_order.size(), (int)ids.size(), rk.second.first, rk.second.second, np});
             ctx->h_order.insert(ctx->h_order.end(), ids.begin(), ids.end());
         }
@@ -1150,7 +1160,7 @@ int impl_get_sizes(Prob* ctx, sdmm_sizes* o) {
     int64_t fl = 0;
     for (auto& u : ctx->units) {
         const DarcyHost& h = P.darcy[u.d];
-        fl += (int64_t)h.N * h.b * h.b + 4LL * h.N * h.b * h.R;
+        fl += (int64_t)h.Ns * h.bs * h.bs + 4LL * h.Ns * h.bs * h.R;
     }
     o->darcy_flops = fl;
     return SDMM_OK;
@@ -1226,6 +1236,8 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     if (precision != SDMM_PREC_FP64 && precision != SDMM_PREC_MIXED) return fail(ctx, SDMM_EINVAL, "bad precision");
     if (method != SDMM_METHOD_STOCHASTIC && method != SDMM_METHOD_DETERMINISTIC && method != SDMM_METHOD_PER_ITERATION)
         return fail(ctx, SDMM_EINVAL, "bad method");
+    if (ctx->P.in.darcy_mass == 1 && (precision != SDMM_PREC_FP64 || method == SDMM_METHOD_PER_ITERATION))
+        return fail(ctx, SDMM_EINVAL, "the exact RT0 mass is built in FP64 for Methods S2 and S3");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipEventRecord(ctx->ev[0], st));
@@ -1238,7 +1250,8 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     } else if (precision == SDMM_PREC_FP64) {
         HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, int np, hipStream_t q) {
             return launch_darcy_basis_blocked(tc, count, bp, Rs, np, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
-                                              ctx->d_L.as<double>(), ctx->d_I.as<double>(), ctx->d_T.as<double>(), q);
+                                              ctx->d_L.as<double>(), ctx->d_I.as<double>(), ctx->d_T.as<double>(),
+                                              ctx->P.in.darcy_mass, q);
         }));
     } else {
         int rc;
@@ -1740,7 +1753,7 @@ int det_layout(Prob* ctx, int64_t n, bool resident = false) {
                 D.chunk_start.push_back((int)D.units.size());
                 L_off = T_off = I_off = 0;
             }
-            const int64_t Np = (h.N + 15) / 16 * 16, bp = (h.b + 15) / 16 * 16;
+            const int64_t Np = (h.Ns + 15) / 16 * 16, bp = (h.bs + 15) / 16 * 16;
             UnitDev u{};
             u.d = (int)di;
             u.k = (int)q;
@@ -1753,7 +1766,7 @@ int det_layout(Prob* ctx, int64_t n, bool resident = false) {
             u.off_I = I_off;
             X_off += Np * h.R;
             L_off += Np * (bp + 1);
-            T_off += (int64_t)4 * h.N + h.n_medge;
+            T_off += darcy_tscr(h);
             I_off += Np * 16;
             L_max = std::max(L_max, L_off);
             T_max = std::max(T_max, T_off);
@@ -1838,7 +1851,7 @@ int det_build(Prob* ctx, const std::vector<double>& y, hipStream_t st) {
     t.order = D.d_order.as<int>();
     t.xi = D.d_xi.as<double>();
     int max_np = 0;
-    for (auto& h : ctx->P.darcy) max_np = std::max(max_np, (h.N + 15) / 16 * 16);
+    for (auto& h : ctx->P.darcy) max_np = std::max(max_np, (h.Ns + 15) / 16 * 16);
     const bool mixed = D.precision == SDMM_PREC_MIXED;
     if (mixed) HIPCHK(hipMemsetAsync(D.d_refine.p, 0, 16, st));
     for (size_t c = 0; c + 1 < D.chunk_start.size(); ++c) {
@@ -1854,7 +1867,7 @@ int det_build(Prob* ctx, const std::vector<double>& y, hipStream_t st) {
         else
             HIPCHK(launch_darcy_basis_blocked(t, count, ctx->max_b, ctx->max_Rd, max_np, D.d_S.as<double>(),
                                               D.d_X.as<double>(), D.d_L.as<double>(), D.d_I.as<double>(),
-                                              D.d_T.as<double>(), st));
+                                              D.d_T.as<double>(), ctx->P.in.darcy_mass, st));
     }
     const Problem& P = ctx->P;
     std::vector<int64_t> sbase(P.subs.size());

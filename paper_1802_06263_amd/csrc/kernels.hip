@@ -829,6 +829,7 @@ hipError_t launch_accumulate_chunks(const MomArgs& m, const int4* awork, int naw
 __device__ inline int darcy_response_row(const DarcyTables& t, const DarcyDev& D, const double* xi, const double* X,
                                          int o, double* F) {
     // fills F (R values) with the response row of output o; returns 0 when zero
+    if (D.exact) return exact_response_row(t, D, xi, X, o, F);
     const int R = D.R, nx = D.nx, ny = D.ny, N = D.N;
     if (o < N) {
         const int ci = internal_of_cell(o, nx, ny, D.swap);

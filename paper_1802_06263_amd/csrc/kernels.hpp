@@ -8,6 +8,9 @@ namespace sdmm {
 // Per Darcy subdomain (device-resident table entry).
 struct DarcyDev {
     int nx, ny, N, swap, b, R, nterm, n_medge;
+    // the factored system: the N cells (trapezoidal mass, half bandwidth b)
+    // or, with the exact mass, Ns face pressures of half bandwidth bs
+    int exact, Ns, bs, pad;
     double hx, hy, nu, mean_logk;
     int64_t off_be;     // boundary-edge arrays (2 (nx + ny) entries)
     int64_t off_cellbe; // 2 entries per cell (row-major): boundary edge ids or -1
@@ -56,8 +59,9 @@ constexpr int kMaxDarcyBand = 112;   // largest padded half-bandwidth of a Darcy
 size_t darcy_factor_lds(int bp, size_t elem);
 size_t darcy_solve_lds(int bp, int R, size_t elem);
 // max_np: largest padded cell count of the launch's units
+// exact != 0: the hybridized system of the exactly integrated RT0 mass (FP64)
 hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np,
-                                      double* S_cache, double* X, double* Lscr, double* Iscr, double* Tscr,
+                                      double* S_cache, double* X, double* Lscr, double* Iscr, double* Tscr, int exact,
                                       hipStream_t stream);
 // Method S1: the band factors of the units only (mortar loads E, factor L,
 // block inverses I, transmissibilities T), for per-iteration local solves

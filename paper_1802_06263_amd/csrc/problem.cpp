@@ -263,6 +263,9 @@ static std::string build_darcy(Problem& P, int i, DarcyHost& d) {
     d.N = s.nx * s.ny;
     d.swap = s.nx > s.ny ? 1 : 0;
     d.b = std::min(s.nx, s.ny);
+    d.exact = P.in.darcy_mass == 1;
+    d.Ns = d.exact ? std::max(s.nx, s.ny) * (2 * d.b + 1) + d.b : d.N;
+    d.bs = d.exact ? 2 * d.b + 1 : d.b;
     d.hx = s.hx;
     d.hy = s.hy;
     d.R = (int)(P.sub_ptr[i + 1] - P.sub_ptr[i]);
@@ -382,6 +385,82 @@ static void compress(std::vector<Trip>& t) {
     t.resize(w);
 }
 
+// P2-P1 (triangular Taylor-Hood, the pair of the numerical cases of Section
+// 6) on one rectangle cut into two right triangles, accumulated into the
+// 18x18 / 4x18 blocks of the Q2-Q1 layout: the P2 nodes of both triangles are
+// the 3x3 node grid of the rectangle (node 3b+a at (a hx/2, b hy/2), the
+// diagonal midpoint is the centre) and the P1 pressures its four corners.
+// cut 0 runs the diagonal from (0,0) to (hx,hy), cut 1 from (hx,0) to (0,hy).
+// With barycentric coordinates l_k every P2 gradient is linear,
+//   grad(l_i (2 l_i - 1)) = sum_k (4 delta_ik - 1) l_k grad l_i,
+//   grad(4 l_i l_j)       = 4 l_j grad l_i + 4 l_i grad l_j,
+// so both forms are sums of the exact moments int_T l_k l_l = |T| (1 + delta_kl) / 12.
+static void p2p1_blocks(double hx, double hy, double nu, int cut, double Ae[18][18], double Be[4][18]) {
+    static const int tri[2][2][3][2] = {{{{0, 0}, {2, 0}, {2, 2}}, {{0, 0}, {2, 2}, {0, 2}}},
+                                        {{{0, 0}, {2, 0}, {0, 2}}, {{2, 0}, {2, 2}, {0, 2}}}};
+    for (int m = 0; m < 18; ++m) {
+        for (int n = 0; n < 18; ++n) Ae[m][n] = 0.0;
+        for (int q = 0; q < 4; ++q) Be[q][m] = 0.0;
+    }
+    for (int t = 0; t < 2; ++t) {
+        const int(*v)[2] = tri[cut][t];
+        double x[3], y[3];
+        for (int k = 0; k < 3; ++k) {
+            x[k] = 0.5 * hx * v[k][0];
+            y[k] = 0.5 * hy * v[k][1];
+        }
+        const double det = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]);
+        const double area = 0.5 * std::fabs(det);
+        double gl[3][2];  // grad l_k
+        for (int k = 0; k < 3; ++k) {
+            const int a = (k + 1) % 3, b = (k + 2) % 3;
+            gl[k][0] = (y[a] - y[b]) / det;
+            gl[k][1] = (x[b] - x[a]) / det;
+        }
+        // six P2 functions: node on the 3x3 grid, gradient coefficients c[k] (grad = sum_k l_k c[k])
+        int node[6];
+        double c[6][3][2] = {};
+        for (int i = 0; i < 3; ++i) {
+            node[i] = 3 * v[i][1] + v[i][0];
+            for (int k = 0; k < 3; ++k)
+                for (int d = 0; d < 2; ++d) c[i][k][d] = (k == i ? 3.0 : -1.0) * gl[i][d];
+        }
+        for (int e = 0; e < 3; ++e) {
+            const int i = e, j = (e + 1) % 3;
+            node[3 + e] = 3 * ((v[i][1] + v[j][1]) / 2) + (v[i][0] + v[j][0]) / 2;
+            for (int d = 0; d < 2; ++d) {
+                c[3 + e][j][d] = 4.0 * gl[i][d];
+                c[3 + e][i][d] = 4.0 * gl[j][d];
+            }
+        }
+        int pn[3];
+        for (int k = 0; k < 3; ++k) pn[k] = 2 * (v[k][1] / 2) + v[k][0] / 2;
+        double mom[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) mom[k][l] = area * (k == l ? 2.0 : 1.0) / 12.0;
+        for (int m = 0; m < 6; ++m)
+            for (int n = 0; n < 6; ++n) {
+                double g[2][2] = {};  // g[dm][dn] = int d_dm(phi_m) d_dn(phi_n)
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l)
+                        for (int dm = 0; dm < 2; ++dm)
+                            for (int dn = 0; dn < 2; ++dn) g[dm][dn] += c[m][k][dm] * c[n][l][dn] * mom[k][l];
+                const int M = node[m], N = node[n];
+                Ae[2 * M][2 * N] += nu * (2.0 * g[0][0] + g[1][1]);
+                Ae[2 * M + 1][2 * N + 1] += nu * (2.0 * g[1][1] + g[0][0]);
+                Ae[2 * M + 1][2 * N] += nu * g[0][1];
+                Ae[2 * M][2 * N + 1] += nu * g[1][0];
+            }
+        for (int n = 0; n < 6; ++n)
+            for (int q = 0; q < 3; ++q)
+                for (int d = 0; d < 2; ++d) {
+                    double s = 0.0;
+                    for (int k = 0; k < 3; ++k) s += c[n][k][d] * mom[k][q];
+                    Be[pn[q]][2 * node[n] + d] -= s;
+                }
+    }
+}
+
 static std::string build_stokes(Problem& P, int i, StokesHost& S) {
     const Sub& s = P.subs[i];
     const sdmm_problem& in = P.in;
@@ -439,6 +518,13 @@ static std::string build_stokes(Problem& P, int i, StokesHost& S) {
                     Be[q][2 * n] -= hy * DL[an][qa] * ML[bn][qb];
                     Be[q][2 * n + 1] -= hx * ML[an][qa] * DL[bn][qb];
                 }
+    // the triangular pair: two cuts (the lower-right and upper-left corner
+    // rectangles take the diagonal through their outer corner, so no triangle
+    // has two edges on the subdomain boundary)
+    double At[2][18][18], Bt[2][4][18];
+    const bool tri = in.stokes_element == 1;
+    if (tri)
+        for (int c = 0; c < 2; ++c) p2p1_blocks(hx, hy, nu, c, At[c], Bt[c]);
     std::vector<Trip> A, B;
     A.reserve((size_t)s.nx * s.ny * 324 + 1000);
     B.reserve((size_t)s.nx * s.ny * 72);
@@ -453,12 +539,15 @@ static std::string build_stokes(Problem& P, int i, StokesHost& S) {
                 }
             for (int b = 0; b < 2; ++b)
                 for (int a = 0; a < 2; ++a) pn[2 * b + a] = (ey + b) * (s.nx + 1) + ex + a;
+            const int cut = (ex == s.nx - 1 && ey == 0) || (ex == 0 && ey == s.ny - 1);
+            const double(*Ause)[18] = tri ? At[cut] : Ae;
+            const double(*Buse)[18] = tri ? Bt[cut] : Be;
             for (int m = 0; m < 18; ++m)
                 for (int n = 0; n < 18; ++n)
-                    if (Ae[m][n] != 0.0) A.push_back({dofs[m], dofs[n], Ae[m][n]});
+                    if (Ause[m][n] != 0.0) A.push_back({dofs[m], dofs[n], Ause[m][n]});
             for (int q = 0; q < 4; ++q)
                 for (int n = 0; n < 18; ++n)
-                    if (Be[q][n] != 0.0) B.push_back({pn[q], dofs[n], Be[q][n]});
+                    if (Buse[q][n] != 0.0) B.push_back({pn[q], dofs[n], Buse[q][n]});
         }
     // boundary: Dirichlet nodes, traces against mortar functions, BJS
     std::vector<char> dir(nnx * nny, 0);
@@ -674,6 +763,8 @@ std::string build_problem(const sdmm_problem& in, Problem& P) {
     P.in = in;
     if (in.n_sub <= 0 || !in.sub_type || !in.sub_rect || !in.sub_n || !in.sub_region) return "no subdomains";
     if (in.mortar_degree != 1 && in.mortar_degree != 2) return "mortar degree must be 1 or 2";
+    if (in.stokes_element != 0 && in.stokes_element != 1) return "Stokes element must be 0 (Q2-Q1) or 1 (P2-P1)";
+    if (in.darcy_mass != 0 && in.darcy_mass != 1) return "Darcy mass must be 0 (trapezoidal) or 1 (exact)";
     if (in.mortar_elements < 1) return "mortar elements must be positive";
     if (in.p_bottom != 0.0) return "the GPU path requires p_bottom == 0";
     if (in.nu_s <= 0 || in.nu_d <= 0 || in.k_bjs <= 0 || in.alpha < 0) return "invalid physical parameters";
@@ -697,6 +788,10 @@ std::string build_problem(const sdmm_problem& in, Problem& P) {
         } else {
             P.n_darcy++;
             if (s.region < 0 || s.region >= in.n_region) return "Darcy subdomain with an invalid KL region";
+            // the face-pressure band (2 min(nx, ny) + 1, padded to 16) must fit the
+            // factor's LDS window, and every cell has at most two boundary faces
+            if (in.darcy_mass == 1 && (std::min(s.nx, s.ny) < 2 || std::min(s.nx, s.ny) > 55))
+                return "the exact RT0 mass needs 2 <= min(nx, ny) <= 55 on every Darcy subdomain";
         }
         P.subs.push_back(s);
     }

@@ -44,6 +44,9 @@ struct MedgeTerm { int dof; double val; };
 struct DarcyHost {
     int sub;
     int nx, ny, N, swap, b;   // swap: internal order is y-fastest (nx > ny)
+    // factored system: the N cells (half bandwidth b), or with the exact
+    // RT0 mass the Ns = nyi (2 nxi + 1) + nxi face pressures (bs = 2 nxi + 1)
+    int exact, Ns, bs;
     double hx, hy;
     int R;
     // boundary edges: 2(nx+ny), ordered bottom, top, left, right

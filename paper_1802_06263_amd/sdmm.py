@@ -33,7 +33,7 @@ class CProblem(ctypes.Structure):
                 ("n_region", ctypes.c_int32), ("region_rect", _f64p), ("region_nterm", _i32p),
                 ("region_sigma2", _f64p), ("region_eta", _f64p), ("region_mean_logk", _f64p),
                 ("rule_kind", ctypes.c_int32), ("rule_m", ctypes.c_int32), ("rule_level", ctypes.c_int32),
-                ("rule_growth", ctypes.c_int32)]
+                ("rule_growth", ctypes.c_int32), ("stokes_element", ctypes.c_int32), ("darcy_mass", ctypes.c_int32)]
 
 
 class CSizes(ctypes.Structure):
@@ -252,6 +252,9 @@ class Context:
         c.rule_m = int(rule.get("m", 0))
         c.rule_level = int(rule.get("level", 0))
         c.rule_growth = 0 if rule.get("growth", "paper") == "paper" else 1
+        disc = prob.get("discretization", {})
+        c.stokes_element = {"q2q1": 0, "p2p1": 1}[disc.get("stokes", "q2q1")]
+        c.darcy_mass = {"trapezoidal": 0, "exact": 1}[disc.get("darcy", "trapezoidal")]
         pid = ctypes.c_int64()
         self._check(self.lib.sdmm_set_problem(self.h, ctypes.byref(c), ctypes.byref(pid)))
         self.pid = pid.value

@@ -1,0 +1,175 @@
+"""Discretization variants of Section 6 on the device (needs an MI355X): the
+triangular Taylor-Hood pair and the exactly integrated RT0 mass.
+
+Triangular Taylor-Hood (P2-P1, two triangles per rectangle on the Q2-Q1 node
+grid) against the oracle's StokesLocal with the same element:
+  * every Stokes S_{H,i} (FP64 band LDL^T, one refinement step): 1e-11
+    relative to max|S|, the bar of the Q2-Q1 blocks;
+  * lambda and the five fields' means and variances at rtol 1e-12: 1e-9,
+    on the two-region layout and on the small layout with two floating
+    Stokes subdomains (FETI);
+  * at full size (4x2 Stokes subdomains of 64x64 elements), the S blocks of
+    one Stokes subdomain on the outer boundary and of one floating one.
+"""
+import numpy as np
+import pytest
+
+from oracle.geometry import Layout
+from oracle.methods import FIELDS, Oracle
+from oracle.stokes import StokesLocal
+from workloads import problem
+
+from gpu_helpers import gpu_ctx, gpu_solve, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _with(prob, **disc):
+    prob = dict(prob)
+    prob["discretization"] = dict(disc)
+    return prob
+
+
+def _small_feti():
+    return problem("cfg2", stokes_mesh=(8, 8), darcy_mesh=(4, 4), mortar={"degree": 1, "elements": 2})
+
+
+def _check_moments(ctx, mom, tol):
+    for f in FIELDS:
+        mg, vg = ctx.get_moments(f)
+        mo, vo = mom[f]
+        assert rel(mg, mo) < tol, (f, rel(mg, mo))
+        assert np.abs(vg - vo).max() < tol * max(np.abs(vo).max(), 1e-12 * np.abs(mo).max() ** 2), f
+
+
+@pytest.mark.parametrize("name", ["cfg0", "small"])
+def test_p2p1_matches_oracle(name):
+    print("case: P2-P1 Stokes element,", name, flush=True)
+    import torch
+    prob = _with(_small_feti() if name == "small" else problem("cfg0"), stokes="p2p1")
+    o = Oracle(prob)
+    o.stochastic_basis()
+    ctx = gpu_ctx(prob, "fp64")
+    for i in o.stokes_ids:
+        S = o.s3_table[(i, 0)]
+        assert rel(ctx.get_basis(i, 0, S.shape[0]), S) < 1e-11, i
+    if name == "small":
+        assert ctx.sizes()["n_kernel"] == 4
+        idx, w = [0, 17, 4000, 6560], np.array([0.1, 0.2, 0.3, 0.4])
+    else:
+        idx, w = list(range(o.grid.nreal)), None
+    g, lam, it, rr, st, rc = gpu_solve(ctx, idx, rtol=1e-12)
+    assert (st == 0).all()
+    mom, info = o.run("S3", indices=idx, weights=w, rtol=1e-12)
+    assert rel(lam.cpu().numpy(), np.stack([d["lambda"] for d in info])) < 1e-9
+    ctx.accumulate_moments(g, lam, None if w is None else torch.tensor(w, device="cuda"))
+    _check_moments(ctx, mom, 1e-9)
+    ctx.close()
+
+
+def test_p2p1_full_size_stokes_blocks():
+    print("case: P2-P1 Stokes blocks on the 4x2 layout of 64x64 elements", flush=True)
+    prob = _with(problem("cfg2"), stokes="p2p1")
+    L = Layout(prob)
+    ctx = gpu_ctx(prob, "fp64")
+    floating = [i for i in range(L.n_stokes) if L.is_floating(i)]
+    assert floating
+    for i in (0, floating[0]):
+        S = StokesLocal(L, i).basis()
+        assert rel(ctx.get_basis(i, 0, S.shape[0]), S) < 1e-11, i
+    ctx.close()
+
+
+# ---- exactly integrated RT0 mass (hybridized face-pressure system) ----------
+#   * every Darcy S_{H,i}^{(k)} (FP64 band Cholesky of the face-pressure
+#     system, no refinement): 1e-11 relative to max|S|;
+#   * lambda and the five fields at rtol 1e-12: 1e-9, with Methods S3 and S2;
+#   * on the 4x2 Stokes over 8x4 Darcy layout with 48x48 Darcy meshes
+#     (the largest that fits the factor's LDS window: band 2 min(nx, ny) + 1),
+#     sampled units of three Darcy subdomains;
+#   * the mixed precision path and Method S1 refuse the exact mass (EINVAL).
+
+
+@pytest.mark.parametrize("name", ["cfg0", "small"])
+def test_exact_rt0_matches_oracle(name):
+    print("case: exact RT0 mass,", name, flush=True)
+    import torch
+    prob = _with(_small_feti() if name == "small" else problem("cfg0"), darcy="exact")
+    o = Oracle(prob)
+    o.stochastic_basis()
+    ctx = gpu_ctx(prob, "fp64")
+    for (i, k), S in o.s3_table.items():
+        if i in o.darcy_ids and (name == "cfg0" or k in (0, 4, 8)):
+            assert rel(ctx.get_basis(i, k, S.shape[0]), S) < 1e-11, (i, k, rel(ctx.get_basis(i, k, S.shape[0]), S))
+    if name == "small":
+        idx, w = [0, 17, 4000, 6560], np.array([0.1, 0.2, 0.3, 0.4])
+    else:
+        idx, w = list(range(o.grid.nreal)), None
+    g, lam, it, rr, st, rc = gpu_solve(ctx, idx, rtol=1e-12)
+    assert (st == 0).all()
+    mom, info = o.run("S3", indices=idx, weights=w, rtol=1e-12)
+    assert rel(lam.cpu().numpy(), np.stack([d["lambda"] for d in info])) < 1e-9
+    ctx.accumulate_moments(g, lam, None if w is None else torch.tensor(w, device="cuda"))
+    _check_moments(ctx, mom, 1e-9)
+    ctx.close()
+
+
+def test_exact_rt0_method_s2_matches_oracle():
+    print("case: exact RT0 mass, Method S2 on the two-region layout", flush=True)
+    import torch
+    from paper_1802_06263_amd import sdmm
+    prob = _with(problem("cfg0"), darcy="exact")
+    o = Oracle(prob)
+    idx = [1, 6, 11]
+    w = np.array([0.5, 0.3, 0.2])
+    mom, info = o.run("S2", indices=idx, weights=w, rtol=1e-12)
+    ctx = sdmm.Context(0)
+    ctx.set_problem(prob)
+    ctx.build_flux_basis("fp64", method="deterministic")
+    M = ctx.sizes()["M"]
+    gi = torch.tensor(idx, dtype=torch.int64, device="cuda")
+    lam = torch.zeros((len(idx), M), dtype=torch.float64, device="cuda")
+    st = torch.zeros(len(idx), dtype=torch.int32, device="cuda")
+    ctx.solve_interface(gi, lam, rtol=1e-12, status=st)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    assert rel(lam.cpu().numpy(), np.stack([d["lambda"] for d in info])) < 1e-9
+    ctx.reset_moments()
+    ctx.accumulate_moments(gi, lam, torch.tensor(w, device="cuda"))
+    _check_moments(ctx, mom, 1e-9)
+    ctx.close()
+
+
+def test_exact_rt0_sampled_units_48x48():
+    print("case: exact RT0 mass, sampled units of the 8x4 Darcy layout at 48x48", flush=True)
+    from oracle.collocation import Grid
+    from oracle.darcy import DarcyLocalExact
+    from oracle.kl import cell_centres, region_field
+    prob = _with(problem("cfg2", darcy_mesh=(48, 48)), darcy="exact")
+    L = Layout(prob)
+    grid = Grid(prob["regions"], prob["rule"])
+    ctx = gpu_ctx(prob, "fp64")
+    darcy = [i for i in range(L.nsub) if L.subs[i]["type"] == "darcy"]
+    rng = np.random.default_rng(13)
+    for i in (darcy[0], darcy[len(darcy) // 2], darcy[-1]):
+        sub = L.subs[i]
+        reg = L.regions[sub["region"]]
+        k = int(rng.integers(grid.nlocal[sub["region"]]))
+        y = grid.local_points(sub["region"])[k]
+        K = np.exp(float(reg["mean_logk"]) + np.asarray(y) @ region_field(reg, cell_centres(sub)))
+        S = DarcyLocalExact(L, i, K).basis()
+        assert rel(ctx.get_basis(i, k, S.shape[0]), S) < 1e-11, (i, k)
+    ctx.close()
+
+
+def test_exact_rt0_refuses_mixed_and_s1():
+    print("case: exact RT0 mass refuses mixed precision and Method S1", flush=True)
+    import torch  # noqa: F401
+    from paper_1802_06263_amd import sdmm
+    ctx = sdmm.Context(0)
+    ctx.set_problem(_with(problem("cfg0"), darcy="exact"))
+    for prec, meth in (("mixed", "stochastic"), ("fp64", "per_iteration")):
+        with pytest.raises(sdmm.SdmmError) as e:
+            ctx.build_flux_basis(prec, method=meth)
+        assert e.value.code == sdmm.EINVAL
+    ctx.close()
