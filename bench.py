@@ -340,17 +340,18 @@ def cg_whole(M, sum_R2, real_iters, ms_cg):
 def kernel_rooflines(sz, M, sum_R2, d, ms, prec, workload):
     """Per-kernel roofline entries.  The algorithmic unit of the CG kernels is
     one realization-iteration (one CG iteration of one realization still
-    iterating); the library times one (product, update) launch pair per
-    timed check group, with the other lane idle, and counts the realizations
-    active in it.  The product is priced by its 2 sum_i R_i^2 flops (FP64
-    MFMA; 2 M 8 bytes of vectors, above the ridge), the update by the 7 M 8
-    bytes an unfused update streams (the operator result, p, r and lambda
-    read; lambda, r and p written).  The basis builds are one unit per step."""
+    iterating); the library times two consecutive (product, update) launch
+    pairs per timed check group, with the other lane idle, and counts the
+    realizations active in them.  The product is priced by its 2 sum_i R_i^2
+    flops (FP64 MFMA; 2 M 8 bytes of vectors, above the ridge), the update by
+    the 6 M 8 bytes it streams per iteration on average (the operator result,
+    p and r read, r and p written, and lambda read and written in every other
+    iteration).  The basis builds are one unit per step."""
     out = {}
     nl = d["cg_timed_launches"]
     if nl:
         act = d["cg_timed_active"] / nl
-        b_upd = 7.0 * M * 8
+        b_upd = 6.0 * M * 8
         avg = d["ms_cg_update"] * 1e-3 / nl
         out["cg_update"] = {"kernel": "cg_update2_kernel", "bound": "hbm", "achieved": b_upd * act / avg / 1e9,
                             "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": b_upd * act / avg / PEAK_HBM,

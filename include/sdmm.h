@@ -370,12 +370,13 @@ int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
  *                      two lanes with their own streams, so that one lane's
  *                      operator product overlaps the other's update on the
  *                      device; 1 = one lane
- *   SDMM_OPT_KERNEL_TIMING n > 0 = time one iteration of every n-th check
- *                      group of the first lane with HIP events and sum the
- *                      durations into the counters; the second lane is
- *                      drained first and waits for the timed pair, so the
- *                      timed kernels run alone (those groups run eagerly,
- *                      the others replay the captured graph); 0 = off
+ *   SDMM_OPT_KERNEL_TIMING n > 0 = time two consecutive iterations of every
+ *                      n-th check group of the first lane with HIP events
+ *                      (the update writes lambda in every other iteration)
+ *                      and sum the durations into the counters; the second
+ *                      lane is drained first and waits for the timed pairs,
+ *                      so the timed kernels run alone (those groups run
+ *                      eagerly, the others replay the captured graph); 0 = off
  *   SDMM_OPT_STOKES_REBUILD 1 = every sdmm_build_flux_basis rebuilds the
  *                      Stokes basis too (0, the default: built once, since
  *                      it does not depend on the realization)

@@ -67,7 +67,7 @@ struct CgStream {
     double rtol = 1e-8;
     int32_t max_iter = 1;
     hipStream_t st = nullptr;
-    DevBuf r, p, Y, rr, r0, relres, iters, status, active, any, slot_q, init, lam;
+    DevBuf r, p, Y, rr, r0, pend, relres, iters, status, active, any, slot_q, init, lam;
     DevBuf g_slot, g_lam, g_it, g_rel, g_st;   // gather lists of finished realizations
     Groups G;
     std::vector<int> init_h, sel;
@@ -170,7 +170,7 @@ struct Prob {
     DevBuf d_flag; // index validation flag
     // CG workspace
     DevBuf w_slot_q, w_init;   // CG slot -> batch position; slots to start
-    DevBuf w_r, w_p, w_rr, w_r0, w_iters, w_relres, w_status, w_active, w_any, w_alpha, w_Slam;
+    DevBuf w_r, w_p, w_rr, w_r0, w_pend, w_iters, w_relres, w_status, w_active, w_any, w_alpha, w_Slam;
     int64_t w_cap = 0;
     // realization groups (grouped operator), one set per CG lane; the moment
     // passes use the first
@@ -855,6 +855,7 @@ CgArgs cg_args(Prob* ctx, int64_t n, const int64_t* gidx, double* lam) {
     a.p = ctx->w_p.as<double>();
     a.rr = ctx->w_rr.as<double>();
     a.r0 = ctx->w_r0.as<double>();
+    a.pend = ctx->w_pend.as<double>();
     a.iters = ctx->w_iters.as<int32_t>();
     a.relres = ctx->w_relres.as<double>();
     a.status = ctx->w_status.as<int32_t>();
@@ -999,6 +1000,7 @@ int ensure_workspace(Prob* ctx, int64_t n) {
     if ((rc = alloc(ctx, ctx->w_Slam, n * M * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_rr, n * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_r0, n * 8))) return rc;
+    if ((rc = alloc(ctx, ctx->w_pend, n * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_iters, n * 4))) return rc;
     if ((rc = alloc(ctx, ctx->w_relres, n * 8))) return rc;
     if ((rc = alloc(ctx, ctx->w_status, n * 4))) return rc;
@@ -1473,6 +1475,7 @@ int solve_batch(Prob* ctx, int64_t n, int64_t S, const int64_t* gidx, double rto
         a.p += L.base * M;
         a.rr += L.base;
         a.r0 += L.base;
+        a.pend += L.base;
         a.iters += L.base;
         a.relres += L.base;
         a.status += L.base;
@@ -1493,7 +1496,7 @@ int solve_batch(Prob* ctx, int64_t n, int64_t S, const int64_t* gidx, double rto
     int64_t next = 0;   // next batch position to start
     int ngroup = 0;
     if (ktime) {
-        while ((int)ctx->kev.size() < 4) {
+        while ((int)ctx->kev.size() < 8) {
             hipEvent_t e = nullptr;
             HIPCHK(hipEventCreate(&e));
             ctx->kev.push_back(e);
@@ -1501,24 +1504,28 @@ int solve_batch(Prob* ctx, int64_t n, int64_t S, const int64_t* gidx, double rto
     }
     const int* pos = ctx->d_pos.as<int>();
     // one check group of iterations of a lane; a timed group counts the
-    // active slots before its second iteration and launches that
-    // iteration's product and update with events that take the time stamps
-    // of their own dispatch packets
+    // active slots before its second iteration and launches the product and
+    // update of its second and third iterations with events that take the
+    // time stamps of their own dispatch packets (two consecutive iterations:
+    // the update writes lambda in every other one)
     // the graph holds `gcap` iterations and is launched group / gcap times per
     // check group, so that the re-capture after a refill or compaction is short
     const int gcap = (group > 16 && group % 16 == 0) ? 16 : group;
+    auto n_timed = [](int iters) { return iters > 2 ? 2 : 1; };
     auto body = [&](Lane& L, bool timed_group, int iters) -> hipError_t {
-        const int tq = iters > 1 ? 1 : 0;
+        const int tq = iters > 1 ? 1 : 0, nt = n_timed(iters);
         hipError_t e = hipSuccess;
         for (int q = 0; q < iters && e == hipSuccess; ++q) {
-            const bool timed = timed_group && q == tq;
-            if (timed && (e = launch_count_active(L.a.active, L.S, L.a.any_active + 1, L.s)) != hipSuccess) break;
+            const int ti = q - tq;
+            const bool timed = timed_group && ti >= 0 && ti < nt;
+            if (timed && ti == 0 && (e = launch_count_active(L.a.active, L.S, L.a.any_active + 1, L.s)) != hipSuccess)
+                break;
+            hipEvent_t* ev = timed ? &ctx->kev[4 * ti] : nullptr;
             e = launch_cg_apply_mfma(L.a, L.a.p, L.Y, ctx->SR, L.G->d_work.as<int4>(), L.G->nwork,
-                                     L.G->d_perm.as<int>(), ctx->max_R, L.s, timed ? ctx->kev[0] : nullptr,
-                                     timed ? ctx->kev[1] : nullptr);
+                                     L.G->d_perm.as<int>(), ctx->max_R, L.s, ev ? ev[0] : nullptr,
+                                     ev ? ev[1] : nullptr);
             if (e == hipSuccess)
-                e = launch_cg_update2(L.a, L.Y, ctx->SR, pos, L.s, timed ? ctx->kev[2] : nullptr,
-                                      timed ? ctx->kev[3] : nullptr);
+                e = launch_cg_update2(L.a, L.Y, ctx->SR, pos, L.s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
         }
         return e;
     };
@@ -1611,14 +1618,18 @@ int solve_batch(Prob* ctx, int64_t n, int64_t S, const int64_t* gidx, double rto
         HIPCHK(hipStreamSynchronize(L.s));
         const int32_t count = ctx->h_count[2 * L.id], tactive = ctx->h_count[2 * L.id + 1];
         if (L.timed) {
-            float ma = 0.f, mu = 0.f;
-            HIPCHK(hipEventElapsedTime(&ma, ctx->kev[0], ctx->kev[1]));
-            HIPCHK(hipEventElapsedTime(&mu, ctx->kev[2], ctx->kev[3]));
-            ctx->counters.ms_cg_apply += ma;
-            ctx->counters.ms_cg_update += mu;
-            ctx->counters.cg_timed_launches += 1;
-            ctx->counters.cg_timed_active += tactive;
-            ctx->counters.cg_timed_columns += L.in_work;
+            // the active count of the first timed iteration stands for both
+            const int nt = n_timed(group);
+            for (int ti = 0; ti < nt; ++ti) {
+                float ma = 0.f, mu = 0.f;
+                HIPCHK(hipEventElapsedTime(&ma, ctx->kev[4 * ti], ctx->kev[4 * ti + 1]));
+                HIPCHK(hipEventElapsedTime(&mu, ctx->kev[4 * ti + 2], ctx->kev[4 * ti + 3]));
+                ctx->counters.ms_cg_apply += ma;
+                ctx->counters.ms_cg_update += mu;
+                ctx->counters.cg_timed_launches += 1;
+                ctx->counters.cg_timed_active += tactive;
+                ctx->counters.cg_timed_columns += L.in_work;
+            }
         }
         int r2;
         const int64_t refill = std::max<int64_t>(1, L.S / 16);
@@ -2190,7 +2201,7 @@ int impl_solve_interface_noalloc(Prob* ctx, int64_t n, const int64_t* gidx, doub
         return o;
     };
     const size_t o_r = take((size_t)n * M * 8), o_p = take((size_t)n * M * 8), o_Y = take((size_t)n * ctx->SR * 8);
-    const size_t o_rr = take(n * 8), o_r0 = take(n * 8), o_rel = take(n * 8);
+    const size_t o_rr = take(n * 8), o_r0 = take(n * 8), o_rel = take(n * 8), o_pend = take(n * 8);
     const size_t o_it = take(n * 4), o_stat = take(n * 4), o_act = take(n * 4), o_slot = take(n * 4),
                  o_init = take(n * 4), o_any = take(16);
     const size_t o_perm = take(G.h_perm.size() * 4), o_work = take(G.h_work.size() * 16);
@@ -2204,6 +2215,7 @@ int impl_solve_interface_noalloc(Prob* ctx, int64_t n, const int64_t* gidx, doub
     a.p = reinterpret_cast<double*>(base + o_p);
     a.rr = reinterpret_cast<double*>(base + o_rr);
     a.r0 = reinterpret_cast<double*>(base + o_r0);
+    a.pend = reinterpret_cast<double*>(base + o_pend);
     a.relres = reinterpret_cast<double*>(base + o_rel);
     a.iters = reinterpret_cast<int32_t*>(base + o_it);
     a.status = reinterpret_cast<int32_t*>(base + o_stat);
@@ -2308,7 +2320,8 @@ int impl_stream_open(Prob* ctx, int64_t slots, double rtol, int32_t max_iter, vo
     int rc;
     if ((rc = alloc(ctx, c.r, S * M * 8)) || (rc = alloc(ctx, c.p, S * M * 8)) ||
         (rc = alloc(ctx, c.Y, S * ctx->SR * 8)) || (rc = alloc(ctx, c.lam, S * M * 8)) ||
-        (rc = alloc(ctx, c.rr, S * 8)) || (rc = alloc(ctx, c.r0, S * 8)) || (rc = alloc(ctx, c.relres, S * 8)) ||
+        (rc = alloc(ctx, c.rr, S * 8)) || (rc = alloc(ctx, c.r0, S * 8)) || (rc = alloc(ctx, c.pend, S * 8)) ||
+        (rc = alloc(ctx, c.relres, S * 8)) ||
         (rc = alloc(ctx, c.iters, S * 4)) || (rc = alloc(ctx, c.status, S * 4)) ||
         (rc = alloc(ctx, c.active, S * 4)) || (rc = alloc(ctx, c.any, 16)) || (rc = alloc(ctx, c.slot_q, S * 4)) ||
         (rc = alloc(ctx, c.init, S * 4)) || (rc = alloc(ctx, c.g_slot, S * 4)) || (rc = alloc(ctx, c.g_lam, S * 8)) ||
@@ -2367,6 +2380,7 @@ int impl_stream_run(Prob* ctx, int64_t sid, int32_t max_groups, int64_t* done, i
     a.p = c.p.as<double>();
     a.rr = c.rr.as<double>();
     a.r0 = c.r0.as<double>();
+    a.pend = c.pend.as<double>();
     a.relres = c.relres.as<double>();
     a.iters = c.iters.as<int32_t>();
     a.status = c.status.as<int32_t>();

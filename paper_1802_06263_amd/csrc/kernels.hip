@@ -317,6 +317,7 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CgArgs a) {
     if (threadIdx.x == 0) {
         a.rr[l] = rr;
         a.r0[l] = sqrt(rr);
+        a.pend[l] = 0.0;
         a.iters[l] = 0;
         a.relres[l] = rr > 0 ? 1.0 : 0.0;
         a.status[l] = rr > 0 ? SDMM_CG_MAXITER : SDMM_CG_CONVERGED;
@@ -543,8 +544,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
     for (int w = 0; w < kThreads / 64; ++w) pAp += red[w];
     const double rr = a.rr[l];
     const int iter = a.iters[l];
+    // lambda update held back from the previous iteration: alpha' p' with
+    // p' = (p - r) / beta' from this iteration's p = r + beta' p'
+    const double pc = a.pend[l];
     if (!(pAp > 0.0) || !isfinite(pAp)) {
+        if (pc != 0.0) {
+#pragma unroll
+            for (int q = 0; q < kMaxQ; ++q) {
+                const int m = tid + q * kThreads;
+                if (m < M) lam[m] += pc * (pv[q] - rv[q]);
+            }
+        }
         if (tid == 0) {
+            a.pend[l] = 0.0;
             const double rel = a.r0[l] > 0 ? sqrt(rr) / a.r0[l] : 0.0;
             a.status[l] = SDMM_CG_BREAKDOWN;
             a.active[l] = 0;
@@ -556,13 +568,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
         return;
     }
     const double alpha = rr / pAp;
+    // lambda moves by alpha p every iteration, but its row is read and
+    // written only every other one: with a held-back update this iteration
+    // adds both (the old one through p - r), otherwise it holds its own back
+    // unless the realization stops here or beta is small (the held-back form
+    // divides by beta; its rounding is within eps (2 / sqrt(beta) + 1) of the
+    // step, as |r_new|^2 = beta |r|^2 and |p| >= |r|)
     part = 0.0;
 #pragma unroll
     for (int q = 0; q < kMaxQ; ++q) {
         const int m = tid + q * kThreads;
         if (m < M) {
-            rv[q] -= alpha * aps[m];
-            lam[m] += alpha * pv[q];
+            const double ro = rv[q];
+            rv[q] = ro - alpha * aps[m];
+            if (pc != 0.0) lam[m] += pc * (pv[q] - ro) + alpha * pv[q];
             r[m] = rv[q];
         }
         part += rv[q] * rv[q];
@@ -575,9 +594,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
     const double rel = sqrt(rrn) / a.r0[l];
     const bool conv = rel <= a.rtol;
     const bool last = iter + 1 >= a.max_iter;
+    const double beta = rrn / rr;
+    const bool hold = pc == 0.0 && !conv && !last && beta >= 1e-6;
+    if (pc == 0.0 && !hold) {
+#pragma unroll
+        for (int q = 0; q < kMaxQ; ++q) {
+            const int m = tid + q * kThreads;
+            if (m < M) lam[m] += alpha * pv[q];
+        }
+    }
     if (tid == 0) {
         a.iters[l] = iter + 1;
         a.relres[l] = rel;
+        a.pend[l] = hold ? alpha / beta : 0.0;
     }
     if (conv || last) {
         if (tid == 0) {
@@ -590,7 +619,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(W, 8))
         }
         return;
     }
-    const double beta = rrn / rr;
 #pragma unroll
     for (int q = 0; q < kMaxQ; ++q) {
         const int m = tid + q * kThreads;

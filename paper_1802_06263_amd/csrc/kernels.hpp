@@ -162,6 +162,7 @@ struct CgArgs {
     double* p;
     double* rr;
     double* r0;
+    double* pend;         // per slot: lambda update held back one iteration (cg_update2)
     int32_t* iters;
     double* relres;
     int32_t* status;
