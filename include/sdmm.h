@@ -382,7 +382,19 @@ int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
  *                      it does not depend on the realization)
  *   SDMM_OPT_STOKES_REFINE FP64 refinement steps after the band LDL^T solves
  *                      of the Stokes subdomains (0 .. 8, default 0)
- * Results do not depend on any of them. */
+ *   SDMM_OPT_BASIS_LAUNCH layout of the Darcy units of a Method S3 build
+ *                      (Section 5.4 pre-computation loop): 1 = one launch
+ *                      per shape class (padded band, padded R), LDS sized for
+ *                      the class, classes on forked streams; 2 = one launch
+ *                      per phase over the whole queue of units sorted by
+ *                      cost, LDS sized for the widest class; 0 (default) =
+ *                      tuned: the first build of each precision times both
+ *                      layouts and the right-hand-side group width (16, 32,
+ *                      64) of every class and of the queue, and keeps the
+ *                      fastest for the builds that follow
+ * Results do not depend on any of them (the mixed path refines each group of
+ * right-hand sides to the same tolerance, so its bases agree to that
+ * tolerance across group widths). */
 #define SDMM_OPT_CG_CHUNK 0
 #define SDMM_OPT_CG_CHECK 1
 #define SDMM_OPT_CG_GRAPH 2
@@ -390,6 +402,7 @@ int sdmm_reset_moments(sdmm_ctx* ctx, int64_t id);
 #define SDMM_OPT_CG_LANES 4
 #define SDMM_OPT_STOKES_REBUILD 5
 #define SDMM_OPT_STOKES_REFINE 6
+#define SDMM_OPT_BASIS_LAUNCH 7
 int sdmm_set_option(sdmm_ctx* ctx, int64_t id, int option, int64_t value);
 /* Autotuner of the batched CG: runs the first min(n, 16384) realizations of
  * gidx (device int64, n) through the whole CG (rtol, max_iter as in

@@ -139,7 +139,8 @@ struct Prob {
     // Darcy units grouped by shape class (padded band bp, padded R): each
     // class is one launch with LDS sized for it, on its own stream
     struct UnitClass {
-        int base, count, bp, Rs, np;   // np: largest padded cell count of the class
+        int base, count, bp, Rs, np;   // np: largest padded row count of the class
+        int rs[2];                     // solve group width per precision (FP64, mixed); 0: smallest holding Rs
     };
     std::vector<UnitClass> classes;
     std::vector<int> h_order;
@@ -186,6 +187,9 @@ struct Prob {
     int64_t opt_chunk = 0;   // realizations per CG chunk, 0 = from the cache budget
     int opt_check = 64;      // iterations between convergence checks
     int opt_graph = 1;       // capture the iteration group in a HIP graph
+    int opt_basis_launch = 0;   // Darcy basis layout: 0 tuned, 1 one launch per shape class, 2 one queue
+    int basis_mode[2] = {0, 0};  // layout the tuner picked per precision (FP64, mixed); 0: not tuned yet
+    int queue_rs[2] = {0, 0};    // solve group width of the one-queue layout per precision
     int opt_ktime = 0;       // 0: no kernel timing; n: time one iteration of every n-th check group
     int opt_stokes_rebuild = 0;   // rebuild the Stokes basis on every build_flux_basis
     int opt_stokes_refine = 0;    // FP64 refinement steps of the Stokes solves
@@ -451,7 +455,8 @@ int setup_device(Prob* ctx) {
             const auto& ids = cls[rk.second];
             int np = 0;
             for (int u : ids) np = std::max(np, (P.darcy[ctx->units[u].d].Ns + 15) / 16 * 16);
-            ctx->classes.push_back({(int)ctx->h_order.size(), (int)ids.size(), rk.second.first, rk.second.second, np});
+            ctx->classes.push_back(
+                {(int)ctx->h_order.size(), (int)ids.size(), rk.second.first, rk.second.second, np, {0, 0}});
             ctx->h_order.insert(ctx->h_order.end(), ids.begin(), ids.end());
         }
     }
@@ -1027,7 +1032,7 @@ hipError_t launch_classes(Prob* ctx, hipStream_t st, F&& launch) {
     if (nc == 1) {
         const auto& c = ctx->classes[0];
         t.unit_base = c.base;
-        return launch(t, c.count, c.bp, c.Rs, c.np, st);
+        return launch(t, c, st);
     }
     const int ns = std::min(nc, 4);
     hipError_t e;
@@ -1047,7 +1052,7 @@ hipError_t launch_classes(Prob* ctx, hipStream_t st, F&& launch) {
     for (int c = 0; c < nc; ++c) {
         const auto& cl = ctx->classes[c];
         t.unit_base = cl.base;
-        if ((e = launch(t, cl.count, cl.bp, cl.Rs, cl.np, ctx->class_streams[c % ns])) != hipSuccess) return e;
+        if ((e = launch(t, cl, ctx->class_streams[c % ns])) != hipSuccess) return e;
     }
     for (int q = 0; q < ns; ++q) {
         if ((e = hipEventRecord(ctx->class_events[q], ctx->class_streams[q])) != hipSuccess) return e;
@@ -1231,6 +1236,132 @@ int impl_get_kl(Prob* ctx, int region, double* lam, int32_t* modes) {
 constexpr double kRefineTol = 1e-11;
 constexpr int kMaxRefine = 4;
 
+// The Darcy units of a Method S3 build.  mode 1: one launch per shape class
+// (LDS sized for the class) on forked streams, each class with its own solve
+// group width; mode 2: one launch per phase over the whole queue of units,
+// sorted by cost (largest shape first), LDS sized for the widest class.
+int darcy_build(Prob* ctx, int precision, int mode, hipStream_t st) {
+    const int pi = precision == SDMM_PREC_MIXED ? 1 : 0;
+    int rc;
+    double* max_res = nullptr;
+    int* steps = nullptr;
+    if (pi == 1) {
+        if (!ctx->d_L32.p && (rc = alloc(ctx, ctx->d_L32, ctx->L_total * 4))) return rc;
+        if (!ctx->d_I32.p && (rc = alloc(ctx, ctx->d_I32, std::max<int64_t>(ctx->I_total, 1) * 4))) return rc;
+        if (!ctx->d_W32.p && (rc = alloc(ctx, ctx->d_W32, ctx->X_total * 4))) return rc;
+        if (!ctx->d_E.p && (rc = alloc(ctx, ctx->d_E, ctx->X_total * 8))) return rc;
+        HIPCHK(hipMemsetAsync(ctx->d_refine.p, 0, 16, st));
+        max_res = ctx->d_refine.as<double>();
+        steps = reinterpret_cast<int*>(ctx->d_refine.as<char>() + 8);
+    }
+    auto launch = [&](const DarcyTables& tc, int count, int bp, int Rs, int np, int rs, hipStream_t q) {
+        if (pi == 0)
+            return launch_darcy_basis_blocked(tc, count, bp, Rs, np, rs, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
+                                              ctx->d_L.as<double>(), ctx->d_I.as<double>(), ctx->d_T.as<double>(),
+                                              ctx->P.in.darcy_mass, q);
+        return launch_darcy_basis_blocked_mixed(tc, count, bp, Rs, np, rs, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
+                                                ctx->d_E.as<double>(), ctx->d_L32.as<float>(), ctx->d_I32.as<float>(),
+                                                ctx->d_T.as<double>(), ctx->d_W32.as<float>(), kMaxRefine, kRefineTol,
+                                                max_res, steps, q);
+    };
+    if (mode == 2) {
+        DarcyTables t = darcy_tables(ctx);
+        t.unit_base = 0;
+        int bp = 0, Rs = 0, np = 0;
+        for (const auto& c : ctx->classes) {
+            bp = std::max(bp, c.bp);
+            Rs = std::max(Rs, c.Rs);
+            np = std::max(np, c.np);
+        }
+        HIPCHK(launch(t, (int)ctx->n_units, bp, Rs, np, ctx->queue_rs[pi], st));
+    } else {
+        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, const Prob::UnitClass& c, hipStream_t q) {
+            return launch(tc, c.count, c.bp, c.Rs, c.np, c.rs[pi], q);
+        }));
+    }
+    return SDMM_OK;
+}
+
+// Tuning of the Darcy build at the first Method S3 build of a precision: every
+// shape class alone with each solve group width that its right-hand sides
+// need (16; 32 above 16; 64 above 32), the one-queue layout with each width,
+// then both layouts with their best widths, each timed twice with events on
+// the caller's stream (the smaller time counts); the fastest choices are kept
+// for the builds that follow.  The results do not depend on them: every
+// right-hand side is swept by the same per-column arithmetic.
+int tune_darcy(Prob* ctx, int precision, hipStream_t st) {
+    const int pi = precision == SDMM_PREC_MIXED ? 1 : 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, SDMM_EDEVICE, "events for the basis tuning");
+    }
+    int rc = SDMM_OK;
+    auto timed = [&](auto&& run, double& ms) -> int {
+        ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            int r;
+            if (hipEventRecord(e0, st) != hipSuccess) return fail(ctx, SDMM_EDEVICE, "event record");
+            if ((r = run())) return r;
+            float t = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                return fail(ctx, SDMM_EDEVICE, "event timing");
+            ms = std::min(ms, (double)t);
+        }
+        return SDMM_OK;
+    };
+    auto widths = [](int R) {
+        std::vector<int> w{16};
+        if (R > 16) w.push_back(32);
+        if (R > 32) w.push_back(64);
+        return w;
+    };
+    std::vector<Prob::UnitClass> saved = ctx->classes;
+    const int nc = (int)ctx->classes.size();
+    // classes one at a time: a build in the one-class layout of that class
+    for (int c = 0; c < nc && !rc; ++c) {
+        double best = 1e300;
+        int best_w = 0;
+        for (int w : widths(ctx->classes[c].Rs)) {
+            std::vector<Prob::UnitClass> one{ctx->classes[c]};
+            one[0].rs[pi] = w;
+            std::swap(ctx->classes, one);
+            double ms;
+            rc = timed([&] { return darcy_build(ctx, precision, 1, st); }, ms);
+            std::swap(ctx->classes, one);
+            if (rc) break;
+            if (ms < best) {
+                best = ms;
+                best_w = w;
+            }
+        }
+        saved[c].rs[pi] = best_w;
+    }
+    ctx->classes = saved;
+    int Rmax = 0;
+    for (const auto& c : ctx->classes) Rmax = std::max(Rmax, c.Rs);
+    double best_q = 1e300, per_class = 1e300;
+    int best_qw = 0;
+    for (int w : widths(Rmax)) {
+        if (rc) break;
+        ctx->queue_rs[pi] = w;
+        double ms;
+        if ((rc = timed([&] { return darcy_build(ctx, precision, 2, st); }, ms))) break;
+        if (ms < best_q) {
+            best_q = ms;
+            best_qw = w;
+        }
+    }
+    ctx->queue_rs[pi] = best_qw;
+    if (!rc) rc = timed([&] { return darcy_build(ctx, precision, 1, st); }, per_class);
+    ctx->basis_mode[pi] = rc ? 0 : (best_q < per_class ? 2 : 1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     if (!ctx) return SDMM_EINVAL;
     if (ctx->host_only) return fail(ctx, SDMM_ESTATE, "context has no device");
@@ -1242,6 +1373,11 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
         return fail(ctx, SDMM_EINVAL, "the exact RT0 mass is built in FP64 for Methods S2 and S3");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
+    if (method == SDMM_METHOD_STOCHASTIC && ctx->opt_basis_launch == 0 &&
+        ctx->basis_mode[precision == SDMM_PREC_MIXED ? 1 : 0] == 0) {
+        int rc = tune_darcy(ctx, precision, st);
+        if (rc) return rc;
+    }
     HIPCHK(hipEventRecord(ctx->ev[0], st));
     ctx->method = method;
     ctx->det.valid = false;
@@ -1249,28 +1385,11 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
     if (method != SDMM_METHOD_STOCHASTIC) {
         // Methods S2 and S1: the Darcy bases (S2) or factors (S1) are built per
         // batch inside solve_interface
-    } else if (precision == SDMM_PREC_FP64) {
-        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, int np, hipStream_t q) {
-            return launch_darcy_basis_blocked(tc, count, bp, Rs, np, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
-                                              ctx->d_L.as<double>(), ctx->d_I.as<double>(), ctx->d_T.as<double>(),
-                                              ctx->P.in.darcy_mass, q);
-        }));
     } else {
-        int rc;
-        if (!ctx->d_L32.p && (rc = alloc(ctx, ctx->d_L32, ctx->L_total * 4))) return rc;
-        if (!ctx->d_I32.p && (rc = alloc(ctx, ctx->d_I32, std::max<int64_t>(ctx->I_total, 1) * 4))) return rc;
-        if (!ctx->d_W32.p && (rc = alloc(ctx, ctx->d_W32, ctx->X_total * 4))) return rc;
-        if (!ctx->d_E.p && (rc = alloc(ctx, ctx->d_E, ctx->X_total * 8))) return rc;
-        HIPCHK(hipMemsetAsync(ctx->d_refine.p, 0, 16, st));
-        double* max_res = ctx->d_refine.as<double>();
-        int* steps = reinterpret_cast<int*>(ctx->d_refine.as<char>() + 8);
-        HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, int count, int bp, int Rs, int np, hipStream_t q) {
-            return launch_darcy_basis_blocked_mixed(tc, count, bp, Rs, np, ctx->d_S.as<double>(), ctx->d_X.as<double>(),
-                                                    ctx->d_E.as<double>(), ctx->d_L32.as<float>(),
-                                                    ctx->d_I32.as<float>(),
-                                                    ctx->d_T.as<double>(), ctx->d_W32.as<float>(), kMaxRefine,
-                                                    kRefineTol, max_res, steps, q);
-        }));
+        const int pi = precision == SDMM_PREC_MIXED ? 1 : 0;
+        int rc, mode = ctx->opt_basis_launch;
+        if (mode == 0) mode = ctx->basis_mode[pi];
+        if ((rc = darcy_build(ctx, precision, mode, st))) return rc;
     }
     HIPCHK(hipEventRecord(ctx->ev[1], st));
     if (!ctx->stokes_built || ctx->opt_stokes_rebuild) {
@@ -1384,6 +1503,10 @@ int impl_set_option(Prob* ctx, int option, int64_t value) {
                 ctx->stokes_graph = nullptr;
             }
             ctx->opt_stokes_refine = (int)value;
+            return SDMM_OK;
+        case SDMM_OPT_BASIS_LAUNCH:
+            if (value < 0 || value > 2) return fail(ctx, SDMM_EINVAL, "basis launch layout must be 0, 1 or 2");
+            ctx->opt_basis_launch = (int)value;
             return SDMM_OK;
         case SDMM_OPT_CG_LANES:
             if (value < 1 || value > kMaxLanes) return fail(ctx, SDMM_EINVAL, "cg_lanes must be 1 or 2");
@@ -1870,13 +1993,13 @@ int det_build(Prob* ctx, const std::vector<double>& y, hipStream_t st) {
         const int count = D.chunk_start[c + 1] - D.chunk_start[c];
         if (count <= 0) continue;
         if (mixed)
-            HIPCHK(launch_darcy_basis_blocked_mixed(t, count, ctx->max_b, ctx->max_Rd, max_np, D.d_S.as<double>(),
+            HIPCHK(launch_darcy_basis_blocked_mixed(t, count, ctx->max_b, ctx->max_Rd, max_np, 0, D.d_S.as<double>(),
                                                     D.d_X.as<double>(), D.d_E.as<double>(), D.d_L32.as<float>(),
                                                     D.d_I32.as<float>(), D.d_T.as<double>(), D.d_W32.as<float>(),
                                                     kMaxRefine, kRefineTol, D.d_refine.as<double>(),
                                                     reinterpret_cast<int*>(D.d_refine.as<char>() + 8), st));
         else
-            HIPCHK(launch_darcy_basis_blocked(t, count, ctx->max_b, ctx->max_Rd, max_np, D.d_S.as<double>(),
+            HIPCHK(launch_darcy_basis_blocked(t, count, ctx->max_b, ctx->max_Rd, max_np, 0, D.d_S.as<double>(),
                                               D.d_X.as<double>(), D.d_L.as<double>(), D.d_I.as<double>(),
                                               D.d_T.as<double>(), ctx->P.in.darcy_mass, st));
     }

@@ -59,8 +59,10 @@ constexpr int kMaxDarcyBand = 112;   // largest padded half-bandwidth of a Darcy
 size_t darcy_factor_lds(int bp, size_t elem);
 size_t darcy_solve_lds(int bp, int R, size_t elem);
 // max_np: largest padded cell count of the launch's units
+// rs: right-hand sides per solve workgroup (16, 32 or 64; 0 picks the
+// smallest of them that holds max_R, at most 64)
 // exact != 0: the hybridized system of the exactly integrated RT0 mass (FP64)
-hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np,
+hipError_t launch_darcy_basis_blocked(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np, int rs,
                                       double* S_cache, double* X, double* Lscr, double* Iscr, double* Tscr, int exact,
                                       hipStream_t stream);
 // Method S1: the band factors of the units only (mortar loads E, factor L,
@@ -87,7 +89,7 @@ hipError_t launch_darcy_s1_moments(const DarcyTables& t, const int* unit_of_dq, 
                                    const double* colloc_w, double* sum, hipStream_t stream);
 constexpr int kS1MaxR = 256;       // Method S1: mortar DOFs of one Darcy subdomain
 constexpr int kS1MaxMedge = 512;   // Method S1: mortar edges of one Darcy subdomain
-hipError_t launch_darcy_basis_blocked_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np,
+hipError_t launch_darcy_basis_blocked_mixed(const DarcyTables& t, int n_units, int max_b, int max_R, int max_np, int rs,
                                             double* S_cache, double* X, double* E, float* L32, float* I32,
                                             double* Tscr, float* W32, int max_refine, double refine_tol,
                                             double* max_res, int* steps, hipStream_t stream);

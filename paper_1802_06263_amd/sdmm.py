@@ -88,7 +88,8 @@ EXPORTS = {
     "sdmm_get_counters": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(CCounters)]),
     "sdmm_set_option": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _i64]),
 }
-OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2, "kernel_timing": 3, "cg_lanes": 4, "stokes_rebuild": 5, "stokes_refine": 6}
+OPTIONS = {"cg_chunk": 0, "cg_check": 1, "cg_graph": 2, "kernel_timing": 3, "cg_lanes": 4, "stokes_rebuild": 5, "stokes_refine": 6,
+           "basis_launch": 7}
 
 _LIB = None
 

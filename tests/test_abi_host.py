@@ -153,7 +153,10 @@ def test_options_are_validated():
     ctx.set_option("cg_lanes", 2)
     ctx.set_option("cg_graph", 0)
     ctx.set_option("kernel_timing", 1)
-    for name, bad in (("cg_lanes", 0), ("cg_lanes", 3), ("cg_check", 0), ("cg_check", 1025), ("cg_chunk", -1)):
+    for v in (0, 1, 2):
+        ctx.set_option("basis_launch", v)
+    for name, bad in (("cg_lanes", 0), ("cg_lanes", 3), ("cg_check", 0), ("cg_check", 1025), ("cg_chunk", -1),
+                      ("basis_launch", -1), ("basis_launch", 3)):
         with pytest.raises(sdmm.SdmmError):
             ctx.set_option(name, bad)
     rc = ctx.lib.sdmm_set_option(ctx.h, pid, 99, 1)

@@ -164,6 +164,39 @@ def test_lambda_moments_are_weighted_sums_cfg2():
     ctx.close()
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 0.0), ("mixed", 1e-10)])
+def test_basis_layouts_agree_on_the_uneven_layout(precision, tol):
+    """The Darcy units of the uneven layout through one launch per shape class,
+    one launch per phase over the whole cost-sorted queue, and the tuned
+    choice (Section 5.4 pre-computation loop): the same S for one unit of
+    every mesh shape, bit for bit in FP64 (every right-hand side is swept by
+    the same per-column arithmetic), to the refinement tolerance in mixed
+    precision (each group of right-hand sides is refined on its own)."""
+    print("case: Darcy basis layouts on the uneven layout", precision, flush=True)
+    import torch  # noqa: F401
+    from paper_1802_06263_amd import sdmm
+    prob = problem("cfg3")
+    L = Layout(prob)
+    grid = Grid(prob["regions"], prob["rule"])
+    units = sampled_units(L, grid, "cfg3", np.random.default_rng(5))
+    got = {}
+    for mode in (1, 2, 0):
+        ctx = sdmm.Context(0)
+        ctx.set_problem(prob)
+        ctx.set_option("basis_launch", mode)
+        ctx.build_flux_basis(precision)
+        if mode == 0:
+            ctx.build_flux_basis(precision)   # the second build uses the tuned choice
+        got[mode] = [ctx.get_basis(i, k, L.sub_dofs[i].size) for i, k in units]
+        ctx.close()
+    for mode in (2, 0):
+        for (i, k), a, b in zip(units, got[1], got[mode]):
+            if tol == 0.0:
+                assert np.array_equal(a, b), (mode, i, k)
+            else:
+                assert rel(b, a) < tol, (mode, i, k, rel(b, a))
+
+
 def test_autotune_keeps_results():
     print("case: autotune on the small FETI case", flush=True)
     prob = problem("cfg2", stokes_mesh=(8, 8), darcy_mesh=(4, 4), mortar={"degree": 1, "elements": 2})
