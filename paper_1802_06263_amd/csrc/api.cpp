@@ -188,6 +188,16 @@ struct Prob {
     int opt_check = 64;      // iterations between convergence checks
     int opt_graph = 1;       // capture the iteration group in a HIP graph
     int opt_basis_launch = 0;   // Darcy basis layout: 0 tuned, 1 one launch per shape class, 2 one queue
+    // exact-mass units whose face-pressure band does not fit the LDS window:
+    // the first n_wide entries of h_order, built in chunks through the tiled
+    // band LDL^T (one StokesDev per unit, offsets into the chunk buffers)
+    struct WideChunk {
+        int first, count, max_nblk, max_w, max_ncol, max_ld, max_np;
+        int64_t tiles, rhs, linv;   // doubles of each chunk buffer
+    };
+    int n_wide = 0;
+    std::vector<WideChunk> wide_chunks;
+    DevBuf d_wide_sdx, d_wide_units, d_wt_tiles, d_wt_tilesN, d_wt_linv, d_wt_rhs, d_wt_tmp;
     int basis_mode[2] = {0, 0};  // layout the tuner picked per precision (FP64, mixed); 0: not tuned yet
     int queue_rs[2] = {0, 0};    // solve group width of the one-queue layout per precision
     int opt_ktime = 0;       // 0: no kernel timing; n: time one iteration of every n-th check group
@@ -430,13 +440,9 @@ int setup_device(Prob* ctx) {
         edge_tot += (int64_t)(h.nx + 1) * h.ny + (int64_t)h.nx * (h.ny + 1);
     }
     ctx->n_units = (int64_t)ctx->units.size();
-    // the block kernels hold a band block of 16 (bp + 1) <= 8 x 256 values in
-    // registers and index band columns below 128: bp <= 112
-    if ((ctx->max_b + 15) / 16 * 16 > kMaxDarcyBand || darcy_factor_lds((ctx->max_b + 15) / 16 * 16, 8) > 150 * 1024 ||
-        darcy_solve_lds((ctx->max_b + 15) / 16 * 16, ctx->max_Rd, 8) > 150 * 1024)
-        return fail(ctx, SDMM_EINVAL, "a Darcy subdomain's band window does not fit (shorter side above 112 cells)");
     {
-        // shape classes, most expensive unit shape first
+        // shape classes, most expensive unit shape first; units whose band
+        // does not fit the LDS window (only the exact mass has them) first of all
         std::map<std::pair<int, int>, std::vector<int>> cls;
         for (size_t u = 0; u < ctx->units.size(); ++u) {
             const DarcyHost& h = P.darcy[ctx->units[u].d];
@@ -446,18 +452,87 @@ int setup_device(Prob* ctx) {
         for (auto& kv : cls) {
             const DarcyHost& h = P.darcy[ctx->units[kv.second[0]].d];
             const double cost = (double)h.Ns * kv.first.first * (kv.first.first + kv.first.second);
-            rank.push_back({-cost, kv.first});
+            rank.push_back({(kv.first.first > kMaxDarcyBand ? -1e300 : 0.0) - cost, kv.first});
         }
         std::sort(rank.begin(), rank.end());
         ctx->classes.clear();
         ctx->h_order.clear();
+        ctx->n_wide = 0;
+        ctx->max_b = 0;
         for (auto& rk : rank) {
             const auto& ids = cls[rk.second];
+            if (rk.second.first > kMaxDarcyBand) {
+                ctx->h_order.insert(ctx->h_order.end(), ids.begin(), ids.end());
+                ctx->n_wide += (int)ids.size();
+                continue;
+            }
             int np = 0;
             for (int u : ids) np = std::max(np, (P.darcy[ctx->units[u].d].Ns + 15) / 16 * 16);
             ctx->classes.push_back(
                 {(int)ctx->h_order.size(), (int)ids.size(), rk.second.first, rk.second.second, np, {0, 0}});
             ctx->h_order.insert(ctx->h_order.end(), ids.begin(), ids.end());
+            ctx->max_b = std::max(ctx->max_b, rk.second.first);
+        }
+    }
+    // the block kernels hold a band block of 16 (bp + 1) <= 8 x 256 values in
+    // registers and index band columns below 128: bp <= 112 for every unit
+    // that runs through the LDS window
+    if (ctx->max_b > kMaxDarcyBand || darcy_factor_lds(ctx->max_b, 8) > 150 * 1024 ||
+        darcy_solve_lds(ctx->max_b, ctx->max_Rd, 8) > 150 * 1024)
+        return fail(ctx, SDMM_EINVAL, "a Darcy subdomain's band window does not fit (shorter side above 112 cells)");
+    {
+        // chunks of the wide units, each within about 4 GB of tiles, inverses
+        // and right-hand sides
+        ctx->wide_chunks.clear();
+        std::vector<StokesDev> sdx;
+        std::vector<int> wunits(ctx->h_order.begin(), ctx->h_order.begin() + ctx->n_wide);
+        Prob::WideChunk ch{};
+        auto close_chunk = [&]() {
+            if (ch.count > 0) ctx->wide_chunks.push_back(ch);
+            ch = Prob::WideChunk{};
+            ch.first = (int)sdx.size();
+        };
+        close_chunk();
+        for (int u : wunits) {
+            const DarcyHost& h = P.darcy[ctx->units[u].d];
+            StokesDev x{};
+            x.nband = h.Ns;
+            x.nblk = (h.Ns + 63) / 64;
+            x.w = (h.bs + 63) / 64;
+            x.ncol = h.R;
+            x.R = h.R;
+            const int64_t nt = (int64_t)x.nblk * (x.w + 1) * 4096, nr = (int64_t)x.nblk * 64 * x.ncol,
+                          nl = (int64_t)x.nblk * 4096;
+            if (ch.count > 0 && (2 * (ch.tiles + nt) + ch.linv + nl + 2 * (ch.rhs + nr)) * 8 > (int64_t)4 << 30)
+                close_chunk();
+            x.off_tiles = ch.tiles;
+            x.off_rhs = ch.rhs;
+            x.off_linv = ch.linv;
+            ch.tiles += nt;
+            ch.rhs += nr;
+            ch.linv += nl;
+            ch.count++;
+            ch.max_nblk = std::max(ch.max_nblk, x.nblk);
+            ch.max_w = std::max(ch.max_w, x.w);
+            ch.max_ncol = std::max(ch.max_ncol, x.ncol);
+            ch.max_ld = std::max(ch.max_ld, x.nblk * 64);
+            ch.max_np = std::max(ch.max_np, (h.Ns + 15) / 16 * 16);
+            sdx.push_back(x);
+        }
+        close_chunk();
+        int64_t mt = 0, mr = 0, ml = 0;
+        for (auto& c : ctx->wide_chunks) {
+            mt = std::max(mt, c.tiles);
+            mr = std::max(mr, c.rhs);
+            ml = std::max(ml, c.linv);
+        }
+        int rc;
+        if (ctx->n_wide > 0 && !ctx->host_only) {
+            if ((rc = upload(ctx, ctx->d_wide_sdx, sdx)) || (rc = upload(ctx, ctx->d_wide_units, wunits)) ||
+                (rc = alloc(ctx, ctx->d_wt_tiles, mt * 8)) || (rc = alloc(ctx, ctx->d_wt_tilesN, mt * 8)) ||
+                (rc = alloc(ctx, ctx->d_wt_linv, ml * 8)) || (rc = alloc(ctx, ctx->d_wt_rhs, mr * 8)) ||
+                (rc = alloc(ctx, ctx->d_wt_tmp, mr * 8)))
+                return rc;
         }
     }
     // ---- Stokes
@@ -1240,9 +1315,41 @@ constexpr int kMaxRefine = 4;
 // (LDS sized for the class) on forked streams, each class with its own solve
 // group width; mode 2: one launch per phase over the whole queue of units,
 // sorted by cost (largest shape first), LDS sized for the widest class.
-int darcy_build(Prob* ctx, int precision, int mode, hipStream_t st) {
+// The exact-mass units too wide for the LDS window, chunk by chunk (FP64):
+// band and loads into zeroed tiles, identity on the padding rows, the band
+// LDL^T block column by block column, the sweep tiles, the solve of all
+// right-hand sides in place, then responses and flux bases.
+int darcy_build_wide(Prob* ctx, hipStream_t st) {
+    DarcyTables t = darcy_tables(ctx);
+    double* tiles = ctx->d_wt_tiles.as<double>();
+    double* tilesN = ctx->d_wt_tilesN.as<double>();
+    double* linv = ctx->d_wt_linv.as<double>();
+    double* rhs = ctx->d_wt_rhs.as<double>();
+    for (const auto& c : ctx->wide_chunks) {
+        const StokesDev* sdx = ctx->d_wide_sdx.as<StokesDev>() + c.first;
+        const int* units = ctx->d_wide_units.as<int>() + c.first;
+        HIPCHK(launch_fill_zero(tiles, c.tiles, st));
+        HIPCHK(launch_fill_zero(rhs, c.rhs, st));
+        HIPCHK(launch_exact_tiles_assemble(t, units, sdx, c.count, c.max_ld, tiles, rhs, ctx->d_T.as<double>(), st));
+        HIPCHK(launch_stokes_pad_identity(sdx, c.count, c.max_nblk, tiles, st));
+        for (int J = 0; J < c.max_nblk; ++J) {
+            HIPCHK(launch_stokes_ldl_diag(sdx, c.count, J, tiles, linv, st));
+            HIPCHK(launch_stokes_ldl_panel(sdx, c.count, J, c.max_w, tiles, linv, st));
+            HIPCHK(launch_stokes_ldl_rest(sdx, c.count, J, c.max_w, tiles, st));
+        }
+        HIPCHK(launch_stokes_sweep_tiles(sdx, c.count, c.max_nblk, c.max_w, tiles, tilesN, linv, st));
+        HIPCHK(launch_stokes_solve(sdx, c.count, c.max_nblk, c.max_w, c.max_ncol, tiles, tilesN, linv, rhs,
+                                   ctx->d_wt_tmp.as<double>(), st));
+        HIPCHK(launch_exact_tiles_finish(t, units, sdx, c.count, c.max_np, c.max_ncol, rhs, ctx->d_X.as<double>(),
+                                         ctx->d_S.as<double>(), ctx->d_T.as<double>(), st));
+    }
+    return SDMM_OK;
+}
+
+int darcy_build(Prob* ctx, int precision, int mode, hipStream_t st, bool wide = true) {
     const int pi = precision == SDMM_PREC_MIXED ? 1 : 0;
     int rc;
+    if (wide && ctx->n_wide > 0 && (rc = darcy_build_wide(ctx, st))) return rc;
     double* max_res = nullptr;
     int* steps = nullptr;
     if (pi == 1) {
@@ -1264,16 +1371,17 @@ int darcy_build(Prob* ctx, int precision, int mode, hipStream_t st) {
                                                 ctx->d_T.as<double>(), ctx->d_W32.as<float>(), kMaxRefine, kRefineTol,
                                                 max_res, steps, q);
     };
+    if (ctx->classes.empty()) return SDMM_OK;
     if (mode == 2) {
         DarcyTables t = darcy_tables(ctx);
-        t.unit_base = 0;
+        t.unit_base = ctx->n_wide;
         int bp = 0, Rs = 0, np = 0;
         for (const auto& c : ctx->classes) {
             bp = std::max(bp, c.bp);
             Rs = std::max(Rs, c.Rs);
             np = std::max(np, c.np);
         }
-        HIPCHK(launch(t, (int)ctx->n_units, bp, Rs, np, ctx->queue_rs[pi], st));
+        HIPCHK(launch(t, (int)ctx->n_units - ctx->n_wide, bp, Rs, np, ctx->queue_rs[pi], st));
     } else {
         HIPCHK(launch_classes(ctx, st, [&](const DarcyTables& tc, const Prob::UnitClass& c, hipStream_t q) {
             return launch(tc, c.count, c.bp, c.Rs, c.np, c.rs[pi], q);
@@ -1329,7 +1437,7 @@ int tune_darcy(Prob* ctx, int precision, hipStream_t st) {
             one[0].rs[pi] = w;
             std::swap(ctx->classes, one);
             double ms;
-            rc = timed([&] { return darcy_build(ctx, precision, 1, st); }, ms);
+            rc = timed([&] { return darcy_build(ctx, precision, 1, st, false); }, ms);
             std::swap(ctx->classes, one);
             if (rc) break;
             if (ms < best) {
@@ -1348,14 +1456,14 @@ int tune_darcy(Prob* ctx, int precision, hipStream_t st) {
         if (rc) break;
         ctx->queue_rs[pi] = w;
         double ms;
-        if ((rc = timed([&] { return darcy_build(ctx, precision, 2, st); }, ms))) break;
+        if ((rc = timed([&] { return darcy_build(ctx, precision, 2, st, false); }, ms))) break;
         if (ms < best_q) {
             best_q = ms;
             best_qw = w;
         }
     }
     ctx->queue_rs[pi] = best_qw;
-    if (!rc) rc = timed([&] { return darcy_build(ctx, precision, 1, st); }, per_class);
+    if (!rc) rc = timed([&] { return darcy_build(ctx, precision, 1, st, false); }, per_class);
     ctx->basis_mode[pi] = rc ? 0 : (best_q < per_class ? 2 : 1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1371,6 +1479,8 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
         return fail(ctx, SDMM_EINVAL, "bad method");
     if (ctx->P.in.darcy_mass == 1 && (precision != SDMM_PREC_FP64 || method == SDMM_METHOD_PER_ITERATION))
         return fail(ctx, SDMM_EINVAL, "the exact RT0 mass is built in FP64 for Methods S2 and S3");
+    if (ctx->n_wide > 0 && method != SDMM_METHOD_STOCHASTIC)
+        return fail(ctx, SDMM_EINVAL, "exact-mass subdomains wider than 55 cells on their shorter side need Method S3");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     if (method == SDMM_METHOD_STOCHASTIC && ctx->opt_basis_launch == 0 &&

@@ -112,6 +112,16 @@ struct StokesDev {
     int64_t off_linv;   // L(J, J)^{-1} of every block column (nblk x 64 x 64)
 };
 
+// Exact RT0 mass, units too wide for the LDS window: per chunk of nu units
+// (units: their ids; sdx: one StokesDev per unit, tile, right-hand-side and
+// inverse offsets into the chunk's buffers), the band into zeroed tiles and
+// the mortar loads into zeroed column-major right-hand sides; after the tiled
+// band LDL^T solve, the solutions into X and the flux bases into S.
+hipError_t launch_exact_tiles_assemble(const DarcyTables& t, const int* units, const StokesDev* sdx, int nu, int max_ld,
+                                       double* tiles, double* rhs, double* Tscr, hipStream_t stream);
+hipError_t launch_exact_tiles_finish(const DarcyTables& t, const int* units, const StokesDev* sdx, int nu, int max_np,
+                                     int max_R, const double* rhs, double* X, double* S_cache, const double* Tscr,
+                                     hipStream_t stream);
 hipError_t launch_stokes_scatter(const StokesDev* sd, int ns, const int* tr_sub, const int* tr_r, const int* tr_c,
                                  const double* tr_v, int64_t ntrip, double* tiles, hipStream_t stream);
 hipError_t launch_stokes_pad_identity(const StokesDev* sd, int ns, int max_nblk, double* tiles, hipStream_t stream);

@@ -87,7 +87,11 @@ def test_p2p1_full_size_stokes_blocks():
 #   * on the 4x2 Stokes over 8x4 Darcy layout with 48x48 Darcy meshes
 #     (the largest that fits the factor's LDS window: band 2 min(nx, ny) + 1),
 #     sampled units of three Darcy subdomains;
-#   * the mixed precision path and Method S1 refuse the exact mass (EINVAL).
+#   * at full size (64x64 Darcy subdomains, band 129: the tiled band LDL^T),
+#     sampled units, and on the uneven layout one unit of every mesh shape
+#     (window and tiled units in one build); the CG converges at full size;
+#   * the mixed precision path and Method S1 refuse the exact mass (EINVAL),
+#     and Method S2 refuses units too wide for the LDS window.
 
 
 @pytest.mark.parametrize("name", ["cfg0", "small"])
@@ -171,5 +175,49 @@ def test_exact_rt0_refuses_mixed_and_s1():
     for prec, meth in (("mixed", "stochastic"), ("fp64", "per_iteration")):
         with pytest.raises(sdmm.SdmmError) as e:
             ctx.build_flux_basis(prec, method=meth)
+        assert e.value.code == sdmm.EINVAL
+    ctx.close()
+
+
+def _exact_unit_basis(L, grid, i, k):
+    from oracle.darcy import DarcyLocalExact
+    from oracle.kl import cell_centres, region_field
+    sub = L.subs[i]
+    reg = L.regions[sub["region"]]
+    y = grid.local_points(sub["region"])[k]
+    K = np.exp(float(reg["mean_logk"]) + np.asarray(y) @ region_field(reg, cell_centres(sub)))
+    return DarcyLocalExact(L, i, K).basis()
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+def test_exact_rt0_full_size_units(name):
+    print("case: exact RT0 mass at full size,", name, flush=True)
+    import torch
+    from oracle.collocation import Grid
+    from paper_1802_06263_amd import sdmm
+    prob = _with(problem(name), darcy="exact")
+    L = Layout(prob)
+    grid = Grid(prob["regions"], prob["rule"])
+    ctx = gpu_ctx(prob, "fp64")
+    darcy = [i for i in range(L.nsub) if L.subs[i]["type"] == "darcy"]
+    rng = np.random.default_rng(17)
+    if name == "cfg3":
+        seen = {}
+        for i in darcy:
+            seen.setdefault(tuple(L.subs[i]["n"]), i)
+        subs = list(seen.values())
+    else:
+        subs = [darcy[0], darcy[len(darcy) // 2], darcy[-1]]
+    for i in subs:
+        k = int(rng.integers(grid.nlocal[L.subs[i]["region"]]))
+        S = _exact_unit_basis(L, grid, i, k)
+        assert rel(ctx.get_basis(i, k, S.shape[0]), S) < 1e-11, (i, k, L.subs[i]["n"])
+    if name == "cfg2":
+        idx = list(rng.integers(0, grid.nreal, 64))
+        g, lam, it, rr, st, rc = gpu_solve(ctx, idx, rtol=1e-8)
+        assert (st == 0).all() and (rr <= 1e-8).all()
+        # Method S2 cannot take units too wide for the LDS window
+        with pytest.raises(sdmm.SdmmError) as e:
+            ctx.build_flux_basis("fp64", method="deterministic")
         assert e.value.code == sdmm.EINVAL
     ctx.close()
