@@ -365,7 +365,7 @@ int setup_device(Prob* ctx) {
         be_len.insert(be_len.end(), h.be_len.begin(), h.be_len.end());
         be_hperp.insert(be_hperp.end(), h.be_hperp.begin(), h.be_hperp.end());
         Pi.insert(Pi.end(), h.Pi.begin(), h.Pi.end());
-        phi.insert(phi.end(), h.phi.begin(), h.phi.end());
+        phi.resize(phi.size() + (size_t)h.nterm * h.N);   // filled on the device (launch_kl)
         std::vector<int> cb((size_t)2 * h.N, -1);
         me_cell.resize(me_cell.size() + h.n_medge);
         for (size_t e = 0; e < h.be_cell.size(); ++e) {
@@ -650,7 +650,65 @@ int setup_device(Prob* ctx) {
     UP(ctx->d_be_sgn, be_sgn);
     UP(ctx->d_cell_be, cell_be);
     UP(ctx->d_Pi, Pi);
-    UP(ctx->d_phi, phi);
+    {
+        // the KL modes and the phi tables on the device (the kept modes and
+        // eigenvalues come back to the problem, for sdmm_get_kl)
+        std::vector<KLRegionDev> kreg;
+        int nm_max = 1, nt_max = 1, max_cells = 0;
+        for (int r = 0; r < P.n_region; ++r) {
+            const double* rr = &P.region_rect[4 * r];
+            KLRegionDev k{};
+            k.ax = 0.5 * (rr[1] - rr[0]);
+            k.ay = 0.5 * (rr[3] - rr[2]);
+            k.etax = P.region_eta[2 * r];
+            k.etay = P.region_eta[2 * r + 1];
+            k.sigma2 = P.region_sigma2[r];
+            k.xc = 0.5 * (rr[0] + rr[1]);
+            k.yc = 0.5 * (rr[2] + rr[3]);
+            k.nterm = P.region_nterm[r];
+            k.nm = k.nterm + 1;
+            nm_max = std::max(nm_max, k.nm);
+            nt_max = std::max(nt_max, k.nterm);
+            kreg.push_back(k);
+        }
+        std::vector<KLSubDev> ksub;
+        for (size_t di = 0; di < P.darcy.size(); ++di) {
+            const Sub& sb = P.subs[P.darcy[di].sub];
+            KLSubDev q{};
+            q.x0 = sb.x0;
+            q.y0 = sb.y0;
+            q.hx = sb.hx;
+            q.hy = sb.hy;
+            q.nx = sb.nx;
+            q.ny = sb.ny;
+            q.region = sb.region;
+            q.off_phi = dar[di].off_phi;
+            max_cells = std::max(max_cells, sb.nx * sb.ny);
+            ksub.push_back(q);
+        }
+        DevBuf d_kreg, d_ksub, d_w, d_nrm, d_lam1, d_ma, d_mb, d_lam2;
+        const size_t nr = std::max(1, P.n_region);
+        if ((rc = upload(ctx, d_kreg, kreg)) || (rc = upload(ctx, d_ksub, ksub)) ||
+            (rc = alloc(ctx, d_w, nr * 2 * nm_max * 8)) || (rc = alloc(ctx, d_nrm, nr * 2 * nm_max * 8)) ||
+            (rc = alloc(ctx, d_lam1, nr * 2 * nm_max * 8)) || (rc = alloc(ctx, d_ma, nr * nt_max * 4)) ||
+            (rc = alloc(ctx, d_mb, nr * nt_max * 4)) || (rc = alloc(ctx, d_lam2, nr * nt_max * 8)) ||
+            (rc = alloc(ctx, ctx->d_phi, std::max<size_t>(phi.size(), 1) * 8)))
+            return rc;
+        HIPCHK(launch_kl(d_kreg.as<KLRegionDev>(), P.n_region, d_ksub.as<KLSubDev>(), (int)ksub.size(), nm_max, nt_max,
+                         max_cells, d_w.as<double>(), d_nrm.as<double>(), d_lam1.as<double>(), d_ma.as<int>(),
+                         d_mb.as<int>(), d_lam2.as<double>(), ctx->d_phi.as<double>(), nullptr));
+        std::vector<int> hma(nr * nt_max), hmb(nr * nt_max);
+        std::vector<double> hl(nr * nt_max);
+        HIPCHK(hipMemcpy(hma.data(), d_ma.p, hma.size() * 4, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hmb.data(), d_mb.p, hmb.size() * 4, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hl.data(), d_lam2.p, hl.size() * 8, hipMemcpyDeviceToHost));
+        for (int r = 0; r < P.n_region; ++r)
+            for (int t = 0; t < P.region_nterm[r]; ++t) {
+                P.kl[r].ma[t] = hma[r * nt_max + t];
+                P.kl[r].mb[t] = hmb[r * nt_max + t];
+                P.kl[r].lam[t] = hl[r * nt_max + t];
+            }
+    }
     UP(ctx->d_xi, xi);
     UP(ctx->d_supp_ptr, supp_ptr);
     UP(ctx->d_supp_e, supp_e);
@@ -1311,10 +1369,6 @@ int impl_get_kl(Prob* ctx, int region, double* lam, int32_t* modes) {
 constexpr double kRefineTol = 1e-11;
 constexpr int kMaxRefine = 4;
 
-// The Darcy units of a Method S3 build.  mode 1: one launch per shape class
-// (LDS sized for the class) on forked streams, each class with its own solve
-// group width; mode 2: one launch per phase over the whole queue of units,
-// sorted by cost (largest shape first), LDS sized for the widest class.
 // The exact-mass units too wide for the LDS window, chunk by chunk (FP64):
 // band and loads into zeroed tiles, identity on the padding rows, the band
 // LDL^T block column by block column, the sweep tiles, the solve of all
@@ -1346,6 +1400,12 @@ int darcy_build_wide(Prob* ctx, hipStream_t st) {
     return SDMM_OK;
 }
 
+// The Darcy units of a Method S3 build.  mode 1: one launch per shape class
+// (LDS sized for the class) on forked streams, each class with its own solve
+// group width; mode 2: one launch per phase over the whole queue of units,
+// sorted by cost (largest shape first), LDS sized for the widest class.  The
+// units too wide for the LDS window go first, through darcy_build_wide
+// (skipped while the window layouts are timed).
 int darcy_build(Prob* ctx, int precision, int mode, hipStream_t st, bool wide = true) {
     const int pi = precision == SDMM_PREC_MIXED ? 1 : 0;
     int rc;

@@ -108,6 +108,7 @@ __device__ void darcy_transmissibilities(const DarcyTables& t, const DarcyDev& D
 }  // namespace
 
 #include "darcy_blocked.inc"
+#include "kl.inc"
 
 // ---------------------------------------------------------------------------
 // Stokes: tiled band LDL^T.  Block column J holds tiles I = J .. J + w, each

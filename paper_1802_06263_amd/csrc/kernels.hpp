@@ -53,6 +53,24 @@ struct DarcyTables {
     int unit_base;      // first entry of `order` this launch covers
 };
 
+// KL expansion on the device: per region the half-lengths, correlation
+// lengths, amplitude, centre, kept terms and 1-D modes computed (nterm + 1
+// per direction); per Darcy subdomain its cell grid and phi offset.
+struct KLRegionDev {
+    double ax, ay, etax, etay, sigma2, xc, yc;
+    int nterm, nm;
+};
+struct KLSubDev {
+    double x0, y0, hx, hy;
+    int nx, ny, region, pad;
+    int64_t off_phi;
+};
+// 1-D roots (w, nrm, lam1: nreg x 2 x nm_max), kept modes (ma, mb, lam2:
+// nreg x nt_max) and phi of every Darcy subdomain (nterm x cells at off_phi)
+hipError_t launch_kl(const KLRegionDev* reg, int nreg, const KLSubDev* sub, int nsub, int nm_max, int nt_max,
+                     int max_cells, double* w, double* nrm, double* lam1, int* ma, int* mb, double* lam2, double* phi,
+                     hipStream_t stream);
+
 // Launchers (all enqueue on `stream`).
 
 constexpr int kMaxDarcyBand = 112;   // largest padded half-bandwidth of a Darcy unit

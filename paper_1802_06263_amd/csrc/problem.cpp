@@ -118,10 +118,6 @@ static void kl_1d(double a, double eta, int nmodes, std::vector<double>& lam, st
     }
 }
 
-static double kl_eval(double x, double w, int parity, double nrm) {
-    return (parity == 0 ? std::cos(w * x) : std::sin(w * x)) / nrm;
-}
-
 // ---------------------------------------------------------- collocation ----
 // Probabilists' Gauss-Hermite nodes as the roots of He_m (recurrence
 // He_{k+1} = x He_k - k He_{k-1}), bracketed on a grid and bisected; weights
@@ -319,23 +315,10 @@ static std::string build_darcy(Problem& P, int i, DarcyHost& d) {
         int nfine = (int)std::lround((f.b - f.a) / (f.horizontal ? s.hx : s.hy));
         if (f.nnode > nfine) return "a mortar has more degrees of freedom than the fine trace of a Darcy subdomain";
     }
-    // KL table
-    int r = s.region;
-    const KLRegion& K = P.kl[r];
-    d.nterm = P.region_nterm[r];
-    d.mean_logk = P.region_mean[r];
-    d.phi.assign((size_t)d.nterm * d.N, 0.0);
-    for (int t = 0; t < d.nterm; ++t) {
-        int a = K.ma[t], b = K.mb[t];
-        double sq = std::sqrt(K.lam[t]);
-        for (int iy = 0; iy < s.ny; ++iy)
-            for (int ix = 0; ix < s.nx; ++ix) {
-                double x = s.x0 + (ix + 0.5) * s.hx - K.xc;
-                double y = s.y0 + (iy + 0.5) * s.hy - K.yc;
-                d.phi[(size_t)t * d.N + iy * s.nx + ix] =
-                    sq * kl_eval(x, K.wx[a], K.px[a], K.nx_[a]) * kl_eval(y, K.wy[b], K.py[b], K.ny_[b]);
-            }
-    }
+    // KL: the terms of the region (their values at the cell centres are
+    // computed on the device)
+    d.nterm = P.region_nterm[s.region];
+    d.mean_logk = P.region_mean[s.region];
     return "";
 }
 

@@ -58,7 +58,6 @@ struct DarcyHost {
     std::vector<int> be_edge;      // RT0 edge index
     int n_medge;
     std::vector<double> Pi;        // n_medge x R edge averages of the mortar functions
-    std::vector<double> phi;       // nterm x N  sqrt(lambda_t) f_t(cell centre)
     int nterm;
     double mean_logk;
 };

@@ -103,6 +103,27 @@ def test_feti_floating_stokes_parity():
     ctx.close()
 
 
+@pytest.mark.parametrize("name", ["cfg0", "cfg1", "cfg2", "cfg3"])
+def test_kl_modes_on_the_device(name):
+    """On a device context the KL roots, the selection of the kept 2-D modes
+    and the phi tables are computed on the GPU (Section 2.1); sdmm_get_kl
+    reports the kept modes, which equal the oracle's, and the eigenvalues to
+    1e-13.  phi itself is pinned through every basis parity test."""
+    print("case: KL modes on the device,", name, flush=True)
+    import torch  # noqa: F401
+    from oracle.kl import region_modes
+    from paper_1802_06263_amd import sdmm
+    p = problem(name)
+    ctx = sdmm.Context(0)
+    ctx.set_problem(p)
+    for r, reg in enumerate(p["regions"]):
+        lam, modes = ctx.kl(r, reg["nterm"])
+        om, *_ = region_modes(reg)
+        assert [tuple(m) for m in modes] == [(m["a"], m["b"]) for m in om]
+        assert np.allclose(lam, [m["lam"] for m in om], rtol=1e-13, atol=0)
+    ctx.close()
+
+
 def test_results_identical_alone_and_in_a_batch(cfg0):
     print("case: cfg0 alone vs mixed batch", flush=True)
     ctx = gpu_ctx(cfg0.prob, "fp64")
