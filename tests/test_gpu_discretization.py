@@ -91,7 +91,9 @@ def test_p2p1_full_size_stokes_blocks():
 #     sampled units, and on the uneven layout one unit of every mesh shape
 #     (window and tiled units in one build); the CG converges at full size;
 #   * the mixed precision path and Method S1 refuse the exact mass (EINVAL),
-#     and Method S2 refuses units too wide for the LDS window.
+#     and Method S2 refuses units too wide for the LDS window;
+#   * both variants together (P2-P1 Stokes, exact-mass Darcy) on the
+#     two-region layout: every S block, lambda and the moments.
 
 
 @pytest.mark.parametrize("name", ["cfg0", "small"])
@@ -114,6 +116,23 @@ def test_exact_rt0_matches_oracle(name):
     mom, info = o.run("S3", indices=idx, weights=w, rtol=1e-12)
     assert rel(lam.cpu().numpy(), np.stack([d["lambda"] for d in info])) < 1e-9
     ctx.accumulate_moments(g, lam, None if w is None else torch.tensor(w, device="cuda"))
+    _check_moments(ctx, mom, 1e-9)
+    ctx.close()
+
+
+def test_both_variants_together_match_oracle():
+    print("case: P2-P1 Stokes with the exact RT0 mass on the two-region layout", flush=True)
+    prob = _with(problem("cfg0"), stokes="p2p1", darcy="exact")
+    o = Oracle(prob)
+    o.stochastic_basis()
+    ctx = gpu_ctx(prob, "fp64")
+    for (i, k), S in o.s3_table.items():
+        assert rel(ctx.get_basis(i, k, S.shape[0]), S) < 1e-11, (i, k)
+    idx = list(range(o.grid.nreal))
+    g, lam, it, rr, st, rc = gpu_solve(ctx, idx, rtol=1e-12)
+    mom, info = o.run("S3", indices=idx, rtol=1e-12)
+    assert rel(lam.cpu().numpy(), np.stack([d["lambda"] for d in info])) < 1e-9
+    ctx.accumulate_moments(g, lam)
     _check_moments(ctx, mom, 1e-9)
     ctx.close()
 
