@@ -144,9 +144,8 @@ typedef struct {
     int32_t stokes_element;
     /* RT0 velocity mass of the Darcy subdomains: 0 trapezoidal (diagonal,
      * the cell-centred 5-point system), 1 exact integration (Section 6),
-     * solved as the SPD system of the face pressures (FP64; every Darcy
-     * subdomain 2 <= min(nx, ny) <= 128; Method S3, and Method S2 when
-     * min(nx, ny) <= 55)                                                  */
+     * solved as the SPD system of the face pressures (FP64, Methods S3
+     * and S2; every Darcy subdomain 2 <= min(nx, ny) <= 128)              */
     int32_t darcy_mass;
 } sdmm_problem;
 

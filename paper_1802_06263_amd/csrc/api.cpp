@@ -105,8 +105,19 @@ struct BasisView {
 };
 
 // Method S2 state: the batch of the last deterministic solve and its bases.
+// A chunk of exact-mass units too wide for the LDS window, built together
+// through the tiled band LDL^T (entries first .. first + count - 1 of the
+// unit and StokesDev lists; the chunk's doubles of tiles, right-hand sides
+// and inverses).
+struct WideChunk {
+    int first, count, max_nblk, max_w, max_ncol, max_ld, max_np;
+    int64_t tiles, rhs, linv;
+};
+
 struct DetBatch {
     int64_t n = 0, cap = 0;
+    std::vector<WideChunk> wide_chunks;   // the batch's wide units (exact mass)
+    DevBuf d_wide_sdx, d_wide_units;
     std::vector<double> y;               // n x n_term points of the batch
     std::vector<UnitDev> units;
     std::vector<int> chunk_start;        // unit ranges built per launch (scratch reused)
@@ -191,12 +202,9 @@ struct Prob {
     // exact-mass units whose face-pressure band does not fit the LDS window:
     // the first n_wide entries of h_order, built in chunks through the tiled
     // band LDL^T (one StokesDev per unit, offsets into the chunk buffers)
-    struct WideChunk {
-        int first, count, max_nblk, max_w, max_ncol, max_ld, max_np;
-        int64_t tiles, rhs, linv;   // doubles of each chunk buffer
-    };
     int n_wide = 0;
     std::vector<WideChunk> wide_chunks;
+    int64_t wt_cap_tiles = 0, wt_cap_rhs = 0, wt_cap_linv = 0;   // doubles of the chunk buffers
     DevBuf d_wide_sdx, d_wide_units, d_wt_tiles, d_wt_tilesN, d_wt_linv, d_wt_rhs, d_wt_tmp;
     int basis_mode[2] = {0, 0};  // layout the tuner picked per precision (FP64, mixed); 0: not tuned yet
     int queue_rs[2] = {0, 0};    // solve group width of the one-queue layout per precision
@@ -294,6 +302,52 @@ DarcyTables darcy_tables(Prob* c) {
 // face-pressure system (exact mass)
 static int64_t darcy_tscr(const DarcyHost& h) {
     return h.exact ? (int64_t)h.N + 5LL * ((h.Ns + 15) / 16 * 16) : 4LL * h.N + h.n_medge;
+}
+
+// Chunks of wide units (ids into `units`, in order): each chunk within
+// the given doubles of tiles (twice: L and the backward tiles), right-hand
+// sides (twice: solution and scratch) and inverses, or, with no caps (0),
+// within about 4 GB of all of them; one StokesDev per unit with its offsets
+// into the chunk buffers.
+void plan_wide(const Problem& P, const std::vector<UnitDev>& units, const std::vector<int>& ids, int64_t cap_t,
+               int64_t cap_r, int64_t cap_l, std::vector<WideChunk>& chunks, std::vector<StokesDev>& sdx) {
+    chunks.clear();
+    sdx.clear();
+    WideChunk ch{};
+    auto close_chunk = [&]() {
+        if (ch.count > 0) chunks.push_back(ch);
+        ch = WideChunk{};
+        ch.first = (int)sdx.size();
+    };
+    close_chunk();
+    for (int u : ids) {
+        const DarcyHost& h = P.darcy[units[u].d];
+        StokesDev x{};
+        x.nband = h.Ns;
+        x.nblk = (h.Ns + 63) / 64;
+        x.w = (h.bs + 63) / 64;
+        x.ncol = h.R;
+        x.R = h.R;
+        const int64_t nt = (int64_t)x.nblk * (x.w + 1) * 4096, nr = (int64_t)x.nblk * 64 * x.ncol,
+                      nl = (int64_t)x.nblk * 4096;
+        const bool full = cap_t > 0 ? (ch.tiles + nt > cap_t || ch.rhs + nr > cap_r || ch.linv + nl > cap_l)
+                                    : (2 * (ch.tiles + nt) + ch.linv + nl + 2 * (ch.rhs + nr)) * 8 > (int64_t)4 << 30;
+        if (ch.count > 0 && full) close_chunk();
+        x.off_tiles = ch.tiles;
+        x.off_rhs = ch.rhs;
+        x.off_linv = ch.linv;
+        ch.tiles += nt;
+        ch.rhs += nr;
+        ch.linv += nl;
+        ch.count++;
+        ch.max_nblk = std::max(ch.max_nblk, x.nblk);
+        ch.max_w = std::max(ch.max_w, x.w);
+        ch.max_ncol = std::max(ch.max_ncol, x.ncol);
+        ch.max_ld = std::max(ch.max_ld, x.nblk * 64);
+        ch.max_np = std::max(ch.max_np, (h.Ns + 15) / 16 * 16);
+        sdx.push_back(x);
+    }
+    close_chunk();
 }
 
 int setup_device(Prob* ctx) {
@@ -483,49 +537,18 @@ int setup_device(Prob* ctx) {
     {
         // chunks of the wide units, each within about 4 GB of tiles, inverses
         // and right-hand sides
-        ctx->wide_chunks.clear();
         std::vector<StokesDev> sdx;
         std::vector<int> wunits(ctx->h_order.begin(), ctx->h_order.begin() + ctx->n_wide);
-        Prob::WideChunk ch{};
-        auto close_chunk = [&]() {
-            if (ch.count > 0) ctx->wide_chunks.push_back(ch);
-            ch = Prob::WideChunk{};
-            ch.first = (int)sdx.size();
-        };
-        close_chunk();
-        for (int u : wunits) {
-            const DarcyHost& h = P.darcy[ctx->units[u].d];
-            StokesDev x{};
-            x.nband = h.Ns;
-            x.nblk = (h.Ns + 63) / 64;
-            x.w = (h.bs + 63) / 64;
-            x.ncol = h.R;
-            x.R = h.R;
-            const int64_t nt = (int64_t)x.nblk * (x.w + 1) * 4096, nr = (int64_t)x.nblk * 64 * x.ncol,
-                          nl = (int64_t)x.nblk * 4096;
-            if (ch.count > 0 && (2 * (ch.tiles + nt) + ch.linv + nl + 2 * (ch.rhs + nr)) * 8 > (int64_t)4 << 30)
-                close_chunk();
-            x.off_tiles = ch.tiles;
-            x.off_rhs = ch.rhs;
-            x.off_linv = ch.linv;
-            ch.tiles += nt;
-            ch.rhs += nr;
-            ch.linv += nl;
-            ch.count++;
-            ch.max_nblk = std::max(ch.max_nblk, x.nblk);
-            ch.max_w = std::max(ch.max_w, x.w);
-            ch.max_ncol = std::max(ch.max_ncol, x.ncol);
-            ch.max_ld = std::max(ch.max_ld, x.nblk * 64);
-            ch.max_np = std::max(ch.max_np, (h.Ns + 15) / 16 * 16);
-            sdx.push_back(x);
-        }
-        close_chunk();
+        plan_wide(P, ctx->units, wunits, 0, 0, 0, ctx->wide_chunks, sdx);
         int64_t mt = 0, mr = 0, ml = 0;
         for (auto& c : ctx->wide_chunks) {
             mt = std::max(mt, c.tiles);
             mr = std::max(mr, c.rhs);
             ml = std::max(ml, c.linv);
         }
+        ctx->wt_cap_tiles = mt;
+        ctx->wt_cap_rhs = mr;
+        ctx->wt_cap_linv = ml;
         int rc;
         if (ctx->n_wide > 0 && !ctx->host_only) {
             if ((rc = upload(ctx, ctx->d_wide_sdx, sdx)) || (rc = upload(ctx, ctx->d_wide_units, wunits)) ||
@@ -1373,18 +1396,21 @@ constexpr int kMaxRefine = 4;
 // band and loads into zeroed tiles, identity on the padding rows, the band
 // LDL^T block column by block column, the sweep tiles, the solve of all
 // right-hand sides in place, then responses and flux bases.
-int darcy_build_wide(Prob* ctx, hipStream_t st) {
-    DarcyTables t = darcy_tables(ctx);
+// t: the unit tables (Method S3's, or a Method S2 batch's); chunks, d_sdx
+// and d_units as planned by plan_wide; X, S and T the responses, bases and
+// scratch the units' offsets point into.
+int darcy_build_wide(Prob* ctx, const DarcyTables& t, const std::vector<WideChunk>& chunks, const DevBuf& d_sdx,
+                     const DevBuf& d_units, double* X, double* S, double* T, hipStream_t st) {
     double* tiles = ctx->d_wt_tiles.as<double>();
     double* tilesN = ctx->d_wt_tilesN.as<double>();
     double* linv = ctx->d_wt_linv.as<double>();
     double* rhs = ctx->d_wt_rhs.as<double>();
-    for (const auto& c : ctx->wide_chunks) {
-        const StokesDev* sdx = ctx->d_wide_sdx.as<StokesDev>() + c.first;
-        const int* units = ctx->d_wide_units.as<int>() + c.first;
+    for (const auto& c : chunks) {
+        const StokesDev* sdx = d_sdx.as<StokesDev>() + c.first;
+        const int* units = d_units.as<int>() + c.first;
         HIPCHK(launch_fill_zero(tiles, c.tiles, st));
         HIPCHK(launch_fill_zero(rhs, c.rhs, st));
-        HIPCHK(launch_exact_tiles_assemble(t, units, sdx, c.count, c.max_ld, tiles, rhs, ctx->d_T.as<double>(), st));
+        HIPCHK(launch_exact_tiles_assemble(t, units, sdx, c.count, c.max_ld, tiles, rhs, T, st));
         HIPCHK(launch_stokes_pad_identity(sdx, c.count, c.max_nblk, tiles, st));
         for (int J = 0; J < c.max_nblk; ++J) {
             HIPCHK(launch_stokes_ldl_diag(sdx, c.count, J, tiles, linv, st));
@@ -1394,8 +1420,7 @@ int darcy_build_wide(Prob* ctx, hipStream_t st) {
         HIPCHK(launch_stokes_sweep_tiles(sdx, c.count, c.max_nblk, c.max_w, tiles, tilesN, linv, st));
         HIPCHK(launch_stokes_solve(sdx, c.count, c.max_nblk, c.max_w, c.max_ncol, tiles, tilesN, linv, rhs,
                                    ctx->d_wt_tmp.as<double>(), st));
-        HIPCHK(launch_exact_tiles_finish(t, units, sdx, c.count, c.max_np, c.max_ncol, rhs, ctx->d_X.as<double>(),
-                                         ctx->d_S.as<double>(), ctx->d_T.as<double>(), st));
+        HIPCHK(launch_exact_tiles_finish(t, units, sdx, c.count, c.max_np, c.max_ncol, rhs, X, S, T, st));
     }
     return SDMM_OK;
 }
@@ -1409,7 +1434,10 @@ int darcy_build_wide(Prob* ctx, hipStream_t st) {
 int darcy_build(Prob* ctx, int precision, int mode, hipStream_t st, bool wide = true) {
     const int pi = precision == SDMM_PREC_MIXED ? 1 : 0;
     int rc;
-    if (wide && ctx->n_wide > 0 && (rc = darcy_build_wide(ctx, st))) return rc;
+    if (wide && ctx->n_wide > 0 &&
+        (rc = darcy_build_wide(ctx, darcy_tables(ctx), ctx->wide_chunks, ctx->d_wide_sdx, ctx->d_wide_units,
+                               ctx->d_X.as<double>(), ctx->d_S.as<double>(), ctx->d_T.as<double>(), st)))
+        return rc;
     double* max_res = nullptr;
     int* steps = nullptr;
     if (pi == 1) {
@@ -1539,8 +1567,6 @@ int impl_build_flux_basis(Prob* ctx, int method, int precision, void* stream) {
         return fail(ctx, SDMM_EINVAL, "bad method");
     if (ctx->P.in.darcy_mass == 1 && (precision != SDMM_PREC_FP64 || method == SDMM_METHOD_PER_ITERATION))
         return fail(ctx, SDMM_EINVAL, "the exact RT0 mass is built in FP64 for Methods S2 and S3");
-    if (ctx->n_wide > 0 && method != SDMM_METHOD_STOCHASTIC)
-        return fail(ctx, SDMM_EINVAL, "exact-mass subdomains wider than 55 cells on their shorter side need Method S3");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     if (method == SDMM_METHOD_STOCHASTIC && ctx->opt_basis_launch == 0 &&
@@ -2047,17 +2073,18 @@ int det_layout(Prob* ctx, int64_t n, bool resident = false) {
     int64_t L_off = 0, T_off = 0, I_off = 0, L_max = 0, T_max = 0, I_max = 0;
     int in_chunk = 0;
     unit_of_dk.assign(P.darcy.size() * (size_t)n, -1);
+    // order: the units built through the LDS window, chunk by chunk
+    // (chunk_start indexes it); wide: the exact-mass units that go through
+    // the tiled band LDL^T instead
+    std::vector<int> order, wide;
     for (size_t di = 0; di < P.darcy.size(); ++di) {
         const DarcyHost& h = P.darcy[di];
         const int i = h.sub, r = P.subs[i].region;
+        const int64_t Np = (h.Ns + 15) / 16 * 16, bp = (h.bs + 15) / 16 * 16;
+        const bool is_wide = bp > kMaxDarcyBand;
         dabase.push_back(abase[i]);
         dnl.push_back((int)n);
         for (int64_t q = 0; q < n; ++q) {
-            if (in_chunk == 0) {
-                D.chunk_start.push_back((int)D.units.size());
-                L_off = T_off = I_off = 0;
-            }
-            const int64_t Np = (h.Ns + 15) / 16 * 16, bp = (h.bs + 15) / 16 * 16;
             UnitDev u{};
             u.d = (int)di;
             u.k = (int)q;
@@ -2065,24 +2092,39 @@ int det_layout(Prob* ctx, int64_t n, bool resident = false) {
             u.off_xi = q * P.nterm + P.dim_off[r];
             u.off_S = sbase[i] + q * (int64_t)h.R * h.R;
             u.off_X = X_off;
-            u.off_L = L_off;
-            u.off_T = T_off;
-            u.off_I = I_off;
             X_off += Np * h.R;
-            L_off += Np * (bp + 1);
-            T_off += darcy_tscr(h);
-            I_off += Np * 16;
-            L_max = std::max(L_max, L_off);
-            T_max = std::max(T_max, T_off);
-            I_max = std::max(I_max, I_off);
+            if (is_wide) {
+                wide.push_back((int)D.units.size());
+            } else {
+                if (in_chunk == 0) {
+                    D.chunk_start.push_back((int)order.size());
+                    L_off = T_off = I_off = 0;
+                }
+                u.off_L = L_off;
+                u.off_T = T_off;
+                u.off_I = I_off;
+                L_off += Np * (bp + 1);
+                T_off += darcy_tscr(h);
+                I_off += Np * 16;
+                L_max = std::max(L_max, L_off);
+                T_max = std::max(T_max, T_off);
+                I_max = std::max(I_max, I_off);
+                order.push_back((int)D.units.size());
+                if (++in_chunk == kDetChunkUnits && !resident) in_chunk = 0;
+            }
             unit_of_dk[di * (size_t)n + q] = (int)D.units.size();
             D.units.push_back(u);
             V.pair_sub.push_back(i);
             V.pair_k.push_back((int)q);
-            if (++in_chunk == kDetChunkUnits && !resident) in_chunk = 0;
         }
     }
-    D.chunk_start.push_back((int)D.units.size());
+    D.chunk_start.push_back((int)order.size());
+    // the wide units keep K of their cells (the flux readout reads it) after
+    // the window units' scratch
+    for (int u : wide) {
+        D.units[u].off_T = T_max;
+        T_max += P.darcy[D.units[u].d].N;
+    }
     for (size_t si = 0; si < P.stokes.size(); ++si) {
         V.pair_sub.push_back(P.stokes[si].sub);
         V.pair_k.push_back(0);
@@ -2115,8 +2157,11 @@ int det_layout(Prob* ctx, int64_t n, bool resident = false) {
         std::swap(ctx->d_acc.bytes, nb.bytes);
         std::swap(ctx->d_acc.al, nb.al);
     }
-    std::vector<int> order(D.units.size());
-    for (size_t u = 0; u < order.size(); ++u) order[u] = (int)u;
+    std::vector<StokesDev> wsdx;
+    plan_wide(P, D.units, wide, ctx->wt_cap_tiles, ctx->wt_cap_rhs, ctx->wt_cap_linv, D.wide_chunks, wsdx);
+    if (!wide.empty() && ((rc = upload(ctx, D.d_wide_sdx, wsdx)) || (rc = upload(ctx, D.d_wide_units, wide))))
+        return rc;
+    if (order.empty()) order.push_back(0);
     std::vector<int64_t> pos(n);
     for (int64_t q = 0; q < n; ++q) pos[q] = q;
     if ((rc = upload(ctx, D.d_units, D.units)) || (rc = upload(ctx, D.d_order, order)) ||
@@ -2154,10 +2199,15 @@ int det_build(Prob* ctx, const std::vector<double>& y, hipStream_t st) {
     t.units = D.d_units.as<UnitDev>();
     t.order = D.d_order.as<int>();
     t.xi = D.d_xi.as<double>();
-    int max_np = 0;
-    for (auto& h : ctx->P.darcy) max_np = std::max(max_np, (h.Ns + 15) / 16 * 16);
+    int max_np = 0;   // over the units of the LDS window
+    for (auto& h : ctx->P.darcy)
+        if ((h.bs + 15) / 16 * 16 <= kMaxDarcyBand) max_np = std::max(max_np, (h.Ns + 15) / 16 * 16);
     const bool mixed = D.precision == SDMM_PREC_MIXED;
     if (mixed) HIPCHK(hipMemsetAsync(D.d_refine.p, 0, 16, st));
+    if (!D.wide_chunks.empty() &&
+        (rc = darcy_build_wide(ctx, t, D.wide_chunks, D.d_wide_sdx, D.d_wide_units, D.d_X.as<double>(),
+                               D.d_S.as<double>(), D.d_T.as<double>(), st)))
+        return rc;
     for (size_t c = 0; c + 1 < D.chunk_start.size(); ++c) {
         t.unit_base = D.chunk_start[c];
         const int count = D.chunk_start[c + 1] - D.chunk_start[c];

@@ -90,8 +90,10 @@ def test_p2p1_full_size_stokes_blocks():
 #   * at full size (64x64 Darcy subdomains, band 129: the tiled band LDL^T),
 #     sampled units, and on the uneven layout one unit of every mesh shape
 #     (window and tiled units in one build); the CG converges at full size;
-#   * the mixed precision path and Method S1 refuse the exact mass (EINVAL),
-#     and Method S2 refuses units too wide for the LDS window;
+#   * the mixed precision path and Method S1 refuse the exact mass (EINVAL);
+#   * Method S2 at full size (tiled units alone, and tiled with window units
+#     in one batch): lambda on collocation points agrees with Method S3's,
+#     and every sampled unit with the oracle's basis;
 #   * both variants together (P2-P1 Stokes, exact-mass Darcy) on the
 #     two-region layout: every S block, lambda and the moments.
 
@@ -213,7 +215,6 @@ def test_exact_rt0_full_size_units(name):
     print("case: exact RT0 mass at full size,", name, flush=True)
     import torch
     from oracle.collocation import Grid
-    from paper_1802_06263_amd import sdmm
     prob = _with(problem(name), darcy="exact")
     L = Layout(prob)
     grid = Grid(prob["regions"], prob["rule"])
@@ -231,12 +232,30 @@ def test_exact_rt0_full_size_units(name):
         k = int(rng.integers(grid.nlocal[L.subs[i]["region"]]))
         S = _exact_unit_basis(L, grid, i, k)
         assert rel(ctx.get_basis(i, k, S.shape[0]), S) < 1e-11, (i, k, L.subs[i]["n"])
-    if name == "cfg2":
-        idx = list(rng.integers(0, grid.nreal, 64))
-        g, lam, it, rr, st, rc = gpu_solve(ctx, idx, rtol=1e-8)
-        assert (st == 0).all() and (rr <= 1e-8).all()
-        # Method S2 cannot take units too wide for the LDS window
-        with pytest.raises(sdmm.SdmmError) as e:
-            ctx.build_flux_basis("fp64", method="deterministic")
-        assert e.value.code == sdmm.EINVAL
+    idx = [int(v) for v in rng.integers(0, grid.nreal, 64)]
+    g, lam, it, rr, st, rc = gpu_solve(ctx, idx, rtol=1e-8)
+    assert (st == 0).all() and (rr <= 1e-8).all()
+    # Method S2 builds each realization's own units through the same
+    # tiled path: lambda on collocation points agrees with Method S3's,
+    # and the unit of batch position 0 with the oracle's basis
+    few = idx[:8]
+    gi = torch.tensor(few, dtype=torch.int64, device="cuda")
+    lam3 = torch.zeros((len(few), lam.shape[1]), dtype=torch.float64, device="cuda")
+    ctx.solve_interface(gi, lam3, rtol=1e-12)
+    ctx.build_flux_basis("fp64", method="deterministic")
+    lam2 = torch.zeros_like(lam3)
+    st2 = torch.zeros(len(few), dtype=torch.int32, device="cuda")
+    ctx.solve_interface(gi, lam2, rtol=1e-12, status=st2)
+    torch.cuda.synchronize()
+    assert (st2.cpu().numpy() == 0).all()
+    assert rel(lam2.cpu().numpy(), lam3.cpu().numpy()) < 1e-10
+    from oracle.darcy import DarcyLocalExact
+    from oracle.kl import cell_centres, region_field
+    for i in subs:
+        sub = L.subs[i]
+        r = sub["region"]
+        yr = np.asarray(grid.points[few[0]])[grid.dim_off[r]:grid.dim_off[r + 1]]
+        K = np.exp(float(L.regions[r]["mean_logk"]) + yr @ region_field(L.regions[r], cell_centres(sub)))
+        S = DarcyLocalExact(L, i, K).basis()
+        assert rel(ctx.get_basis(i, 0, S.shape[0]), S) < 1e-11, (i, sub["n"])
     ctx.close()
