@@ -216,8 +216,9 @@ struct Prob {
     hipStream_t cap_stream = nullptr;
     hipStream_t stokes_cap = nullptr;        // capture stream of the Stokes graph
     hipStream_t stokes_side = nullptr;       // second stream of the Stokes factor (the rest updates)
+    hipStream_t stokes_fwd = nullptr;        // third: the forward sweep of the first solve, beside the factor
     hipStream_t stokes_run = nullptr;        // the Stokes build runs here, beside the Darcy build
-    hipEvent_t stokes_ev[5] = {};            // panel done, and the rest updates of four columns
+    hipEvent_t stokes_ev[6] = {};            // panel done, the rest updates of four columns, forward sweep done
     hipGraph_t stokes_graph = nullptr;
     hipGraphExec_t stokes_exec = nullptr;
     hipStream_t lane_stream = nullptr;   // the second CG lane
@@ -859,8 +860,9 @@ int stokes_device_work(Prob* ctx, hipStream_t st) {
     // the factor, block column by block column: diag and panel of column J on
     // st; the rest updates of column J on the side stream, which the diag
     // launch of column J + 2 waits for (every tile still receives its updates
-    // in increasing J)
-    hipStream_t side = ctx->stokes_side;
+    // in increasing J); the forward step J of the first solve on a third
+    // stream, as soon as L(., J) is final
+    hipStream_t side = ctx->stokes_side, fwd = ctx->stokes_fwd;
     hipEvent_t* ev = ctx->stokes_ev;
     for (int J = 0; J < ctx->max_nblk; ++J) {
         if (J >= 2) HIPCHK(hipStreamWaitEvent(st, ev[1 + (J - 2) % 4], 0));
@@ -868,18 +870,26 @@ int stokes_device_work(Prob* ctx, hipStream_t st) {
         HIPCHK(launch_stokes_ldl_panel(sd, ns, J, ctx->max_w, tiles, linv, st));
         HIPCHK(hipEventRecord(ev[0], st));
         HIPCHK(hipStreamWaitEvent(side, ev[0], 0));
+        HIPCHK(hipStreamWaitEvent(fwd, ev[0], 0));
         HIPCHK(launch_stokes_ldl_rest(sd, ns, J, ctx->max_w, tiles, side));
         HIPCHK(hipEventRecord(ev[1 + J % 4], side));
+        HIPCHK(launch_stokes_fwd_early(sd, ns, J, ctx->max_w, ctx->max_ncol, tiles, linv, x,
+                                       ctx->d_stmp.as<double>(), fwd));
     }
-    // join the side stream (the last columns' rest updates) before the sweeps
+    HIPCHK(hipEventRecord(ev[5], fwd));
+    // join the side stream (the last columns' rest updates) and the forward
+    // sweep before the sweep tiles overwrite L with M
     for (int J = std::max(0, ctx->max_nblk - 2); J < ctx->max_nblk; ++J)
         HIPCHK(hipStreamWaitEvent(st, ev[1 + J % 4], 0));
+    HIPCHK(hipStreamWaitEvent(st, ev[5], 0));
     HIPCHK(launch_stokes_sweep_tiles(sd, ns, ctx->max_nblk, ctx->max_w, tiles, ctx->d_tilesN.as<double>(), linv, st));
     auto solve = [&](double* b) {
         return launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, ctx->d_tilesN.as<double>(),
                                    linv, b, ctx->d_stmp.as<double>(), st);
     };
-    HIPCHK(solve(x));
+    // the first solve: its forward sweep ran beside the factor
+    HIPCHK(launch_stokes_solve_back(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles,
+                                    ctx->d_tilesN.as<double>(), linv, x, ctx->d_stmp.as<double>(), st));
     // optional FP64 iterative refinement against the assembled matrix
     for (int step = 0; step < ctx->opt_stokes_refine; ++step) {
         HIPCHK(launch_stokes_residual(sd, ns, ctx->max_nblk, ctx->max_ncol, ctx->d_tiles0.as<double>(),
@@ -901,6 +911,10 @@ int build_stokes(Prob* ctx, hipStream_t st) {
         if (hipStreamCreateWithFlags(&ctx->stokes_side, hipStreamNonBlocking) != hipSuccess) {
             ctx->stokes_side = nullptr;
             return fail(ctx, SDMM_EDEVICE, "second stream of the Stokes factor");
+        }
+        if (hipStreamCreateWithFlags(&ctx->stokes_fwd, hipStreamNonBlocking) != hipSuccess) {
+            ctx->stokes_fwd = nullptr;
+            return fail(ctx, SDMM_EDEVICE, "third stream of the Stokes factor");
         }
         for (hipEvent_t& e : ctx->stokes_ev)
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
@@ -1259,6 +1273,7 @@ int impl_destroy(Prob* ctx) {
     if (ctx->stokes_graph) (void)hipGraphDestroy(ctx->stokes_graph);
     if (ctx->stokes_cap) (void)hipStreamDestroy(ctx->stokes_cap);
     if (ctx->stokes_side) (void)hipStreamDestroy(ctx->stokes_side);
+    if (ctx->stokes_fwd) (void)hipStreamDestroy(ctx->stokes_fwd);
     if (ctx->stokes_run) (void)hipStreamDestroy(ctx->stokes_run);
     for (hipEvent_t e : ctx->stokes_ev)
         if (e) (void)hipEventDestroy(e);

@@ -159,6 +159,16 @@ hipError_t launch_stokes_sweep_tiles(const StokesDev* sd, int ns, int max_nblk, 
 // x := A^{-1} x for all R + 1 columns (tmp: work array of the size of x)
 hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol, const double* tiles,
                                const double* tilesN, const double* linv, double* x, double* tmp, hipStream_t stream);
+// the forward step of block column J while the factor runs (any time after
+// the panel launch of J, after the forward step of J - 1): reads L(I, J) and
+// L(J, J)^{-1}, updates x in place and writes L^{-1}-scaled block J to tmp,
+// bit for bit what the forward sweep of launch_stokes_solve does after the
+// factor; launch_stokes_solve_back then finishes the solve.
+hipError_t launch_stokes_fwd_early(const StokesDev* sd, int ns, int J, int max_w, int max_ncol, const double* tiles,
+                                   const double* linv, double* x, double* tmp, hipStream_t stream);
+hipError_t launch_stokes_solve_back(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol,
+                                    const double* tiles, const double* tilesN, const double* linv, double* x,
+                                    double* tmp, hipStream_t stream);
 // FP64 iterative refinement of the band solves: res = b - A x with the
 // assembled band matrix (tiles0; fixed summation order), then x += d after
 // d = A^{-1} res.
