@@ -856,7 +856,8 @@ int stokes_device_work(Prob* ctx, hipStream_t st) {
                                  ctx->d_tr_v.as<double>(), ctx->n_trip, tiles, st));
     HIPCHK(launch_stokes_pad_identity(sd, ns, ctx->max_nblk, tiles, st));
     // the assembled matrix, kept for the refinement residuals
-    HIPCHK(hipMemcpyAsync(ctx->d_tiles0.p, ctx->d_tiles.p, ctx->d_tiles.bytes, hipMemcpyDeviceToDevice, st));
+    if (ctx->opt_stokes_refine > 0)
+        HIPCHK(hipMemcpyAsync(ctx->d_tiles0.p, ctx->d_tiles.p, ctx->d_tiles.bytes, hipMemcpyDeviceToDevice, st));
     // the factor, block column by block column: diag and panel of column J on
     // st; the rest updates of column J on the side stream, which the diag
     // launch of column J + 2 waits for (every tile still receives its updates
@@ -875,14 +876,18 @@ int stokes_device_work(Prob* ctx, hipStream_t st) {
         HIPCHK(hipEventRecord(ev[1 + J % 4], side));
         HIPCHK(launch_stokes_fwd_early(sd, ns, J, ctx->max_w, ctx->max_ncol, tiles, linv, x,
                                        ctx->d_stmp.as<double>(), fwd));
+        HIPCHK(launch_stokes_sweep_row(sd, ns, J, ctx->max_w, tiles, ctx->d_tilesN.as<double>(), linv, fwd));
     }
     HIPCHK(hipEventRecord(ev[5], fwd));
-    // join the side stream (the last columns' rest updates) and the forward
-    // sweep before the sweep tiles overwrite L with M
+    // join the side stream (the last columns' rest updates) and the third
+    // one (forward sweep, backward sweep tiles); the refinement solves need
+    // the forward sweep tiles M in place of L as well
     for (int J = std::max(0, ctx->max_nblk - 2); J < ctx->max_nblk; ++J)
         HIPCHK(hipStreamWaitEvent(st, ev[1 + J % 4], 0));
     HIPCHK(hipStreamWaitEvent(st, ev[5], 0));
-    HIPCHK(launch_stokes_sweep_tiles(sd, ns, ctx->max_nblk, ctx->max_w, tiles, ctx->d_tilesN.as<double>(), linv, st));
+    if (ctx->opt_stokes_refine > 0)
+        HIPCHK(launch_stokes_sweep_tiles(sd, ns, ctx->max_nblk, ctx->max_w, tiles, ctx->d_tilesN.as<double>(), linv,
+                                         st));
     auto solve = [&](double* b) {
         return launch_stokes_solve(sd, ns, ctx->max_nblk, ctx->max_w, ctx->max_ncol, tiles, ctx->d_tilesN.as<double>(),
                                    linv, b, ctx->d_stmp.as<double>(), st);

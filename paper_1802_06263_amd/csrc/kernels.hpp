@@ -166,6 +166,10 @@ hipError_t launch_stokes_solve(const StokesDev* sd, int ns, int max_nblk, int ma
 // factor; launch_stokes_solve_back then finishes the solve.
 hipError_t launch_stokes_fwd_early(const StokesDev* sd, int ns, int J, int max_w, int max_ncol, const double* tiles,
                                    const double* linv, double* x, double* tmp, hipStream_t stream);
+// the backward sweep tiles N(J, .) of block row J (the sweep-tile kernel's
+// bits), once the panel launch of J - 1 and the diag launch of J are done
+hipError_t launch_stokes_sweep_row(const StokesDev* sd, int ns, int J, int max_w, const double* tiles, double* tilesN,
+                                   const double* linv, hipStream_t stream);
 hipError_t launch_stokes_solve_back(const StokesDev* sd, int ns, int max_nblk, int max_w, int max_ncol,
                                     const double* tiles, const double* tilesN, const double* linv, double* x,
                                     double* tmp, hipStream_t stream);

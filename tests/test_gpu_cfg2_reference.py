@@ -6,12 +6,13 @@ which calls only the FP64 oracle.  Compared element by element:
   * every Stokes S_{H,i} (eqs. starSproblem1-2; the two floating subdomains
     included), g_H (eqs. barSproblem1-2) and the range of the FETI matrix G
     (its rows may be any orthonormal basis of the rigid-motion traces): 1e-10
-    relative.  Both sides solve the 64x64 Taylor-Hood saddle systems to a
-    relative residual near 1e-14 (band LDL^T with two FP64 refinement steps;
-    sparse LU with one), so they differ by the forward error the conditioning
-    allows: the 1-norm condition estimate of these systems is about 2.4e7,
-    i.e. a worst case of about 3e-9 relative; the observed differences are
-    near 1e-11;
+    relative, with no FP64 refinement step after the band LDL^T (the
+    default) and with two.  Both sides solve the 64x64 Taylor-Hood saddle
+    systems to a relative residual near 1e-14 (sparse LU with one refinement
+    step on the oracle's side), so they differ by the forward error the
+    conditioning allows: the 1-norm condition estimate of these systems is
+    about 2.4e7, i.e. a worst case of about 3e-9 relative; the observed
+    differences are near 1e-11;
   * lambda of 24 seeded collocation points at CG rtol 1e-12: 1e-9 (FP64),
     1e-8 (mixed) relative (CG stopping error times the interface condition
     number);
@@ -44,9 +45,15 @@ def ref():
     return dict(np.load(REF, allow_pickle=False))
 
 
-def test_stokes_bases_and_interface_data(ref):
-    print("case: cfg2 Stokes bases, g_H and G vs stored oracle values", flush=True)
-    ctx = gpu_ctx(problem("cfg2"), "fp64")
+@pytest.mark.parametrize("refine", [0, 2])
+def test_stokes_bases_and_interface_data(ref, refine):
+    print("case: cfg2 Stokes bases, g_H and G vs stored oracle values, refinement steps", refine, flush=True)
+    import torch  # noqa: F401
+    from paper_1802_06263_amd import sdmm
+    ctx = sdmm.Context(0)
+    ctx.set_problem(problem("cfg2"))
+    ctx.set_option("stokes_refine", refine)
+    ctx.build_flux_basis("fp64")
     errs = {}
     for i in ref["stokes_ids"]:
         S = ref["S_stokes_%d" % i]
