@@ -2181,6 +2181,8 @@ int det_layout(Prob* ctx, int64_t n, bool resident = false) {
     plan_wide(P, D.units, wide, ctx->wt_cap_tiles, ctx->wt_cap_rhs, ctx->wt_cap_linv, D.wide_chunks, wsdx);
     if (!wide.empty() && ((rc = upload(ctx, D.d_wide_sdx, wsdx)) || (rc = upload(ctx, D.d_wide_units, wide))))
         return rc;
+    // every unit wide: no window chunk reads the order list, but its buffer
+    // is still uploaded
     if (order.empty()) order.push_back(0);
     std::vector<int64_t> pos(n);
     for (int64_t q = 0; q < n; ++q) pos[q] = q;
