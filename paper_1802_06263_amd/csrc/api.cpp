@@ -56,6 +56,7 @@ struct Groups {
 };
 
 constexpr int kMaxLanes = 2;   // CG lanes: halves of the slots on their own streams
+constexpr int kXcds = 8;        // XCDs of an MI355X; a launch deals its workgroups to them in turn
 
 // A CG stream (continuous batching): a fixed number of CG slots that
 // realizations of any number of submitted requests occupy as they free up.
@@ -1120,10 +1121,17 @@ int build_groups_host(Prob* ctx, Groups& G, int64_t n, const std::vector<int>* s
         const int64_t g0 = r >= 0 ? goff[r][k] : 0, g1 = r >= 0 ? goff[r][k + 1] : n;
         const int64_t base = r >= 0 ? rbase[r] : rbase[nr];
         G.h_item0.push_back((int)G.h_awork.size());
+        // product items: the row blocks of a chunk of realizations sit kXcds
+        // items apart, so that they run on one XCD and its L2 serves the
+        // chunk's coefficients to every row block
+        for (int64_t cb = g0; cb < g1; cb += 64 * kXcds)
+            for (int row0 = 0; row0 < R; row0 += 64)
+                for (int64_t c0 = cb; c0 < std::min<int64_t>(g1, cb + 64 * kXcds); c0 += 64) {
+                    const int cnt = (int)std::min<int64_t>(64, g1 - c0);
+                    G.h_work.push_back(make_int4(i, k, row0 | (cnt << 16), (int)(base + c0)));
+                }
         for (int64_t c0 = g0; c0 < g1; c0 += 64) {
             const int cnt = (int)std::min<int64_t>(64, g1 - c0);
-            for (int row0 = 0; row0 < R; row0 += 64)
-                G.h_work.push_back(make_int4(i, k, row0 | (cnt << 16), (int)(base + c0)));
             G.h_awork.push_back(make_int4(i, k, cnt, (int)(base + c0)));
             G.h_slot.push_back(slot);
             slot += (int64_t)ext + (int64_t)ext * ext;
