@@ -19,7 +19,8 @@ kernel's algorithmic flops (or bytes) per launch over its average launch
 duration give `roofline`, priced with the per-realization-iteration counts
 of the scope table (2 sum_i R_i^2 flops; 5 M 8 bytes for the whole CG).  A
 second workload block (`cfg3`: uneven subdomains, 54,273 realizations) runs
-one step per precision.  The CPU baseline (the oracle, one thread, bounded
+one step per precision, and a `methods` block times Methods S1 and S2 in FP64
+on samples of the same collocation points beside Method S3's step.  The CPU baseline (the oracle, one thread, bounded
 sample) runs in a child process started before the GPU is touched.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
@@ -62,6 +63,9 @@ def parse():
     ap.add_argument("--cg-lanes", type=int, default=0, choices=[0, 1, 2],
                     help="CG lanes (0: the library default, two lanes whose kernels overlap)")
     ap.add_argument("--no-cfg3", action="store_true", help="skip the uneven-layout block")
+    ap.add_argument("--no-methods", action="store_true", help="skip the Methods S1/S2 block")
+    ap.add_argument("--methods-sample", type=int, default=512,
+                    help="collocation points of the Method S2 sample (S1: at most 32 of them)")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the rtol-1e-11 reference solve and the moment errors (profiling runs)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
@@ -412,6 +416,7 @@ def run_workload(ctx, args, workload, precs, steps, warmup, chunk, torch, np):
                      "ms_moments_expand": ms["moments"],
                      "basis_builds_per_s": sz["n_units"] / (ms["basis_darcy"] * 1e-3),
                      "local_solves_per_s": d["basis_solves_darcy"] / (steps * ms["basis_darcy"] * 1e-3),
+                     "darcy_local_solves_per_step": d["basis_solves_darcy"] / steps,
                      "cg_iterations_mean": d["cg_iterations"] / max(1, d["realizations"]),
                      "not_converged": bad,
                      "refinement_group_steps_per_unit": (ctx.counters()["refinement_steps"] / sz["n_units"]
@@ -494,7 +499,11 @@ def main():
         ctx.close()
         out["cfg3"] = {"config": i3, "fp64": r3.get("fp64"), "mixed": r3.get("mixed"),
                        "kernels": k3[args.precision]}
+    if not args.no_methods and "fp64" in res:
+        out["methods"] = methods_block(args, res["fp64"], info["n_real"], torch, np)
     bad = sum(res[p]["not_converged"] for p in precs)
+    if "methods" in out:
+        bad += sum(out["methods"][m]["not_converged"] for m in ("S1", "S2"))
     if child is not None:
         log("waiting for the CPU baseline")
         so, _ = child.communicate()
@@ -510,6 +519,57 @@ def main():
 
 
 CFG3_CHUNK = 5120   # CG slots on the uneven layout (what the autotuner picks there)
+
+
+def methods_block(args, s3, n_real, torch, np):
+    """Methods S2 (Section 5.3: each realization's own Darcy basis) and S1
+    (Section 5.2: local Darcy solves in every CG iteration) on the same
+    workload in FP64, beside Method S3's whole step: realizations per second
+    of CG + moment accumulation on a sample of collocation points spread over
+    the grid (the Stokes part, which no realization changes, is built before
+    the timed region, as Method S3's build is counted in its step), and the
+    Darcy local solves per realization that eqs. (S1-cost)-(S3-cost) count."""
+    from paper_1802_06263_amd import sdmm
+    from workloads import problem
+    out = {}
+    # S1 solves every Darcy subdomain of every realization in each CG
+    # iteration (about 3,000 of them), a few seconds per 10 realizations on
+    # cfg2, so its sample is kept to 32 (rate 2.6/s at 16, 3.5/s at 128)
+    for name, method, n in (("S2", "deterministic", args.methods_sample),
+                            ("S1", "per_iteration", min(32, args.methods_sample))):
+        ctx = sdmm.Context(0)
+        ctx.set_problem(problem(args.workload))
+        ctx.build_flux_basis("fp64", method=method)
+        M = ctx.sizes()["M"]
+        idx = np.unique(np.linspace(0, n_real - 1, n).astype(np.int64))
+        n = int(idx.size)
+        g = torch.tensor(idx, device="cuda")
+        lam = torch.zeros((n, M), dtype=torch.float64, device="cuda")
+        st = torch.zeros(n, dtype=torch.int32, device="cuda")
+        w = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+        # warm-up: the batch's device layout, two CG iterations
+        ctx.solve_interface(g, lam, rtol=args.rtol, max_iter=2, allow_notconv=True)
+        c0 = ctx.counters()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve_interface(g, lam, rtol=args.rtol, status=st, allow_notconv=True)
+        ctx.reset_moments()
+        ctx.accumulate_moments(g, lam, w)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        c1 = ctx.counters()
+        bad = int((st != 0).sum().item())
+        out[name] = {"realizations": n, "ms": t * 1e3, "realizations_per_s": n / t,
+                     "darcy_local_solves_per_realization": (c1["basis_solves_darcy"] - c0["basis_solves_darcy"]) / n,
+                     "cg_iterations_mean": (c1["cg_iterations"] - c0["cg_iterations"]) / n, "not_converged": bad}
+        log("Method %s: %d realizations in %.0f ms (%.1f realizations/s)" % (name, n, t * 1e3, n / t))
+        ctx.close()
+    out["S3"] = {"realizations": n_real, "ms": s3["ms_per_step"], "realizations_per_s": s3["realizations_per_s"],
+                 "darcy_local_solves_per_realization": s3["darcy_local_solves_per_step"] / n_real,
+                 "cg_iterations_mean": s3["cg_iterations_mean"], "not_converged": s3["not_converged"]}
+    out["note"] = ("FP64; S1 and S2: CG + moments of the sample after the Stokes build; S3: the whole fp64 step "
+                   "(Darcy and Stokes basis builds included)")
+    return out
 
 
 if __name__ == "__main__":
