@@ -23,7 +23,7 @@ one step per precision, and a `methods` block times Methods S1 and S2 in FP64
 on samples of the same collocation points beside Method S3's step.  The CPU baseline (the oracle, one thread, bounded
 sample) runs in a child process started before the GPU is touched.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the library runs on one GPU.
 """
 import argparse
 import hashlib
@@ -442,7 +442,7 @@ def main():
         print(json.dumps(cpu_baseline(problem(args.workload), args.cpu_budget)), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only (the library has no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     # the oracle child starts before this process touches the GPU
     child = None if args.no_cpu_baseline else start_cpu_baseline(args)
