@@ -9,7 +9,10 @@ grid) against the oracle's StokesLocal with the same element:
     on the two-region layout and on the small layout with two floating
     Stokes subdomains (FETI);
   * at full size (4x2 Stokes subdomains of 64x64 elements), the S blocks of
-    one Stokes subdomain on the outer boundary and of one floating one.
+    one Stokes subdomain on the outer boundary and of one floating one;
+  * Methods S2 and S1 with the P2-P1 element on the two-region layout:
+    lambda and the five fields at rtol 1e-12 against the oracle's S2 / S1,
+    1e-9.
 """
 import numpy as np
 import pytest
@@ -79,6 +82,33 @@ def test_p2p1_full_size_stokes_blocks():
         assert rel(ctx.get_basis(i, 0, S.shape[0]), S) < 1e-11, i
     ctx.close()
 
+
+
+@pytest.mark.parametrize("method", ["S2", "S1"])
+def test_p2p1_methods_s1_s2_match_oracle(method):
+    print("case: P2-P1 Stokes element under Method", method, "on the two-region layout", flush=True)
+    import torch
+    from paper_1802_06263_amd import sdmm
+    prob = _with(problem("cfg0"), stokes="p2p1")
+    o = Oracle(prob)
+    idx = [1, 6, 11]
+    w = np.array([0.5, 0.3, 0.2])
+    mom, info = o.run(method, indices=idx, weights=w, rtol=1e-12)
+    ctx = sdmm.Context(0)
+    ctx.set_problem(prob)
+    ctx.build_flux_basis("fp64", method="deterministic" if method == "S2" else "per_iteration")
+    M = ctx.sizes()["M"]
+    gi = torch.tensor(idx, dtype=torch.int64, device="cuda")
+    lam = torch.zeros((len(idx), M), dtype=torch.float64, device="cuda")
+    st = torch.zeros(len(idx), dtype=torch.int32, device="cuda")
+    ctx.solve_interface(gi, lam, rtol=1e-12, status=st)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    assert rel(lam.cpu().numpy(), np.stack([d["lambda"] for d in info])) < 1e-9
+    ctx.reset_moments()
+    ctx.accumulate_moments(gi, lam, torch.tensor(w, device="cuda"))
+    _check_moments(ctx, mom, 1e-9)
+    ctx.close()
 
 # ---- exactly integrated RT0 mass (hybridized face-pressure system) ----------
 #   * every Darcy S_{H,i}^{(k)} (FP64 band Cholesky of the face-pressure
