@@ -113,7 +113,9 @@ def test_p2p1_methods_s1_s2_match_oracle(method):
 # ---- exactly integrated RT0 mass (hybridized face-pressure system) ----------
 #   * every Darcy S_{H,i}^{(k)} (FP64 band Cholesky of the face-pressure
 #     system, no refinement): 1e-11 relative to max|S|;
-#   * lambda and the five fields at rtol 1e-12: 1e-9, with Methods S3 and S2;
+#   * lambda and the five fields at rtol 1e-12: 1e-9, with Methods S3 and S2
+#     (the two-region and the small FETI layouts), and lambda at off-grid
+#     points under Method S2;
 #   * on the 4x2 Stokes over 8x4 Darcy layout with 48x48 Darcy meshes
 #     (the largest that fits the factor's LDS window: band 2 min(nx, ny) + 1),
 #     sampled units of three Darcy subdomains;
@@ -169,14 +171,15 @@ def test_both_variants_together_match_oracle():
     ctx.close()
 
 
-def test_exact_rt0_method_s2_matches_oracle():
-    print("case: exact RT0 mass, Method S2 on the two-region layout", flush=True)
+@pytest.mark.parametrize("name", ["cfg0", "small"])
+def test_exact_rt0_method_s2_matches_oracle(name):
+    print("case: exact RT0 mass, Method S2,", name, flush=True)
     import torch
     from paper_1802_06263_amd import sdmm
-    prob = _with(problem("cfg0"), darcy="exact")
+    prob = _with(_small_feti() if name == "small" else problem("cfg0"), darcy="exact")
     o = Oracle(prob)
-    idx = [1, 6, 11]
-    w = np.array([0.5, 0.3, 0.2])
+    idx = [0, 17, 4000, 6560] if name == "small" else [1, 6, 11]
+    w = np.array([0.1, 0.2, 0.3, 0.4]) if name == "small" else np.array([0.5, 0.3, 0.2])
     mom, info = o.run("S2", indices=idx, weights=w, rtol=1e-12)
     ctx = sdmm.Context(0)
     ctx.set_problem(prob)
@@ -194,6 +197,30 @@ def test_exact_rt0_method_s2_matches_oracle():
     _check_moments(ctx, mom, 1e-9)
     ctx.close()
 
+
+
+def test_exact_rt0_offgrid_points_match_oracle():
+    print("case: exact RT0 mass, Method S2 at off-grid points of the two-region layout", flush=True)
+    import torch
+    from paper_1802_06263_amd import sdmm
+    prob = _with(problem("cfg0"), darcy="exact")
+    o = Oracle(prob)
+    rng = np.random.default_rng(41)
+    Y = rng.standard_normal((3, o.grid.dim_off[-1]))
+    ctx = sdmm.Context(0)
+    ctx.set_problem(prob)
+    ctx.build_flux_basis("fp64", method="deterministic")
+    M = ctx.sizes()["M"]
+    y = torch.tensor(Y, dtype=torch.float64, device="cuda")
+    lam = torch.zeros((Y.shape[0], M), dtype=torch.float64, device="cuda")
+    st = torch.zeros(Y.shape[0], dtype=torch.int32, device="cuda")
+    ctx.solve_interface(None, lam, rtol=1e-12, status=st, y=y)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    for q in range(Y.shape[0]):
+        fields, it, rr, ok = o.point_S2(Y[q], rtol=1e-12)
+        assert rel(lam[q].cpu().numpy(), fields["lambda"]) < 1e-9, q
+    ctx.close()
 
 def test_exact_rt0_sampled_units_48x48():
     print("case: exact RT0 mass, sampled units of the 8x4 Darcy layout at 48x48", flush=True)
