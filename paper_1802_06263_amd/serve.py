@@ -4,7 +4,12 @@ A request names a problem and a batch of global collocation indices (the
 points of the collocation rule of Section 4); the answer is the mortar
 solution lambda of every realization (Section 5.1, CG with S_H applied from
 the stochastic basis of Section 5.4), and the realizations are added to the
-problem's running moments (Section 2).
+problem's running moments (Section 2).  An engine built with --offgrid takes
+points y of the stochastic space instead (any draw, e.g. iid N(0, 1)): it
+solves each batch of queued points with the deterministic basis of every
+realization (Method S2, Section 5.3), so its batching is per batch of
+requests, not per CG iteration, and it answers lambda without adding to the
+moments (off-grid draws carry no collocation weights).
 
 Design:
   * one Engine per problem: a library context whose flux basis stays
@@ -41,13 +46,23 @@ import numpy as np
 
 
 class Request:
-    __slots__ = ("rid", "problem", "gidx", "t_arrival", "t_done", "lam", "iters", "status", "rejected", "event",
-                 "footprint")
+    __slots__ = ("rid", "problem", "gidx", "points", "n", "t_arrival", "t_done", "lam", "iters", "status",
+                 "rejected", "event", "footprint")
 
     def __init__(self, rid, problem, gidx, t_arrival):
+        """gidx: global collocation indices (1-D), or points y of the
+        stochastic space (n x n_term floats) for an off-grid engine."""
         self.rid = rid
         self.problem = problem
-        self.gidx = np.asarray(gidx, dtype=np.int64)
+        g = np.asarray(gidx)
+        if g.ndim == 2:
+            self.points = np.ascontiguousarray(g, dtype=np.float64)
+            self.gidx = np.zeros(0, dtype=np.int64)
+            self.n = g.shape[0]
+        else:
+            self.points = None
+            self.gidx = g.astype(np.int64)
+            self.n = self.gidx.size
         self.t_arrival = t_arrival
         self.t_done = None
         self.lam = None
@@ -90,6 +105,7 @@ class Engine:
         self.stop = False
         self.server = None
         self.runs = []            # per CG check group: (requests in flight, realizations in flight, seconds)
+        self.error = None         # the library error that stopped the engine, if any
         self.thread = threading.Thread(target=self._run, name="engine-" + name, daemon=True)
 
     def start(self):
@@ -97,12 +113,12 @@ class Engine:
 
     def submit(self, req):
         with self.cv:
-            if self.pending + req.gidx.size > self.max_pending:
+            if self.error is not None or self.pending + req.n > self.max_pending:
                 req.rejected = True
                 req.event.set()
                 return False
             self.queue.append(req)
-            self.pending += req.gidx.size
+            self.pending += req.n
             self.cv.notify()
         return True
 
@@ -117,13 +133,13 @@ class Engine:
         """Queued requests into the CG stream while their bytes fit (oldest first)."""
         while self.queue:
             r = self.queue[0]
-            fp = self.backend.request_bytes(r.gidx.size)
+            fp = self.backend.request_bytes(r.n)
             if self.server is not None and not self.server.reserve(fp):
                 break
             self.queue.popleft()
-            self.pending -= r.gidx.size
+            self.pending -= r.n
             r.footprint = fp
-            self.inflight[self.backend.submit(r.gidx)] = r
+            self.inflight[self.backend.submit(r.gidx if r.points is None else r.points)] = r
 
     def _run(self):
         while True:
@@ -137,18 +153,33 @@ class Engine:
                     self.cv.wait(0.001)   # every queued request waits for device memory
                     continue
             nreq = len(self.inflight)
-            nreal = sum(r.gidx.size for r in self.inflight.values())
+            nreal = sum(r.n for r in self.inflight.values())
             t0 = time.perf_counter()
-            done = self.backend.run(1)
-            t1 = time.perf_counter()
-            self.runs.append((nreq, nreal, t1 - t0))
-            for t in done:
-                r = self.inflight.pop(t)
-                r.lam, r.iters, r.status = self.backend.result(t, self.accumulate)
-                r.t_done = time.perf_counter()
-                if self.server is not None:
-                    self.server.release(r.footprint)
-                r.event.set()
+            try:
+                done = self.backend.run(1)
+                t1 = time.perf_counter()
+                self.runs.append((nreq, nreal, t1 - t0))
+                for t in done:
+                    r = self.inflight.pop(t)
+                    r.lam, r.iters, r.status = self.backend.result(t, self.accumulate)
+                    r.t_done = time.perf_counter()
+                    if self.server is not None:
+                        self.server.release(r.footprint)
+                    r.event.set()
+            except Exception as exc:   # a library error ends this engine: every request it holds is refused
+                self.error = exc
+                with self.cv:
+                    held = list(self.inflight.values()) + list(self.queue)
+                    self.inflight.clear()
+                    self.queue.clear()
+                    self.pending = 0
+                    self.stop = True
+                for r in held:
+                    if r.footprint and self.server is not None:
+                        self.server.release(r.footprint)
+                    r.rejected = True
+                    r.event.set()
+                return
 
 
 class GpuBackend:
@@ -226,6 +257,96 @@ class GpuBackend:
         self.ctx.close()
 
 
+class PointBackend:
+    """Library context of one problem under Method S2: every batch of queued
+    points y is solved at once, each realization with its own Darcy basis
+    built from its KL field (sdmm_solve_interface with y).  It answers
+    lambda only: the moments of off-grid draws need weights that a stream
+    does not fix (1/N for N iid draws), so the caller accumulates them."""
+
+    def __init__(self, prob, precision, rtol):
+        import torch
+        from . import sdmm
+        self.torch = torch
+        self.ctx = sdmm.Context(0)
+        self.ctx.set_problem(prob)
+        # each batch lays out its units with blocking host-to-device copies on
+        # the null stream, which HIP refuses while another thread captures a
+        # graph: the CG iterations of this engine run without capture, so an
+        # off-grid server, whose engines are all of this kind, captures none
+        self.ctx.set_option("cg_graph", 0)
+        self.sizes = self.ctx.sizes()
+        self.stream = torch.cuda.Stream()
+        self.ctx.build_flux_basis(precision, method="deterministic", stream=self.stream)
+        self.stream.synchronize()
+        self.M = self.sizes["M"]
+        self.rtol = rtol
+        self.slots = 0
+        # device bytes per realization of a batch: lambda and outputs, and its
+        # own Darcy bases and fine responses (the stochastic basis per unit
+        # times the Darcy subdomains)
+        self.per_real = request_bytes(self.M, 1) + (self.sizes["basis_bytes"] + self.sizes["response_bytes"]) * \
+            self.sizes["n_darcy"] // max(1, self.sizes["n_units"])
+        self.pending = []
+        self.out = {}
+        self.next = 0
+
+    def request_bytes(self, n):
+        return n * self.per_real
+
+    def submit(self, points):
+        t = self.next
+        self.next += 1
+        self.pending.append((t, np.asarray(points, dtype=np.float64)))
+        return t
+
+    def run(self, groups):
+        if not self.pending:
+            return []
+        torch = self.torch
+        batch, self.pending = self.pending, []
+        Y = np.concatenate([y for _, y in batch])
+        n = Y.shape[0]
+        with torch.cuda.stream(self.stream):
+            y = torch.from_numpy(Y).to("cuda")
+            lam = torch.empty((n, self.M), dtype=torch.float64, device="cuda")
+            it = torch.empty(n, dtype=torch.int32, device="cuda")
+            st = torch.empty(n, dtype=torch.int32, device="cuda")
+            self.ctx.solve_interface(None, lam, rtol=self.rtol, iters=it, status=st, stream=self.stream, y=y,
+                                     allow_notconv=True)
+            out = lam.to("cpu").numpy(), it.to("cpu").numpy(), st.to("cpu").numpy()
+        self.stream.synchronize()
+        q = 0
+        for t, yb in batch:
+            k = yb.shape[0]
+            self.out[t] = tuple(a[q:q + k] for a in out)
+            q += k
+        return [t for t, _ in batch]
+
+    def result(self, ticket, accumulate):
+        return self.out.pop(ticket)
+
+    def solve_alone(self, points, rtol):
+        """The same points as a batch of their own (for checks)."""
+        torch = self.torch
+        Y = np.ascontiguousarray(points, dtype=np.float64)
+        n = Y.shape[0]
+        with torch.cuda.stream(self.stream):
+            y = torch.from_numpy(Y).to("cuda")
+            lam = torch.empty((n, self.M), dtype=torch.float64, device="cuda")
+            it = torch.empty(n, dtype=torch.int32, device="cuda")
+            st = torch.empty(n, dtype=torch.int32, device="cuda")
+            self.ctx.solve_interface(None, lam, rtol=rtol, iters=it, status=st, stream=self.stream, y=y,
+                                     allow_notconv=True)
+            out = lam.to("cpu").numpy(), it.to("cpu").numpy(), st.to("cpu").numpy()
+        self.stream.synchronize()
+        return out
+
+    def close(self):
+        self.stream.synchronize()
+        self.ctx.close()
+
+
 class Server:
     """Engines for several problems plus admission by HBM footprint: every
     engine's resident bytes when it is added, every request's bytes while it
@@ -292,7 +413,7 @@ def replay(server, stream, speed=1.0, progress=None):
 def summarize(reqs, wall_s):
     done = [r for r in reqs if not r.rejected]
     lat = np.array([r.t_done - r.t_arrival for r in done]) if done else np.zeros(1)
-    nreal = int(sum(r.gidx.size for r in done))
+    nreal = int(sum(r.n for r in done))
     out = {"requests": len(reqs), "answered": len(done), "rejected": len(reqs) - len(done),
            "realizations": nreal, "wall_s": wall_s, "realizations_per_s": nreal / wall_s,
            "latency_p50_ms": float(np.percentile(lat, 50) * 1e3), "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -305,11 +426,14 @@ def summarize(reqs, wall_s):
     return out
 
 
-def build_server(problems, precision, budget_gb):
+def build_server(problems, precision, budget_gb, offgrid=False, rtol=1e-8):
     from workloads import problem
     server = Server(int(budget_gb * (1 << 30)))
     for name in problems:
-        e = Engine(name, problem(name), precision=precision)
+        if offgrid:
+            e = Engine(name, problem(name), backend=PointBackend(problem(name), precision, rtol))
+        else:
+            e = Engine(name, problem(name), precision=precision, rtol=rtol)
         server.add(e, footprint_bytes(e.backend.sizes, e.backend.slots))
     return server
 
@@ -322,11 +446,14 @@ def main(argv=None):
     ap.add_argument("--rates", default="200", help="arrival rates (requests/s), comma separated")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--offgrid", action="store_true",
+                    help="requests of iid N(0, 1) points of the stochastic space (Method S2 engines)")
     args = ap.parse_args(argv)
     from workloads import serving_stream
     problems = tuple(args.problems.split(","))
-    server = build_server(problems, args.precision, args.budget_gb)
+    server = build_server(problems, args.precision, args.budget_gb, offgrid=args.offgrid)
     sizes = {p: server.engines[p].backend.sizes["n_real"] for p in problems}
+    nterm = {p: server.engines[p].backend.sizes["n_term"] for p in problems}
 
     def log(msg):
         print("serve: " + msg, file=sys.stderr, flush=True)
@@ -334,12 +461,17 @@ def main(argv=None):
     for rate in (float(x) for x in args.rates.split(",")):
         stream = serving_stream(seed=args.seed, duration_s=args.duration, rate_hz=rate, grid_sizes=sizes,
                                 problems=problems)
+        if args.offgrid:
+            # the same arrivals and request sizes, each realization an iid
+            # N(0, 1) point of the problem's stochastic space
+            rng = np.random.default_rng(args.seed + 1)
+            stream = [(t, p, rng.standard_normal((g.size, nterm[p]))) for t, p, g in stream]
         log("rate %.0f/s: %d requests" % (rate, len(stream)))
         t0 = time.perf_counter()
         reqs = replay(server, stream, progress=log)
         out = summarize(reqs, time.perf_counter() - t0)
-        out.update({"rate_hz": rate, "offered_realizations_per_s": sum(g.size for _, _, g in stream) / args.duration,
-                    "precision": args.precision, "duration_s": args.duration,
+        out.update({"rate_hz": rate, "offered_realizations_per_s": sum(len(g) for _, _, g in stream) / args.duration,
+                    "precision": args.precision, "duration_s": args.duration, "offgrid": args.offgrid,
                     "cg_slots": {p: server.engines[p].backend.slots for p in problems},
                     "requests_in_flight_per_check": {
                         p: float(np.mean([x[0] for x in server.engines[p].runs] or [0])) for p in problems}})

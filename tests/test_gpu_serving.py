@@ -60,3 +60,30 @@ def test_full_layouts_in_the_mix_match_alone(precision):
         lam, it, st = server.engines[r.problem].backend.solve_alone(r.gidx, 1e-8)
         assert np.array_equal(lam, r.lam) and np.array_equal(it, r.iters) and np.array_equal(st, r.status)
     server.close()
+
+
+def test_offgrid_point_requests_match_alone():
+    """Requests of iid N(0, 1) points through a Method S2 engine: queued
+    requests share a batch, and every answer is bit for bit the answer of
+    its points solved as a batch of their own."""
+    print("case: serving off-grid points through a Method S2 engine (two-region layout)", flush=True)
+    from paper_1802_06263_amd.serve import Engine, PointBackend, Request, Server
+    prob = problem("cfg0")
+    be = PointBackend(prob, "fp64", 1e-10)
+    s = Server(1 << 34)
+    e = Engine("cfg0", prob, backend=be)
+    s.add(e, 0)
+    rng = np.random.default_rng(5)
+    nt = be.sizes["n_term"]
+    reqs = [Request(q, "cfg0", rng.standard_normal((q + 2, nt)), 0.0) for q in range(4)]
+    for r in reqs:
+        s.submit(r)
+    for r in reqs:
+        assert r.event.wait(120)
+    runs = list(e.runs)
+    alone = [be.solve_alone(r.points, 1e-10) for r in reqs]
+    s.close()
+    assert max(x[0] for x in runs) >= 2, runs
+    for r, (lam, it, st) in zip(reqs, alone):
+        assert (r.status == 0).all() and (st == 0).all()
+        assert np.array_equal(r.lam, lam), r.rid

@@ -168,3 +168,86 @@ def test_replay_and_latency_summary():
     assert 0 < out["latency_p50_ms"] <= out["latency_p99_ms"]
     assert set(out["per_problem"]) == {"a", "b"}
     assert all(r.t_done >= r.t_arrival for r in reqs)
+
+
+class FakePointBackend:
+    """Stands in for the Method S2 backend: run() answers every queued batch
+    of points at once; lambda[l] = sum(y_l) + arange(M)."""
+
+    M = 4
+
+    def __init__(self):
+        self.pending, self.out, self.next, self.runs = [], {}, 0, []
+        self.gate = threading.Event()
+        self.gate.set()
+
+    def request_bytes(self, n):
+        return request_bytes(self.M, n)
+
+    def submit(self, points):
+        assert np.asarray(points).ndim == 2
+        self.next += 1
+        self.pending.append((self.next, np.asarray(points)))
+        return self.next
+
+    def run(self, groups):
+        self.gate.wait(5)
+        batch, self.pending = self.pending, []
+        self.runs.append(len(batch))
+        for t, y in batch:
+            lam = y.sum(axis=1)[:, None] + np.arange(self.M)[None, :]
+            self.out[t] = (lam, np.ones(len(y), np.int32), np.zeros(len(y), np.int32))
+        return [t for t, _ in batch]
+
+    def result(self, ticket, accumulate):
+        return self.out.pop(ticket)
+
+    def close(self):
+        pass
+
+
+def test_point_requests_are_batched_and_answered():
+    """Requests of points y (n x n_term) count n realizations, reach the
+    backend as points, and requests queued while a batch runs share the
+    next batch."""
+    be = FakePointBackend()
+    be.gate.clear()
+    s = Server(hbm_budget_bytes=1 << 30)
+    e = Engine("p", None, backend=be)
+    s.add(e, 0)
+    rng = np.random.default_rng(3)
+    first = Request(0, "p", rng.standard_normal((2, 5)), 0.0)
+    assert first.n == 2 and first.points.shape == (2, 5) and first.gidx.size == 0
+    e.submit(first)
+    time.sleep(0.05)                 # the first batch is running (held at the gate)
+    later = [Request(q, "p", rng.standard_normal((q + 1, 5)), 0.0) for q in range(1, 4)]
+    for r in later:
+        e.submit(r)
+    be.gate.set()
+    for r in [first] + later:
+        assert r.event.wait(5)
+        assert np.allclose(r.lam[:, 0], r.points.sum(axis=1))
+        assert r.lam.shape == (r.n, be.M)
+    s.close()
+    assert be.runs[0] == 1 and max(be.runs) == 3   # the three later requests in one batch
+    out = summarize([first] + later, 1.0)
+    assert out["realizations"] == 2 + 2 + 3 + 4
+
+
+def test_a_library_error_refuses_the_engines_requests():
+    """An error from the backend stops its engine: the requests it holds and
+    later ones are refused (their events set), nothing waits forever."""
+    class Failing(FakePointBackend):
+        def run(self, groups):
+            raise RuntimeError("device error")
+    be = Failing()
+    s = Server(hbm_budget_bytes=1 << 30)
+    e = Engine("p", None, backend=be)
+    s.add(e, 0)
+    a = Request(0, "p", np.zeros((2, 3)), 0.0)
+    e.submit(a)
+    assert a.event.wait(5) and a.rejected
+    b = Request(1, "p", np.zeros((1, 3)), 0.0)
+    assert not e.submit(b) and b.rejected
+    assert isinstance(e.error, RuntimeError) and s.used == 0
+    s.close()
