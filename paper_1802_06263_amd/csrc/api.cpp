@@ -276,6 +276,21 @@ int upload(Prob* ctx, DevBuf& b, const std::vector<T>& v) {
     return SDMM_OK;
 }
 
+// The same on stream st (then waited for): ordered after the work queued on
+// st, and no operation on the null stream, which HIP refuses while another
+// thread captures a graph (a Method S2 batch laid out beside a serving
+// engine's captured CG).
+template <class T>
+int upload_on(Prob* ctx, DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+    int rc = alloc(ctx, b, v.size() * sizeof(T));
+    if (rc) return rc;
+    if (!v.empty()) {
+        HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return SDMM_OK;
+}
+
 DarcyTables darcy_tables(Prob* c) {
     DarcyTables t;
     t.dar = c->d_dar.as<DarcyDev>();
@@ -2073,7 +2088,7 @@ int det_points(Prob* ctx, int64_t n, const int64_t* gidx, const double* y, hipSt
 // realizations.  resident: every unit keeps its own factor scratch (Method
 // S1 solves with the factors in every CG iteration); otherwise the scratch
 // is reused chunk by chunk.
-int det_layout(Prob* ctx, int64_t n, bool resident = false) {
+int det_layout(Prob* ctx, int64_t n, hipStream_t st, bool resident = false) {
     Problem& P = ctx->P;
     DetBatch& D = ctx->det;
     BasisView& V = D.view;
@@ -2179,32 +2194,34 @@ int det_layout(Prob* ctx, int64_t n, bool resident = false) {
     if (ctx->d_acc.bytes < (size_t)A_off * 8) {
         DevBuf nb;
         if ((rc = alloc(ctx, nb, A_off * 8))) return rc;
-        HIPCHK(hipMemset(nb.p, 0, nb.bytes));
-        HIPCHK(hipMemcpy(nb.p, ctx->d_acc.p, ctx->d_acc.bytes, hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemsetAsync(nb.p, 0, nb.bytes, st));
+        HIPCHK(hipMemcpyAsync(nb.p, ctx->d_acc.p, ctx->d_acc.bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
         std::swap(ctx->d_acc.p, nb.p);
         std::swap(ctx->d_acc.bytes, nb.bytes);
         std::swap(ctx->d_acc.al, nb.al);
     }
     std::vector<StokesDev> wsdx;
     plan_wide(P, D.units, wide, ctx->wt_cap_tiles, ctx->wt_cap_rhs, ctx->wt_cap_linv, D.wide_chunks, wsdx);
-    if (!wide.empty() && ((rc = upload(ctx, D.d_wide_sdx, wsdx)) || (rc = upload(ctx, D.d_wide_units, wide))))
+    if (!wide.empty() && ((rc = upload_on(ctx, D.d_wide_sdx, wsdx, st)) || (rc = upload_on(ctx, D.d_wide_units, wide, st))))
         return rc;
     // every unit wide: no window chunk reads the order list, but its buffer
     // is still uploaded
     if (order.empty()) order.push_back(0);
     std::vector<int64_t> pos(n);
     for (int64_t q = 0; q < n; ++q) pos[q] = q;
-    if ((rc = upload(ctx, D.d_units, D.units)) || (rc = upload(ctx, D.d_order, order)) ||
-        (rc = upload(ctx, D.d_pos, pos)) || (rc = upload(ctx, D.d_unit_of_dk, unit_of_dk)) ||
-        (rc = upload(ctx, D.d_dnlocal, dnl)) || (rc = upload(ctx, D.d_dAbase, dabase)) ||
-        (rc = upload(ctx, V.d_pair_sub, V.pair_sub)) || (rc = upload(ctx, V.d_pair_k, V.pair_k)) ||
-        (rc = upload(ctx, V.d_sub_Sbase, sbase)) || (rc = upload(ctx, V.d_sub_Abase, abase)))
+    if ((rc = upload_on(ctx, D.d_units, D.units, st)) || (rc = upload_on(ctx, D.d_order, order, st)) ||
+        (rc = upload_on(ctx, D.d_pos, pos, st)) || (rc = upload_on(ctx, D.d_unit_of_dk, unit_of_dk, st)) ||
+        (rc = upload_on(ctx, D.d_dnlocal, dnl, st)) || (rc = upload_on(ctx, D.d_dAbase, dabase, st)) ||
+        (rc = upload_on(ctx, V.d_pair_sub, V.pair_sub, st)) || (rc = upload_on(ctx, V.d_pair_k, V.pair_k, st)) ||
+        (rc = upload_on(ctx, V.d_sub_Sbase, sbase, st)) || (rc = upload_on(ctx, V.d_sub_Abase, abase, st)))
         return rc;
     const int64_t nd = 2 * (ctx->field_size[1] + ctx->field_size[2]);
     if ((rc = grow(D.d_tmp, std::max<int64_t>(nd, 1) * 8))) return rc;
     if (!D.d_sum.p) {
         if ((rc = alloc(ctx, D.d_sum, std::max<int64_t>(nd, 1) * 8))) return rc;
-        HIPCHK(hipMemset(D.d_sum.p, 0, D.d_sum.bytes));
+        HIPCHK(hipMemsetAsync(D.d_sum.p, 0, D.d_sum.bytes, st));
+        HIPCHK(hipStreamSynchronize(st));
     }
     V.S = D.d_S.as<double>();
     D.S_total = S_off;
@@ -2221,7 +2238,7 @@ int det_build(Prob* ctx, const std::vector<double>& y, hipStream_t st) {
     DetBatch& D = ctx->det;
     int rc;
     if (!y.empty()) {
-        if ((rc = upload(ctx, D.d_xi, y))) return rc;
+        if ((rc = upload_on(ctx, D.d_xi, y, st))) return rc;
     } else if ((rc = alloc(ctx, D.d_xi, 8))) {
         return rc;
     }
@@ -2255,7 +2272,8 @@ int det_build(Prob* ctx, const std::vector<double>& y, hipStream_t st) {
     }
     const Problem& P = ctx->P;
     std::vector<int64_t> sbase(P.subs.size());
-    HIPCHK(hipMemcpy(sbase.data(), D.view.d_sub_Sbase.p, sbase.size() * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(sbase.data(), D.view.d_sub_Sbase.p, sbase.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     for (auto& sh : P.stokes) {
         const int i = sh.sub, R = ctx->sub_R[i];
         HIPCHK(hipMemcpyAsync(D.d_S.as<double>() + sbase[i], ctx->d_S.as<double>() + ctx->sub_Sbase[i],
@@ -2295,7 +2313,7 @@ int s1_prepare(Prob* ctx, int64_t n, const std::vector<double>& pts, hipStream_t
         if (h.R > kS1MaxR || h.n_medge > kS1MaxMedge)
             return fail(ctx, SDMM_EINVAL, "Method S1 handles at most 256 mortar DOFs and 512 mortar edges per Darcy subdomain");
     D.precision = SDMM_PREC_FP64;
-    if ((rc = det_layout(ctx, n, true))) return rc;
+    if ((rc = det_layout(ctx, n, st, true))) return rc;
     if (!pts.empty()) {
         if ((rc = upload(ctx, D.d_xi, pts))) return rc;
     } else if ((rc = alloc(ctx, D.d_xi, 8))) {
@@ -2498,7 +2516,7 @@ int impl_solve_interface(Prob* ctx, int64_t n, const int64_t* gidx, const double
         // positions stand in for the global indices)
         std::vector<double> pts;
         ctx->det.valid = false;
-        if ((rc = det_points(ctx, n, gidx, y, st, pts)) || (rc = det_layout(ctx, n))) return rc;
+        if ((rc = det_points(ctx, n, gidx, y, st, pts)) || (rc = det_layout(ctx, n, st))) return rc;
         rc = det_build(ctx, pts, st);
         if (rc && rc != SDMM_ENOTCONV) return rc;
         ctx->det.y = pts;

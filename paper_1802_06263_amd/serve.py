@@ -270,11 +270,6 @@ class PointBackend:
         self.torch = torch
         self.ctx = sdmm.Context(0)
         self.ctx.set_problem(prob)
-        # each batch lays out its units with blocking host-to-device copies on
-        # the null stream, which HIP refuses while another thread captures a
-        # graph: the CG iterations of this engine run without capture, so an
-        # off-grid server, whose engines are all of this kind, captures none
-        self.ctx.set_option("cg_graph", 0)
         self.sizes = self.ctx.sizes()
         self.stream = torch.cuda.Stream()
         self.ctx.build_flux_basis(precision, method="deterministic", stream=self.stream)
