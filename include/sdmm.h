@@ -31,12 +31,13 @@
  *     get_* calls synchronise the context's stream themselves.
  *   - A context is used by one host thread at a time.  Several contexts
  *     may run side by side on several threads (one per served problem):
- *     the solves, the builds and sdmm_accumulate_moments keep their copies
- *     on the context's streams, but set-up (sdmm_set_problem) and the
- *     calls that return data to the host (get_*, sdmm_reset_moments) make
- *     blocking copies on the null stream, which HIP refuses with EDEVICE
- *     while another thread captures a graph (a solve's CG iterations): make
- *     those calls while no other context is solving.
+ *     the solves (Method S2 batches included) and sdmm_accumulate_moments
+ *     keep their copies on the context's streams, but set-up
+ *     (sdmm_set_problem), sdmm_build_flux_basis and the calls that return
+ *     data to the host (get_*, sdmm_reset_moments) make blocking copies on
+ *     the null stream, which HIP refuses with EDEVICE while another thread
+ *     captures a graph (a solve's CG iterations): make those calls while no
+ *     other context is solving.
  */
 #ifndef SDMM_H
 #define SDMM_H
